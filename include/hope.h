@@ -1,0 +1,163 @@
+/*
+ * hope.h -- C ABI of the MI355X (gfx950) implementation of the HOPE
+ * shallow-water right-hand side on the gnomonic equiangular cubed sphere
+ * (Zhou, "HOPE: an automatically differentiable high-order non-oscillatory
+ * finite-volume shallow-water dynamic core", arXiv 2411.19185).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * State.  The prognostic variables are the cell averages, over the angular
+ * coordinates dx dy, of q = (sqrtG phi, sqrtG phi u, sqrtG phi v) (eqs
+ * (2.15)-(2.16)), phi = g h the geopotential, (u, v) contravariant winds in
+ * rad/s, sqrtG of (2.8) including the radius squared.
+ *
+ * Panels are numbered 0..5 (the paper's 1..6, Figure 2.1).  Panel p maps the
+ * point (X, Y) = (tan x, tan y), x, y in [-pi/4, pi/4], to the direction
+ *   0: (1, X, Y)   1: (-X, 1, Y)   2: (-1, -X, Y)   3: (X, -1, Y)
+ *   4: (-Y, X, 1)  5: (Y, X, -1)
+ * (normalised), which satisfies (2.5) and reproduces J of (2.10)-(2.11).
+ *
+ * Padded layout.  A state buffer is FP64 [3][6][P][P] with P = n + 2r,
+ * r = (order-1)/2, x fastest: element (var, panel, j, i) of interior cell
+ * (i, j), 0 <= i, j < n, lives at ((var*6 + panel)*P + (j+r))*P + (i+r).
+ * The outer r rings (corner blocks included, Figure 3.1b) are ghost cells.
+ * Unpadded buffers (tendencies, cotangents) are FP64 [3][6][n][n].
+ *
+ * Ownership.  Every state, tendency, cotangent and workspace buffer is a
+ * device allocation owned by the caller.  The grid owns only its constant
+ * tables and a small scratch buffer for panel-edge traces, allocated by
+ * hope_grid_create; no call allocates afterwards.  Calls that use the same
+ * grid must not run concurrently on different streams (they share that
+ * scratch); grids are otherwise independent.
+ *
+ * Errors.  Every int-returning function returns HOPE_OK (0) or a negative
+ * status; a thread-local message is available from hope_last_error().
+ * Argument and launch errors are reported synchronously; faults inside a
+ * kernel surface at the caller's next synchronisation of the stream.  No call
+ * except hope_grid_create / hope_grid_destroy synchronises the device.
+ *
+ * Streams are passed as void* holding a hipStream_t (NULL = null stream).
+ */
+#ifndef HOPE_H
+#define HOPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HOPE_OK = 0,
+  HOPE_ERR_INVALID = -1,     /* null pointer, bad enum, bad size, misaligned buffer */
+  HOPE_ERR_UNSUPPORTED = -2, /* order/scheme/n combination not built */
+  HOPE_ERR_HIP = -3,         /* a HIP runtime call failed */
+  HOPE_ERR_NOMEM = -4,       /* device or host allocation failed in create */
+  HOPE_ERR_NUMERIC = -5      /* ghost-map construction did not converge */
+};
+
+enum { HOPE_SCHEME_TPP = 0, HOPE_SCHEME_WENO = 1 };
+enum { HOPE_RK_SSP3 = 0, HOPE_RK_WS3 = 1 };
+
+typedef struct hope_grid hope_grid;
+
+/* Problem statement (sections 2-3).  Zero fields take the defaults shown. */
+typedef struct hope_grid_desc {
+  int32_t struct_size;   /* sizeof(hope_grid_desc) */
+  int32_t n;             /* cells per panel edge (C<n>), n >= order */
+  int32_t order;         /* stencil width k = order of accuracy, odd:
+                            TPP (3.7)-(3.15): 3,5,7,9,11,13; WENO (3.16)-(3.25): 3,5 */
+  int32_t scheme;        /* HOPE_SCHEME_TPP or HOPE_SCHEME_WENO */
+  int32_t n_gauss;       /* Gauss points per edge (3.5); 0 or (order+1)/2 */
+  int32_t reserved0;
+  double radius;         /* sphere radius a in m (default 6.371e6) */
+  double gravity;        /* g in m/s^2 (default 9.80616), informational */
+  double omega;          /* rotation rate Omega in 1/s (default 7.292e-5) */
+  double axis_tilt;      /* tilt alpha of the rotation axis towards -x (radians);
+                            Coriolis f = 2 Omega (-sin(a) x + cos(a) z) at the
+                            unit position (x, y, z); 0 gives f = 2 Omega sin(theta) */
+  double weno_eps;       /* epsilon of (3.23) (default 1e-12) */
+  double split_theta;    /* theta of the weight split (3.20) (default 3) */
+} hope_grid_desc;
+
+/* Sizes a caller needs to allocate buffers (all counts are elements). */
+typedef struct hope_layout {
+  int32_t n, r, padded, n_gauss;
+  int64_t state_elems;      /* 3*6*P*P: one padded state */
+  int64_t interior_elems;   /* 3*6*n*n: one unpadded field */
+  int64_t rk_workspace_bytes;  /* workspace of hope_rk_step */
+  int64_t ghost_cells;      /* ghost cells per variable, all panels */
+  int64_t ghost_nnz;        /* stored entries of the ghost map */
+} hope_layout;
+
+/* Build a grid: equiangular metrics, reconstruction and WENO tables, the
+ * exact ghost-cell map G of appendix (7.12) (the fixed point of the iterative
+ * interpolation of section 3.3.1, with owner-panel conversion (3.26)-(3.29)),
+ * and the panel-edge trace maps.  Host work plus device uploads; synchronous.
+ * On success *out owns device memory until hope_grid_destroy. */
+int hope_grid_create(const hope_grid_desc* desc, hope_grid** out);
+void hope_grid_destroy(hope_grid* grid);
+int hope_grid_layout(const hope_grid* grid, hope_layout* out);
+
+/* Ghost fill g = G q (7.12): overwrites the ghost rings of the padded state q
+ * (all 3 variables, 6 panels) from its interior cells.  Mass rows are scalar,
+ * momentum rows are 2x2 blocks (the conversion (3.29) at each ghost Gauss
+ * point).  Interior cells are read only. */
+int hope_fill_halo(const hope_grid* grid, double* q, void* stream);
+
+/* Tendency dq/dt of (3.1): fills the ghost rings of q (they are scratch),
+ * then for every interior cell reconstructs to the edge and cell Gauss
+ * points (TPP or genuine 2D WENO), takes the neighbour panel's converted
+ * trace at panel edges (3.26)-(3.29), evaluates the LMARS flux (3.30)-(3.38)
+ * with upwind term |m|(q_R - q_L), integrates fluxes (3.5) and the metric and
+ * Coriolis sources (2.2)-(2.3) (3.6), and writes dqdt [3][6][n][n]. */
+int hope_tendency(const hope_grid* grid, double* q, double* dqdt, void* stream);
+
+/* Vector-Jacobian product of hope_tendency: given w = dL/d(dqdt) [3][6][n][n]
+ * writes gq = dL/dq over the interior cells [3][6][n][n] (overwritten), the
+ * ghost-cell cotangents folded back through G^T.  q's ghost rings are scratch.
+ * Non-smooth points (|m|, |beta_i - beta_j|) take the subgradient sign(0)=0. */
+int hope_tendency_vjp(const hope_grid* grid, double* q, const double* w, double* gq,
+                      void* stream);
+
+/* One three-stage Runge-Kutta step (section 3.5) in place on the padded
+ * state q: HOPE_RK_SSP3 (Shu-Osher), or HOPE_RK_WS3 (3.39)-(3.41) with the
+ * second stage from q^n.  ws: device workspace of at least
+ * layout.rk_workspace_bytes (two padded states). */
+int hope_rk_step(const hope_grid* grid, double* q, double dt, int32_t scheme, double* ws,
+                 size_t ws_bytes, void* stream);
+
+/* Message for the last error on this thread ("" if none). */
+const char* hope_last_error(void);
+
+/* Launch shape of the fused stage kernel: each wavefront owns a strip of
+ * strip_w <= 62 interior columns of one panel and marches over seg_h rows.
+ * Any values in range give identical results; they only change speed (the
+ * autotuner picks them per grid).  Returns HOPE_ERR_INVALID out of range. */
+int hope_grid_set_launch(hope_grid* grid, int32_t strip_w, int32_t seg_h);
+int hope_grid_get_launch(const hope_grid* grid, int32_t* strip_w, int32_t* seg_h);
+
+/* Per-kernel timing.  While enabled, the library brackets each kernel it
+ * launches with HIP events recorded on the launch stream (events are created
+ * on first use and kept by the grid).  hope_grid_profile(g, 1) clears the
+ * record and starts, (g, 0) stops.  hope_grid_profile_read waits for the
+ * recorded events and returns the summed elapsed time and launch count of one
+ * kernel: 0 ghost fill, 1 panel-edge traces, 2 fused stage. */
+int hope_grid_profile(hope_grid* grid, int32_t enable);
+int hope_grid_profile_read(hope_grid* grid, int32_t kernel, double* total_ms, int64_t* launches);
+
+/* Host-only inspection of the ghost map G of appendix (7.12) that
+ * hope_grid_create would build for desc (no device use; for verification).
+ * Call with null arrays to get *rows and *nnz; then with arrays of at least
+ * rows (dst), rows+1 (ptr), nnz (col) and 5*nnz (val, struct of arrays:
+ * mass, C11, C12, C21, C22) elements.  dst/col are offsets inside one
+ * variable plane of the padded layout ((panel*P + jj)*P + ii).  Also returns
+ * the number of fixed-point sweeps the construction took in *sweeps. */
+int hope_inspect_ghost_map(const hope_grid_desc* desc, int64_t* rows, int64_t* nnz, int32_t* sweeps,
+                           int32_t* dst, int32_t* ptr, int32_t* col, double* val);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOPE_H */

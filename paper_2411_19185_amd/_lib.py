@@ -1,0 +1,141 @@
+"""ctypes binding of libhope.so (the C ABI in include/hope.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Device buffers are torch CUDA (HIP) FP64 tensors; the stream is
+torch's current stream.  The library is loaded from this package directory
+and its absence is an error: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhope.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "hope.h")
+
+HOPE_OK = 0
+HOPE_SCHEME_TPP, HOPE_SCHEME_WENO = 0, 1
+HOPE_RK_SSP3, HOPE_RK_WS3 = 0, 1
+
+
+class HopeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hope error {code}: {msg}")
+        self.code = code
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_int32),
+        ("n", ctypes.c_int32),
+        ("order", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
+        ("n_gauss", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("radius", ctypes.c_double),
+        ("gravity", ctypes.c_double),
+        ("omega", ctypes.c_double),
+        ("axis_tilt", ctypes.c_double),
+        ("weno_eps", ctypes.c_double),
+        ("split_theta", ctypes.c_double),
+    ]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("r", ctypes.c_int32),
+        ("padded", ctypes.c_int32),
+        ("n_gauss", ctypes.c_int32),
+        ("state_elems", ctypes.c_int64),
+        ("interior_elems", ctypes.c_int64),
+        ("rk_workspace_bytes", ctypes.c_int64),
+        ("ghost_cells", ctypes.c_int64),
+        ("ghost_nnz", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_SIGS = {
+    "hope_grid_create": (_I32, [ctypes.POINTER(GridDesc), ctypes.POINTER(_P)]),
+    "hope_grid_destroy": (None, [_P]),
+    "hope_grid_layout": (_I32, [_P, ctypes.POINTER(Layout)]),
+    "hope_fill_halo": (_I32, [_P, _P, _P]),
+    "hope_tendency": (_I32, [_P, _P, _P, _P]),
+    "hope_tendency_vjp": (_I32, [_P, _P, _P, _P, _P]),
+    "hope_rk_step": (_I32, [_P, _P, ctypes.c_double, _I32, _P, ctypes.c_size_t, _P]),
+    "hope_last_error": (ctypes.c_char_p, []),
+    "hope_grid_set_launch": (_I32, [_P, _I32, _I32]),
+    "hope_grid_get_launch": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "hope_grid_profile": (_I32, [_P, _I32]),
+    "hope_grid_profile_read": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "hope_inspect_ghost_map": (_I32, [ctypes.POINTER(GridDesc), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_I32),
+                                      _P, _P, _P, _P]),
+}
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/hope.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hope_[a-z_]+)\s*\(", txt)))
+
+
+def lib():
+    """The loaded library (raises if libhope.so has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2411_19185_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code: int):
+    if code != HOPE_OK:
+        raise HopeError(code, lib().hope_last_error().decode())
+
+
+def make_desc(n, order, scheme="tpp", radius=6.371e6, omega=7.292e-5, axis_tilt=0.0, weno_eps=1e-12,
+              split_theta=3.0, gravity=9.80616) -> GridDesc:
+    d = GridDesc()
+    d.struct_size = ctypes.sizeof(GridDesc)
+    d.n = n
+    d.order = order
+    d.scheme = {"tpp": HOPE_SCHEME_TPP, "weno": HOPE_SCHEME_WENO}[scheme]
+    d.n_gauss = 0
+    d.radius = radius
+    d.gravity = gravity
+    d.omega = omega
+    d.axis_tilt = axis_tilt
+    d.weno_eps = weno_eps
+    d.split_theta = split_theta
+    return d
+
+
+def inspect_ghost_map(n, order, scheme="tpp", radius=6.371e6):
+    """The ghost map the library builds, as numpy arrays (host only)."""
+    import numpy as np
+    d = make_desc(n, order, scheme, radius)
+    rows, nnz, sweeps = ctypes.c_int64(), ctypes.c_int64(), _I32()
+    check(lib().hope_inspect_ghost_map(ctypes.byref(d), ctypes.byref(rows), ctypes.byref(nnz),
+                                       ctypes.byref(sweeps), None, None, None, None))
+    dst = np.zeros(rows.value, np.int32)
+    ptr = np.zeros(rows.value + 1, np.int32)
+    col = np.zeros(nnz.value, np.int32)
+    val = np.zeros(5 * nnz.value, np.float64)
+    check(lib().hope_inspect_ghost_map(ctypes.byref(d), ctypes.byref(rows), ctypes.byref(nnz),
+                                       ctypes.byref(sweeps), dst.ctypes.data, ptr.ctypes.data,
+                                       col.ctypes.data, val.ctypes.data))
+    return dst, ptr, col, val.reshape(5, -1), sweeps.value

@@ -1,0 +1,354 @@
+// C ABI of the HOPE right-hand side library (declared in include/hope.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "hope.h"
+#include "hope_internal.hpp"
+
+using namespace hope;
+
+namespace {
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(HOPE_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+}  // namespace
+
+struct hope_grid {
+  HostTables h;
+  DevTables d{};
+  GhostDev g{};
+  std::vector<void*> allocs;
+  double* bt = nullptr;      // panel-edge trace scratch, 24*n*m*3
+  int strip_w = 62, seg_h = 8;
+  // optional per-kernel timing with HIP events on the launch stream
+  bool timing = false;
+  std::vector<hipEvent_t> pool;
+  struct Rec { int kind; int a, b; };
+  std::vector<Rec> recs;
+  size_t used = 0;
+};
+
+namespace {
+// kernels: 0 ghost fill, 1 edge traces, 2 stage
+hipEvent_t next_event(hope_grid* G) {
+  if (G->used == G->pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    G->pool.push_back(e);
+  }
+  return G->pool[G->used++];
+}
+
+struct Timed {
+  hope_grid* G;
+  int kind;
+  hipStream_t s;
+  int a = -1;
+  Timed(const hope_grid* g, int k, void* stream) : G(const_cast<hope_grid*>(g)), kind(k), s((hipStream_t)stream) {
+    if (!G->timing) return;
+    hipEvent_t e = next_event(G);
+    if (!e) return;
+    a = (int)G->used - 1;
+    (void)hipEventRecord(e, s);
+  }
+  ~Timed() {
+    if (a < 0) return;
+    hipEvent_t e = next_event(G);
+    if (!e) return;
+    (void)hipEventRecord(e, s);
+    G->recs.push_back({kind, a, (int)G->used - 1});
+  }
+};
+}  // namespace
+
+template <typename T>
+static int upload(hope_grid* G, const std::vector<T>& v, const T** out) {
+  *out = nullptr;
+  if (v.empty()) return 0;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, v.size() * sizeof(T));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+  G->allocs.push_back(p);
+  e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  *out = static_cast<const T*>(p);
+  return 0;
+}
+
+static void free_grid(hope_grid* G) {
+  if (!G) return;
+  for (hipEvent_t e : G->pool) (void)hipEventDestroy(e);
+  for (void* p : G->allocs) (void)hipFree(p);
+  delete G;
+}
+
+static void default_launch(hope_grid* G) {
+  const int n = G->h.n;
+  int sw = n < 62 ? n : 62;
+  const int strips = (n + 61) / 62;
+  sw = (n + strips - 1) / strips;          // balance the strips
+  G->strip_w = sw;
+  // enough wavefronts to cover the chip a few times over
+  int h = 8;
+  while (h > 2 && 6L * strips * ((n + h - 1) / h) < 2048) --h;
+  G->seg_h = h;
+}
+
+extern "C" {
+
+const char* hope_last_error(void) { return g_last_error.c_str(); }
+
+static int validate(const hope_grid_desc* desc) {
+  if (desc->struct_size != (int32_t)sizeof(hope_grid_desc)) return fail(HOPE_ERR_INVALID, "struct_size mismatch");
+  const int k = desc->order, n = desc->n;
+  const int weno = desc->scheme;
+  if (weno != HOPE_SCHEME_TPP && weno != HOPE_SCHEME_WENO) return fail(HOPE_ERR_INVALID, "bad scheme");
+  if (k < 3 || k > kMaxOrder || k % 2 == 0) return fail(HOPE_ERR_UNSUPPORTED, "order must be odd, 3..13");
+  if (weno && k > 5) return fail(HOPE_ERR_UNSUPPORTED, "WENO is built for orders 3 and 5");
+  if (desc->n_gauss != 0 && desc->n_gauss != (k + 1) / 2)
+    return fail(HOPE_ERR_UNSUPPORTED, "n_gauss must be (order+1)/2");
+  if (n < k || n > 4096) return fail(HOPE_ERR_UNSUPPORTED, "n must satisfy order <= n <= 4096");
+  if (!(desc->radius >= 0) || !std::isfinite(desc->axis_tilt) || !(desc->weno_eps >= 0))
+    return fail(HOPE_ERR_INVALID, "bad physical parameter");
+  return HOPE_OK;
+}
+
+int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
+  if (!desc || !out) return fail(HOPE_ERR_INVALID, "null argument");
+  *out = nullptr;
+  if (int v = validate(desc)) return v;
+  const int k = desc->order, n = desc->n;
+  const int weno = desc->scheme;
+  const double radius = desc->radius > 0 ? desc->radius : 6.371e6;
+  const double omega = desc->omega != 0 ? desc->omega : 7.292e-5;
+  const double eps = desc->weno_eps > 0 ? desc->weno_eps : 1e-12;
+  const double theta = desc->split_theta > 0 ? desc->split_theta : 3.0;
+  hope_grid* G = new (std::nothrow) hope_grid;
+  if (!G) return fail(HOPE_ERR_NOMEM, "host allocation");
+  int st = 0;
+  try {
+    st = build_tables(G->h, n, k, weno, radius, omega, desc->axis_tilt, eps, theta);
+  } catch (const std::bad_alloc&) {
+    free_grid(G);
+    return fail(HOPE_ERR_NOMEM, "host allocation while building tables");
+  }
+  if (st) {
+    std::string msg = G->h.error;
+    free_grid(G);
+    return fail(st, msg);
+  }
+  HostTables& h = G->h;
+  DevTables& d = G->d;
+#define UP(field, src)                         \
+  do {                                         \
+    int e_ = upload(G, src, &d.field);         \
+    if (e_) { free_grid(G); return e_; }       \
+  } while (0)
+  UP(wc, h.wc);
+  UP(wsub, h.wsub);
+  UP(gp, h.gp);
+  UP(gm, h.gm);
+  UP(sp, h.sp);
+  UP(sm, h.sm);
+  UP(V, h.V);
+  UP(lam, h.lam);
+  UP(Xe, h.Xe);
+  UP(Xg, h.Xg);
+  UP(gw, h.gw);
+  UP(fcoef, h.fcoef);
+  UP(bt_cell, h.bt_cell);
+  UP(bt_side, h.bt_side);
+  UP(bt_rev, h.bt_rev);
+  UP(bt_conv, h.bt_conv);
+#undef UP
+  d.radius = h.radius;
+  d.omega2 = 2.0 * h.omega;
+  d.eps = h.eps;
+  d.inv_delta = 1.0 / h.delta;
+  d.n = h.n;
+  d.P = h.P;
+  d.r = h.r;
+  d.m = h.m;
+  GhostDev& g = G->g;
+  int e1 = upload(G, h.g_dst, &g.dst);
+  if (!e1) e1 = upload(G, h.g_ptr, &g.ptr);
+  if (!e1) e1 = upload(G, h.g_col, &g.col);
+  if (!e1) e1 = upload(G, h.g_val, &g.val);
+  if (e1) { free_grid(G); return e1; }
+  g.nnz = (int64_t)h.g_col.size();
+  g.rows = (int)h.g_dst.size();
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, sizeof(double) * 24 * (size_t)n * h.m * 3);
+  if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipMalloc (edge traces)"); }
+  G->allocs.push_back(p);
+  G->bt = static_cast<double*>(p);
+  default_launch(G);
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipDeviceSynchronize"); }
+  *out = G;
+  return HOPE_OK;
+}
+
+void hope_grid_destroy(hope_grid* grid) {
+  if (!grid) return;
+  (void)hipDeviceSynchronize();
+  free_grid(grid);
+}
+
+int hope_grid_layout(const hope_grid* G, hope_layout* out) {
+  if (!G || !out) return fail(HOPE_ERR_INVALID, "null argument");
+  const HostTables& h = G->h;
+  out->n = h.n;
+  out->r = h.r;
+  out->padded = h.P;
+  out->n_gauss = h.m;
+  out->state_elems = 18LL * h.P * h.P;
+  out->interior_elems = 18LL * h.n * h.n;
+  out->rk_workspace_bytes = 2 * out->state_elems * (int64_t)sizeof(double);
+  out->ghost_cells = (int64_t)h.g_dst.size();
+  out->ghost_nnz = (int64_t)h.g_col.size();
+  return HOPE_OK;
+}
+
+int hope_fill_halo(const hope_grid* G, double* q, void* stream) {
+  if (!G || !q) return fail(HOPE_ERR_INVALID, "null argument");
+  if (reinterpret_cast<uintptr_t>(q) % 8) return fail(HOPE_ERR_INVALID, "misaligned state");
+  Timed tm(G, 0, stream);
+  int e = launch_fill_halo(G->g, q, 6 * G->h.P * G->h.P, stream);
+  if (e) return hip_fail((hipError_t)e, "fill_halo launch");
+  return HOPE_OK;
+}
+
+static int run_stage(const hope_grid* G, double* q, const double* qn, double* out, int out_padded, double ca,
+                     double cb, double cc, void* stream) {
+  int e;
+  {
+    Timed tm(G, 0, stream);
+    e = launch_fill_halo(G->g, q, 6 * G->h.P * G->h.P, stream);
+  }
+  if (e) return hip_fail((hipError_t)e, "fill_halo launch");
+  {
+    Timed tm(G, 1, stream);
+    e = launch_edge_traces(G->h.k, G->h.weno, G->d, q, G->bt, stream);
+  }
+  if (e) return hip_fail((hipError_t)e, "edge_traces launch");
+  {
+    Timed tm(G, 2, stream);
+    e = launch_stage(G->h.k, G->h.weno, G->d, q, qn, out, out_padded, ca, cb, cc, G->bt, G->strip_w, G->seg_h,
+                     stream);
+  }
+  if (e) return hip_fail((hipError_t)e, "stage launch");
+  return HOPE_OK;
+}
+
+int hope_tendency(const hope_grid* G, double* q, double* dqdt, void* stream) {
+  if (!G || !q || !dqdt) return fail(HOPE_ERR_INVALID, "null argument");
+  if (reinterpret_cast<uintptr_t>(q) % 8 || reinterpret_cast<uintptr_t>(dqdt) % 8)
+    return fail(HOPE_ERR_INVALID, "misaligned buffer");
+  return run_stage(G, q, nullptr, dqdt, 0, 0.0, 0.0, 1.0, stream);
+}
+
+int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq, void* stream) {
+  (void)q; (void)w; (void)gq; (void)stream;
+  if (!G) return fail(HOPE_ERR_INVALID, "null argument");
+  return fail(HOPE_ERR_UNSUPPORTED, "tendency VJP not built yet");
+}
+
+int hope_rk_step(const hope_grid* G, double* q, double dt, int32_t scheme, double* ws, size_t ws_bytes,
+                 void* stream) {
+  if (!G || !q || !ws) return fail(HOPE_ERR_INVALID, "null argument");
+  if (scheme != HOPE_RK_SSP3 && scheme != HOPE_RK_WS3) return fail(HOPE_ERR_INVALID, "bad RK scheme");
+  const size_t state = 18ULL * G->h.P * G->h.P;
+  if (ws_bytes < 2 * state * sizeof(double)) return fail(HOPE_ERR_INVALID, "workspace too small");
+  if (!std::isfinite(dt)) return fail(HOPE_ERR_INVALID, "dt not finite");
+  double* w0 = ws;
+  double* w1 = ws + state;
+  int st;
+  if (scheme == HOPE_RK_SSP3) {
+    if ((st = run_stage(G, q, nullptr, w0, 1, 0.0, 1.0, dt, stream))) return st;
+    if ((st = run_stage(G, w0, q, w1, 1, 0.75, 0.25, 0.25 * dt, stream))) return st;
+    if ((st = run_stage(G, w1, q, q, 1, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt, stream))) return st;
+  } else {
+    if ((st = run_stage(G, q, nullptr, w0, 1, 0.0, 1.0, dt / 3.0, stream))) return st;
+    if ((st = run_stage(G, w0, q, w1, 1, 1.0, 0.0, 0.5 * dt, stream))) return st;
+    if ((st = run_stage(G, w1, q, q, 1, 1.0, 0.0, dt, stream))) return st;
+  }
+  return HOPE_OK;
+}
+
+int hope_grid_set_launch(hope_grid* G, int32_t strip_w, int32_t seg_h) {
+  if (!G) return fail(HOPE_ERR_INVALID, "null argument");
+  if (strip_w < 1 || strip_w > 62 || seg_h < 1 || seg_h > G->h.n)
+    return fail(HOPE_ERR_INVALID, "launch shape out of range");
+  G->strip_w = strip_w;
+  G->seg_h = seg_h;
+  return HOPE_OK;
+}
+
+int hope_grid_get_launch(const hope_grid* G, int32_t* strip_w, int32_t* seg_h) {
+  if (!G || !strip_w || !seg_h) return fail(HOPE_ERR_INVALID, "null argument");
+  *strip_w = G->strip_w;
+  *seg_h = G->seg_h;
+  return HOPE_OK;
+}
+
+int hope_grid_profile(hope_grid* G, int32_t enable) {
+  if (!G) return fail(HOPE_ERR_INVALID, "null argument");
+  if (enable) {
+    G->recs.clear();
+    G->used = 0;
+  }
+  G->timing = enable != 0;
+  return HOPE_OK;
+}
+
+int hope_grid_profile_read(hope_grid* G, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!G || !total_ms || !launches) return fail(HOPE_ERR_INVALID, "null argument");
+  double tot = 0;
+  int64_t cnt = 0;
+  for (const auto& r : G->recs) {
+    if (r.kind != kernel) continue;
+    hipError_t e = hipEventSynchronize(G->pool[r.b]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0;
+    e = hipEventElapsedTime(&ms, G->pool[r.a], G->pool[r.b]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    tot += ms;
+    ++cnt;
+  }
+  *total_ms = tot;
+  *launches = cnt;
+  return HOPE_OK;
+}
+
+int hope_inspect_ghost_map(const hope_grid_desc* desc, int64_t* rows, int64_t* nnz, int32_t* sweeps,
+                           int32_t* dst, int32_t* ptr, int32_t* col, double* val) {
+  if (!desc || !rows || !nnz) return fail(HOPE_ERR_INVALID, "null argument");
+  if (int v = validate(desc)) return v;
+  const int k = desc->order, n = desc->n;
+  HostTables h;
+  const double radius = desc->radius > 0 ? desc->radius : 6.371e6;
+  int st = build_tables(h, n, k, desc->scheme, radius, 7.292e-5, 0.0, 1e-12, 3.0);
+  if (st) return fail(st, h.error);
+  *rows = (int64_t)h.g_dst.size();
+  *nnz = (int64_t)h.g_col.size();
+  if (sweeps) *sweeps = h.ghost_sweeps;
+  if (dst) std::memcpy(dst, h.g_dst.data(), h.g_dst.size() * sizeof(int32_t));
+  if (ptr) std::memcpy(ptr, h.g_ptr.data(), h.g_ptr.size() * sizeof(int32_t));
+  if (col) std::memcpy(col, h.g_col.data(), h.g_col.size() * sizeof(int32_t));
+  if (val) std::memcpy(val, h.g_val.data(), h.g_val.size() * sizeof(double));
+  return HOPE_OK;
+}
+
+}  // extern "C"

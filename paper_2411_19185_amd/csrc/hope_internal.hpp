@@ -1,0 +1,92 @@
+// Internal declarations shared by the host builder, the C ABI and the HIP
+// kernels of the HOPE right-hand side.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace hope {
+
+constexpr int kMaxOrder = 13;
+constexpr int kMaxGauss = 7;
+constexpr int kMaxPts = 4 * kMaxGauss + kMaxGauss * kMaxGauss;   // EQPs + CQPs of one cell
+constexpr int kMaxSub = 9;                                          // WENO5 sub-stencils
+
+// ---------------------------------------------------------------------------
+// Host-side tables (built once per grid, long double inside, FP64 out)
+// ---------------------------------------------------------------------------
+struct HostTables {
+  int n = 0, k = 0, r = 0, m = 0, P = 0, weno = 0, l = 0, s = 0;
+  double radius = 0, omega = 0, tilt = 0, eps = 0, theta = 0;
+  double delta = 0;
+  // axis coordinates of one cell: [-1/2, +1/2, g_0 .. g_{m-1}]
+  std::vector<double> gnode, gw;       // m
+  std::vector<double> wc;              // (2+m) x k   centred TPP weights
+  std::vector<double> wsub;            // l starts x (2+m) x l   sub-stencil weights
+  std::vector<double> gp, gm, sp, sm;  // npts x s, npts x s, npts, npts
+  std::vector<double> V;               // l starts x l x l   smoothness transform
+  std::vector<double> lam;             // l x l   smoothness eigen-weights
+  std::vector<double> Xe;              // n+1   X at cell edges
+  std::vector<double> Xg;              // n x m X at Gauss nodes
+  std::vector<double> fcoef;           // 6 x 3 Coriolis: f*delta = 2 Omega (c0 + cX X + cY Y)
+  // ghost map, one row per ghost cell (same pattern for the 3 variables)
+  std::vector<int32_t> g_dst;          // padded offset (within one variable plane) of the ghost
+  std::vector<int32_t> g_ptr;          // row pointers
+  std::vector<int32_t> g_col;          // padded offset of the interior cell
+  std::vector<double> g_val;           // 5 x nnz: mass, C11, C12, C21, C22 (SoA)
+  int ghost_sweeps = 0;
+  // panel-edge traces: for (panel A, side, t, h): the neighbour cell and point
+  std::vector<int32_t> bt_cell;        // 6*4*n: padded offset of B's cell centre
+  std::vector<int32_t> bt_side;        // 6*4*n: which side of B's cell (0 L,1 R,2 B,3 T)
+  std::vector<int32_t> bt_rev;         // 6*4*n: 1 if the Gauss points run in reverse
+  std::vector<double> bt_conv;         // 6*4*n*m*5: mass ratio, C11, C12, C21, C22
+  std::string error;
+};
+
+// Builds every table; returns 0 on success, else a HOPE_ERR code with error set.
+int build_tables(HostTables& t, int n, int k, int weno, double radius, double omega, double tilt,
+                 double eps, double theta);
+
+// ---------------------------------------------------------------------------
+// Device-side view of the constant tables (passed by value to kernels)
+// ---------------------------------------------------------------------------
+struct DevTables {
+  const double* wc;
+  const double* wsub;
+  const double* gp;
+  const double* gm;
+  const double* sp;
+  const double* sm;
+  const double* V;
+  const double* lam;
+  const double* Xe;
+  const double* Xg;
+  const double* gw;
+  const double* fcoef;
+  const int32_t* bt_cell;
+  const int32_t* bt_side;
+  const int32_t* bt_rev;
+  const double* bt_conv;
+  double radius, omega2, eps, inv_delta;
+  int n, P, r, m;
+};
+
+struct GhostDev {
+  const int32_t* dst;
+  const int32_t* ptr;
+  const int32_t* col;
+  const double* val;     // 5 x nnz
+  int64_t nnz;
+  int rows;
+};
+
+// Launchers implemented in kernels.hip.  All enqueue on `stream` and return a
+// hipError_t value (0 on success).
+int launch_fill_halo(const GhostDev& g, double* q, int plane, void* stream);
+int launch_edge_traces(int k, int weno, const DevTables& t, const double* q, double* bt, void* stream);
+int launch_stage(int k, int weno, const DevTables& t, const double* q, const double* qn, double* out,
+                 int out_padded, double ca, double cb, double cc, const double* bt, int strip_w,
+                 int seg_h, void* stream);
+
+}  // namespace hope

@@ -1,0 +1,115 @@
+"""Torch-facing wrapper of the C ABI: a Grid owns a hope_grid handle and
+passes tensor pointers and torch's current stream to the library."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import (HOPE_RK_SSP3, HOPE_RK_WS3, Layout, check, lib, make_desc)
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Grid:
+    """One cubed-sphere grid (n cells per panel edge), reconstruction order
+    and scheme ('tpp' or 'weno'), with the physical constants of the problem."""
+
+    def __init__(self, n: int, order: int, scheme: str = "tpp", radius: float = 6.371e6,
+                 omega: float = 7.292e-5, axis_tilt: float = 0.0, weno_eps: float = 1e-12,
+                 split_theta: float = 3.0):
+        self.desc = make_desc(n, order, scheme, radius, omega, axis_tilt, weno_eps, split_theta)
+        h = ctypes.c_void_p()
+        check(lib().hope_grid_create(ctypes.byref(self.desc), ctypes.byref(h)))
+        self._h = h
+        lay = Layout()
+        check(lib().hope_grid_layout(h, ctypes.byref(lay)))
+        self.layout = lay
+        self.n, self.order, self.scheme = n, order, scheme
+        self.r = lay.r
+        self.P = lay.padded
+        self.m = lay.n_gauss
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().hope_grid_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------------
+    def new_state(self, device="cuda") -> torch.Tensor:
+        return torch.zeros(3, 6, self.P, self.P, dtype=torch.float64, device=device)
+
+    def interior(self, q: torch.Tensor) -> torch.Tensor:
+        r, n = self.r, self.n
+        return q[:, :, r:r + n, r:r + n]
+
+    def _check_state(self, q):
+        if not (q.is_cuda and q.dtype == torch.float64 and q.is_contiguous()
+                and tuple(q.shape) == (3, 6, self.P, self.P)):
+            raise ValueError(f"state must be a contiguous cuda float64 tensor of shape (3, 6, {self.P}, {self.P})")
+
+    def _check_field(self, f):
+        if not (f.is_cuda and f.dtype == torch.float64 and f.is_contiguous()
+                and tuple(f.shape) == (3, 6, self.n, self.n)):
+            raise ValueError(f"field must be a contiguous cuda float64 tensor of shape (3, 6, {self.n}, {self.n})")
+
+    # ------------------------------------------------------------------
+    def fill_halo(self, q: torch.Tensor) -> torch.Tensor:
+        self._check_state(q)
+        check(lib().hope_fill_halo(self._h, _ptr(q), _stream()))
+        return q
+
+    def tendency(self, q: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._check_state(q)
+        if out is None:
+            out = torch.empty(3, 6, self.n, self.n, dtype=torch.float64, device=q.device)
+        self._check_field(out)
+        check(lib().hope_tendency(self._h, _ptr(q), _ptr(out), _stream()))
+        return out
+
+    def tendency_vjp(self, q: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._check_state(q)
+        self._check_field(w)
+        if out is None:
+            out = torch.empty(3, 6, self.n, self.n, dtype=torch.float64, device=q.device)
+        self._check_field(out)
+        check(lib().hope_tendency_vjp(self._h, _ptr(q), _ptr(w), _ptr(out), _stream()))
+        return out
+
+    def workspace(self) -> torch.Tensor:
+        return torch.empty(self.layout.rk_workspace_bytes // 8, dtype=torch.float64, device="cuda")
+
+    def rk_step(self, q: torch.Tensor, dt: float, scheme: str = "ssp3", ws: torch.Tensor | None = None):
+        self._check_state(q)
+        if ws is None:
+            ws = self.workspace()
+        code = {"ssp3": HOPE_RK_SSP3, "ws3": HOPE_RK_WS3}[scheme]
+        check(lib().hope_rk_step(self._h, _ptr(q), float(dt), code, _ptr(ws), ws.numel() * 8, _stream()))
+        return q
+
+    def set_launch(self, strip_w: int, seg_h: int):
+        check(lib().hope_grid_set_launch(self._h, int(strip_w), int(seg_h)))
+
+    def get_launch(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().hope_grid_get_launch(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    # ------------------------------------------------------------------
+    KERNELS = {"fill_halo": 0, "edge_traces": 1, "stage": 2}
+
+    def profile(self, enable: bool):
+        check(lib().hope_grid_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self, kernel: str):
+        """(total ms, launches) of one kernel since profile(True)."""
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        check(lib().hope_grid_profile_read(self._h, self.KERNELS[kernel], ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value

@@ -1,0 +1,133 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs, at 1e-11 relative (L-infinity over all cells, per
+variable)."""
+import pytest
+import torch
+
+from cases import STATES, cfl_dt, oracle_grid, rel_err, to_padded
+from oracle.rk import ssp_rk3, ws_rk3
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def _gpu_grid(n, order, scheme, alpha):
+    from paper_2411_19185_amd import Grid
+    return Grid(n, order, scheme, axis_tilt=alpha)
+
+
+CASES = [
+    # (n, order, scheme, state, seed)
+    (30, 3, "tpp", "balanced", 0),           # 3-degree TPP3 balanced flow
+    (90, 5, "weno", "dam_break", 1),          # 1-degree WENO5 dam break
+    (12, 11, "tpp", "perturbed_balanced", 2),  # TPP11 differentiation grid
+    (13, 5, "weno", "member", 3),            # ragged: odd n, one strip
+    (7, 5, "tpp", "member", 4),              # n barely above the order
+    (10, 3, "weno", "dam_break", 5),
+    (14, 7, "tpp", "member", 6),
+    (18, 9, "tpp", "perturbed_balanced", 7),
+    (26, 13, "tpp", "perturbed_balanced", 8),
+    (70, 5, "tpp", "member", 9),             # two strips per panel
+    (64, 3, "tpp", "member", 10),
+]
+
+
+@pytest.mark.parametrize("n,order,scheme,state,seed", CASES)
+def test_tendency_matches_oracle(n, order, scheme, state, seed):
+    print(f"case n={n} order={order} {scheme} {state} seed={seed}", flush=True)
+    alpha, q = STATES[state](n, seed)
+    og = oracle_grid(n, order, scheme, alpha)
+    ref = og.tendency(q)
+    g = _gpu_grid(n, order, scheme, alpha)
+    out = g.tendency(to_padded(q, g.r))
+    torch.cuda.synchronize()
+    err = rel_err(out, ref)
+    print("rel err", err, flush=True)
+    assert max(err) < TOL, err
+
+
+@pytest.mark.parametrize("n,order,scheme,state,seed", [(30, 3, "tpp", "member", 11), (16, 5, "weno", "member", 12),
+                                                       (12, 11, "tpp", "member", 13)])
+def test_halo_matches_oracle_fixed_point(n, order, scheme, state, seed):
+    print(f"case n={n} order={order} {scheme}", flush=True)
+    alpha, q = STATES[state](n, seed)
+    og = oracle_grid(n, order, scheme, alpha)
+    ref = og.ghost.fill(q)
+    g = _gpu_grid(n, order, scheme, alpha)
+    qp = to_padded(q, g.r)
+    g.fill_halo(qp)
+    torch.cuda.synchronize()
+    assert max(rel_err(qp, ref)) < 1e-13
+
+
+@pytest.mark.parametrize("sw,sh", [(5, 3), (62, 30), (17, 1), (30, 7)])
+def test_launch_shape_does_not_change_results(sw, sh):
+    n, order, scheme = 30, 5, "weno"
+    alpha, q = STATES["member"](n, 14)
+    g = _gpu_grid(n, order, scheme, alpha)
+    base = g.tendency(to_padded(q, g.r))
+    g.set_launch(sw, sh)
+    other = g.tendency(to_padded(q, g.r))
+    torch.cuda.synchronize()
+    assert torch.equal(base, other)
+
+
+@pytest.mark.parametrize("n,order,scheme,state,steps,rk", [(30, 3, "tpp", "balanced", 10, "ssp3"),
+                                                            (24, 5, "weno", "dam_break", 4, "ssp3"),
+                                                            (16, 5, "tpp", "member", 3, "ws3")])
+def test_rk_steps_match_oracle(n, order, scheme, state, steps, rk):
+    print(f"case n={n} order={order} {scheme} {rk}", flush=True)
+    alpha, q = STATES[state](n, 15)
+    dt = cfl_dt(q)
+    og = oracle_grid(n, order, scheme, alpha)
+    step = ssp_rk3 if rk == "ssp3" else ws_rk3
+    ref = q.clone()
+    for _ in range(steps):
+        ref = step(og.tendency, ref, dt)
+    g = _gpu_grid(n, order, scheme, alpha)
+    qp = to_padded(q, g.r)
+    ws = g.workspace()
+    for _ in range(steps):
+        g.rk_step(qp, dt, rk, ws)
+    torch.cuda.synchronize()
+    err = rel_err(g.interior(qp), ref)
+    print("rel err", err, flush=True)
+    assert max(err) < TOL, err
+
+
+def test_full_size_weno5_c360_tendency():
+    """0.25-degree WENO5 (the benchmark grid) against the full oracle, on a
+    moving state (balanced flow with a height jump)."""
+    n, order, scheme = 360, 5, "weno"
+    print("case C360 WENO5 member state", flush=True)
+    alpha, q = STATES["member"](n, 22, nq=2)
+    og = oracle_grid(n, order, scheme, alpha)
+    ref = og.tendency(q)
+    print("oracle done", flush=True)
+    g = _gpu_grid(n, order, scheme, alpha)
+    out = g.tendency(to_padded(q, g.r))
+    torch.cuda.synchronize()
+    err = rel_err(out, ref)
+    print("rel err", err, flush=True)
+    assert max(err) < TOL, err
+
+
+def test_full_size_weno5_c360_rk_step():
+    """One SSP-RK3 step of the benchmark's smooth random resting state at
+    C360 (the state, unlike the mass tendency of a fluid at rest, is well
+    conditioned)."""
+    n, order, scheme = 360, 5, "weno"
+    print("case C360 WENO5 smooth random, one SSP-RK3 step", flush=True)
+    alpha, q = STATES["smooth_random"](n, 21, nq=2)
+    dt = cfl_dt(q)
+    og = oracle_grid(n, order, scheme, alpha)
+    ref = ssp_rk3(og.tendency, q, dt)
+    print("oracle done", flush=True)
+    g = _gpu_grid(n, order, scheme, alpha)
+    qp = to_padded(q, g.r)
+    g.rk_step(qp, dt)
+    torch.cuda.synchronize()
+    err = rel_err(g.interior(qp), ref)
+    print("rel err", err, flush=True)
+    assert max(err) < TOL, err
