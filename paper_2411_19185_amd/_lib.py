@@ -12,7 +12,8 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhope.so")
+# HOPE_LIB selects another build of the same library (used to compare build variants)
+LIB_PATH = os.environ.get("HOPE_LIB") or os.path.join(HERE, "libhope.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "hope.h")
 
 HOPE_OK = 0

@@ -165,6 +165,8 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
   UP(lam, h.lam);
   UP(Xe, h.Xe);
   UP(Xg, h.Xg);
+  UP(sqe, h.sqe);
+  UP(sqg, h.sqg);
   UP(gw, h.gw);
   UP(fcoef, h.fcoef);
   UP(bt_cell, h.bt_cell);

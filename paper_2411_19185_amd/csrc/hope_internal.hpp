@@ -29,6 +29,7 @@ struct HostTables {
   std::vector<double> lam;             // l x l   smoothness eigen-weights
   std::vector<double> Xe;              // n+1   X at cell edges
   std::vector<double> Xg;              // n x m X at Gauss nodes
+  std::vector<double> sqe, sqg;        // sqrt(1 + X^2) at edges (n+1) and Gauss nodes (n x m)
   std::vector<double> fcoef;           // 6 x 3 Coriolis: f*delta = 2 Omega (c0 + cX X + cY Y)
   // ghost map, one row per ghost cell (same pattern for the 3 variables)
   std::vector<int32_t> g_dst;          // padded offset (within one variable plane) of the ghost
@@ -62,6 +63,8 @@ struct DevTables {
   const double* lam;
   const double* Xe;
   const double* Xg;
+  const double* sqe;
+  const double* sqg;
   const double* gw;
   const double* fcoef;
   const int32_t* bt_cell;

@@ -686,6 +686,17 @@ int build_tables(HostTables& t, int n, int k, int weno, double radius, double om
   for (int i = 0; i < n; ++i)
     for (int h = 0; h < m; ++h)
       t.Xg[i * m + h] = (double)std::tan(((ld)i + 0.5L - n / 2.0L + gx[h]) * kPi / (2 * (ld)n));
+  t.sqe.resize(n + 1);
+  for (int e = 0; e <= n; ++e) {
+    ld X = (e == 0) ? -1 : (e == n) ? 1 : std::tan(((ld)e - n / 2.0L) * (ld)kPi / (2 * (ld)n));
+    t.sqe[e] = (double)std::sqrt(1 + X * X);
+  }
+  t.sqg.resize(n * m);
+  for (int i = 0; i < n; ++i)
+    for (int h = 0; h < m; ++h) {
+      ld X = std::tan(((ld)i + 0.5L - n / 2.0L + gx[h]) * kPi / (2 * (ld)n));
+      t.sqg[i * m + h] = (double)std::sqrt(1 + X * X);
+    }
   ld sa = std::sin((ld)tilt), ca = std::cos((ld)tilt);
   const ld fc[6][3] = {{-sa, 0, ca}, {0, sa, ca}, {sa, 0, ca}, {0, -sa, ca}, {ca, 0, sa}, {-ca, 0, -sa}};
   t.fcoef.resize(18);

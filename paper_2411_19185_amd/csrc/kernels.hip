@@ -21,6 +21,25 @@
 
 namespace hope {
 
+// Constant-address-space view of the grid tables: the tables never change
+// while a kernel runs, and loads through this address space with uniform
+// addresses become scalar loads into SGPRs instead of per-lane vector loads.
+typedef const __attribute__((address_space(4))) double* cdp;
+typedef const __attribute__((address_space(4))) int32_t* cip;
+
+struct CTab {
+  cdp wc, wsub, gp, gm, sp, sm, V, lam, Xe, Xg, sqe, sqg, gw, fcoef, bt_conv;
+  cip bt_cell, bt_side, bt_rev;
+  double radius, omega2, eps, inv_delta;
+  int n, P, r, m;
+  __device__ explicit CTab(const DevTables& d)
+      : wc((cdp)d.wc), wsub((cdp)d.wsub), gp((cdp)d.gp), gm((cdp)d.gm), sp((cdp)d.sp), sm((cdp)d.sm),
+        V((cdp)d.V), lam((cdp)d.lam), Xe((cdp)d.Xe), Xg((cdp)d.Xg), sqe((cdp)d.sqe), sqg((cdp)d.sqg),
+        gw((cdp)d.gw), fcoef((cdp)d.fcoef), bt_conv((cdp)d.bt_conv), bt_cell((cip)d.bt_cell),
+        bt_side((cip)d.bt_side), bt_rev((cip)d.bt_rev), radius(d.radius), omega2(d.omega2), eps(d.eps),
+        inv_delta(d.inv_delta), n(d.n), P(d.P), r(d.r), m(d.m) {}
+};
+
 // ---------------------------------------------------------------------------
 // Ghost fill
 // ---------------------------------------------------------------------------
@@ -68,10 +87,10 @@ struct Recon {
   const double* __restrict__ c0;   // var-0 value of the cell
   int P;
   size_t vs;                       // distance between variables
-  const DevTables t;
+  const CTab t;
   double kap[W ? 3 : 1][W ? S : 1];
 
-  __device__ Recon(const double* c, int P_, size_t vs_, const DevTables& t_) : c0(c), P(P_), vs(vs_), t(t_) {}
+  __device__ Recon(const double* c, int P_, size_t vs_, const CTab& t_) : c0(c), P(P_), vs(vs_), t(t_) {}
 
   __device__ __forceinline__ double at(int v, int dy, int dx) const { return c0[v * vs + dy * P + dx]; }
 
@@ -252,8 +271,9 @@ __device__ __forceinline__ void sources(double Q0, double Q1, double Q2, double 
 // Panel-edge traces: bt[((A*4+side)*n + t)*m + h][var], in A's variables
 // ---------------------------------------------------------------------------
 template <int K, bool W, int M>
-__global__ __launch_bounds__(64) void k_edge_traces(DevTables t, const double* __restrict__ q,
+__global__ __launch_bounds__(64) void k_edge_traces(DevTables td, const double* __restrict__ q,
                                                      double* __restrict__ bt) {
+  const CTab t(td);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 24 * t.n) return;
   const size_t vs = (size_t)6 * t.P * t.P;
@@ -265,7 +285,7 @@ __global__ __launch_bounds__(64) void k_edge_traces(DevTables t, const double* _
 #pragma unroll
   for (int h = 0; h < M; ++h) {
     const int hb = rev ? M - 1 - h : h;
-    const double* cv = t.bt_conv + ((size_t)idx * M + h) * 5;
+    cdp cv = t.bt_conv + ((size_t)idx * M + h) * 5;
     double* o = bt + ((size_t)idx * M + h) * 3;
     o[0] = cv[0] * vals[0][hb];
     o[1] = cv[1] * vals[1][hb] + cv[2] * vals[2][hb];
@@ -286,10 +306,99 @@ struct StageArgs {
   int strip_w, seg_h, n_strips, n_segs;
 };
 
+// reciprocal: hardware estimate refined by two Newton-Raphson steps
+__device__ __forceinline__ double rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// square root: Goldschmidt iteration from the hardware reciprocal square root
+__device__ __forceinline__ double sqrt_g(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+// LMARS with the fast reciprocal/root; X-direction (dir 0) or y (dir 1).
+// sqx = sqrt(1 + X^2), sqy = sqrt(1 + Y^2) come from tables.
+__device__ __forceinline__ void lmars_fast(const double* qL, const double* qR, double X, double Y, double sqx,
+                                           double sqy, int dir, double a, double ia, double* F) {
+  const double ox = sqx * sqx, oy = sqy * sqy;
+  const double d2 = fma(X, X, oy);
+  const double dl = sqrt_g(d2);
+  const double idl = rcp(dl);
+  // 1/sqrtG = delta^3 / (a^2 (1+X^2)(1+Y^2))
+  const double isg = d2 * dl * ia * ia * rcp(ox * oy);
+  const double sgii = dl * ia * rcp(dir == 0 ? sqx : sqy);      // sqrt(G^ii)
+  const int iv = 1 + dir;
+  const double phiL = qL[0] * isg, phiR = qR[0] * isg;
+  const double iL = rcp(qL[0] * sgii), iR = rcp(qR[0] * sgii);
+  const double upL = qL[iv] * iL, upR = qR[iv] * iR;              // (3.31)
+  const double c = 0.5 * (sqrt_g(phiL) + sqrt_g(phiR));           // (3.34)-(3.35)
+  const double ms = 0.5 * (upL + upR - (phiR - phiL) * rcp(c));   // (3.32)
+  const double ps = 0.5 * (phiL + phiR - c * (upR - upL));        // (3.33)
+  const double mm = ms * sgii;                                    // (3.36)
+  const double am = fabs(mm);
+#pragma unroll
+  for (int v = 0; v < 3; ++v) F[v] = 0.5 * (mm * (qL[v] + qR[v]) - am * (qR[v] - qL[v]));   // (3.37)
+  const double pr = 0.5 * ps * ps * idl;                          // (3.38)
+  if (dir == 0) {
+    F[1] = fma(pr, oy, F[1]);
+    F[2] = fma(pr, X * Y, F[2]);
+  } else {
+    F[1] = fma(pr, X * Y, F[1]);
+    F[2] = fma(pr, ox, F[2]);
+  }
+}
+
+__device__ __forceinline__ void sources_fast(double Q0, double Q1, double Q2, double X, double Y, double Lc,
+                                             double omega2, double& s1, double& s2) {
+  const double X2 = X * X, Y2 = Y * Y;
+  const double id2 = rcp(1.0 + X2 + Y2);
+  const double iq = 2.0 * rcp(Q0);
+  const double m1 = iq * (Y * (1.0 + Y2) * Q1 * Q2 - X * Y2 * Q1 * Q1);
+  const double m2 = iq * (X * (1.0 + X2) * Q1 * Q2 - X2 * Y * Q2 * Q2);
+  const double f = omega2 * Lc;
+  const double c1 = f * ((1.0 + Y2) * Q2 - X * Y * Q1);
+  const double c2 = f * (X * Y * Q2 - (1.0 + X2) * Q1);
+  s1 = (m1 + c1) * id2;
+  s2 = (m2 + c2) * id2;
+}
+
+// Stencil window in LDS: NR = 2R+1 padded rows of CW = 64 + 2R columns of a
+// strip, 3 variables; LDS column c holds padded column i0 - 1 + c.
 template <int K, bool W, int M>
-__global__ __launch_bounds__(64) void k_stage(DevTables t, StageArgs A) {
-  using RC = Recon<K, W, M>;
-  const int n = t.n, P = t.P, r = t.r;
+struct Window {
+  static constexpr int R = (K - 1) / 2;
+  static constexpr int L = (K + 1) / 2;
+  static constexpr int S = L * L;
+  static constexpr int NA = 2 + M;
+  static constexpr int NR = 2 * R + 1;
+  static constexpr int CW = 64 + 2 * R;
+};
+
+template <int K, bool W, int M>
+#ifndef HOPE_STAGE_WAVES
+#define HOPE_STAGE_WAVES 1
+#endif
+__global__ __launch_bounds__(64, HOPE_STAGE_WAVES) void k_stage(DevTables td, StageArgs A) {
+  const CTab t(td);
+  using Wd = Window<K, W, M>;
+  constexpr int R = Wd::R, L = Wd::L, S = Wd::S, NA = Wd::NA, NR = Wd::NR, CW = Wd::CW;
+  constexpr int XR = W ? L * NR : NR;
+  __shared__ double sq[3][NR][CW];
+
+  const int n = t.n, P = t.P;
   const size_t plane = (size_t)P * P;
   const size_t vs = 6 * plane;
   int item = blockIdx.x;
@@ -299,121 +408,303 @@ __global__ __launch_bounds__(64) void k_stage(DevTables t, StageArgs A) {
   const int p = item / A.n_strips;
   const int lane = threadIdx.x;
   const int i0 = strip * A.strip_w;
-  const int i1 = min(n, i0 + A.strip_w);          // owned columns [i0, i1)
-  const int i = i0 - 1 + lane;                     // this lane's column
+  const int i1 = min(n, i0 + A.strip_w);
+  const int i = i0 - 1 + lane;
   const bool in_strip = (i >= i0 - 1) && (i <= i1);
-  const bool can_rec = in_strip && i >= 0 && i < n;      // a real cell of this panel
+  const bool real = in_strip && i >= 0 && i < n;
   const bool owner = i >= i0 && i < i1;
   const int j0 = seg * A.seg_h;
   const int j1 = min(n, j0 + A.seg_h);
   const double invd = t.inv_delta;
+  const double ia = 1.0 / t.radius;
   const double* qp = A.q + p * plane;
   const double* btp = A.bt + (size_t)p * 4 * n * M * 3;
   const double Lx0 = t.fcoef[p * 3 + 0], LxX = t.fcoef[p * 3 + 1], LxY = t.fcoef[p * 3 + 2];
+  const int ic = max(0, min(n - 1, i));        // clamped column for table reads
+  const int ie = max(0, min(n, i));            // clamped edge index
+  const double Xei = t.Xe[ie], sqxe = t.sqe[ie];
 
-  // ---- prologue: top traces of row j0-1 --------------------------------
-  double ptop[3][M];
+  // ---- window loading --------------------------------------------------
+  constexpr int PER = (3 * CW + 63) / 64;
+  auto fetch = [&](int pr, double* buf) {
 #pragma unroll
-  for (int v = 0; v < 3; ++v)
-#pragma unroll
-    for (int h = 0; h < M; ++h) ptop[v][h] = 0.0;
-  if (i >= 0 && i < n && in_strip) {
-    if (j0 == 0) {
-#pragma unroll
-      for (int h = 0; h < M; ++h)
-#pragma unroll
-        for (int v = 0; v < 3; ++v) ptop[v][h] = btp[(((size_t)2 * n + i) * M + h) * 3 + v];
-    } else {
-      RC rc(qp + (size_t)(j0 - 1 + r) * P + (i + r), P, vs, t);
-      rc.init();
-      rc.side(3, ptop);
+    for (int k = 0; k < PER; ++k) {
+      const int idx = lane + 64 * k;
+      const int v = idx / CW, c = idx % CW;
+      const int gc = i0 - 1 + c;
+      buf[k] = (idx < 3 * CW && pr >= 0 && pr < P && gc >= 0 && gc < P) ? qp[v * vs + (size_t)pr * P + gc] : 0.0;
     }
+  };
+  auto store = [&](int pr, const double* buf) {
+    const int slot = pr % NR;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = lane + 64 * k;
+      if (idx < 3 * CW) sq[idx / CW][slot][idx % CW] = buf[k];
+    }
+  };
+  // stencil value at offset (dy, dx) of this lane's cell in the row centred at padded row pc
+  // pc = interior row of the centre cell, so the padded row is pc + R + dy
+  auto at = [&](int v, int pc, int dy, int dx) -> double { return sq[v][(pc + R + dy) % NR][lane + R + dx]; };
+
+  // ---- reconstruction helpers (centre padded row pc) --------------------
+  double kap[W ? 3 : 1][W ? S : 1];
+  auto weights_init = [&](int pc) {
+    if constexpr (W) {
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        double beta[S];
+#pragma unroll
+        for (int sx = 0; sx < L; ++sx) {
+          double tr[NR][L];
+#pragma unroll
+          for (int row = 0; row < NR; ++row)
+#pragma unroll
+            for (int al = 0; al < L; ++al) {
+              double s = 0;
+#pragma unroll
+              for (int a = 0; a < L; ++a)
+                s = fma(t.V[(sx * L + al) * L + a], at(v, pc, row - R, sx - (L - 1) + a), s);
+              tr[row][al] = s;
+            }
+#pragma unroll
+          for (int sy = 0; sy < L; ++sy) {
+            double b = 0;
+#pragma unroll
+            for (int be = 0; be < L; ++be)
+#pragma unroll
+              for (int al = 0; al < L; ++al) {
+                if (al == 0 && be == 0) continue;
+                double c = 0;
+#pragma unroll
+                for (int bb = 0; bb < L; ++bb) c = fma(t.V[(sy * L + be) * L + bb], tr[sy + bb][al], c);
+                b = fma(t.lam[be * L + al] * c, c, b);
+              }
+            beta[sy * L + sx] = b;
+          }
+        }
+        double tau = 0;
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+#pragma unroll
+          for (int b = a + 1; b < S; ++b) tau += fabs(beta[a] - beta[b]);
+        tau *= 2.0 / (S * (S + 1));
+#pragma unroll
+        for (int j = 0; j < S; ++j) kap[v][j] = fma(tau, rcp(beta[j] + t.eps), 1.0);
+      }
+    }
+  };
+  auto xpass = [&](int v, int pc, int px, double* xr) {
+    // each pass re-reads its stencil from LDS rather than keeping all of it live
+    asm volatile("" ::: "memory");
+    if constexpr (!W) {
+#pragma unroll
+      for (int row = 0; row < NR; ++row) {
+        double s = 0;
+#pragma unroll
+        for (int a = 0; a < K; ++a) s = fma(t.wc[px * K + a], at(v, pc, row - R, a - R), s);
+        xr[row] = s;
+      }
+    } else {
+#pragma unroll
+      for (int sx = 0; sx < L; ++sx)
+#pragma unroll
+        for (int row = 0; row < NR; ++row) {
+          double s = 0;
+#pragma unroll
+          for (int a = 0; a < L; ++a)
+            s = fma(t.wsub[(sx * NA + px) * L + a], at(v, pc, row - R, sx - (L - 1) + a), s);
+          xr[sx * NR + row] = s;
+        }
+    }
+  };
+  auto point = [&](int v, int py, int pt, const double* xr) -> double {
+    if constexpr (!W) {
+      double s = 0;
+#pragma unroll
+      for (int b = 0; b < K; ++b) s = fma(t.wc[py * K + b], xr[b], s);
+      return s;
+    } else {
+      double ap = 0, dp = 0, am = 0, dm = 0;
+#pragma unroll
+      for (int sy = 0; sy < L; ++sy)
+#pragma unroll
+        for (int sx = 0; sx < L; ++sx) {
+          double pv = 0;
+#pragma unroll
+          for (int b = 0; b < L; ++b) pv = fma(t.wsub[(sy * NA + py) * L + b], xr[sx * NR + sy + b], pv);
+          const int j = sy * L + sx;
+          const double tk = kap[v][j] * pv;
+          ap = fma(t.gp[pt * S + j], tk, ap);
+          am = fma(t.gm[pt * S + j], tk, am);
+          dp = fma(t.gp[pt * S + j], kap[v][j], dp);
+          dm = fma(t.gm[pt * S + j], kap[v][j], dm);
+        }
+      return (t.sp[pt] * ap * dm - t.sm[pt] * am * dp) * rcp(dp * dm);
+    }
+  };
+
+  // ---- prologue: window and the top traces of row j0-1 ------------------
+  double ptop[3][M];
+  double nxt[PER];
+  {
+    for (int pr = max(0, j0 - 1); pr < j0 + 2 * R; ++pr) {
+      fetch(pr, nxt);
+      store(pr, nxt);
+    }
+    fetch(j0 + 2 * R, nxt);          // row needed by the first step
+  }
+  __syncthreads();
+  if (j0 == 0) {
+#pragma unroll
+    for (int h = 0; h < M; ++h)
+#pragma unroll
+      for (int v = 0; v < 3; ++v) ptop[v][h] = real ? btp[(((size_t)2 * n + ic) * M + h) * 3 + v] : 1.0;
+  } else {
+    weights_init(j0 - 1);
+#pragma unroll
+    for (int h = 0; h < M; ++h)
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        double xr[XR];
+        xpass(v, j0 - 1, 2 + h, xr);
+        ptop[v][h] = point(v, 1, 3 * M + h, xr);
+      }
   }
   double acc[3] = {0.0, 0.0, 0.0};
 
   for (int j = j0; j <= j1; ++j) {
     const bool last = (j == j1);
-    double xl[3][M], xrr[3][M], yb[3][M], yt[3][M];
+    const int pc = j;
+    // the window of step j holds padded rows j .. j+2R; row j+2R was fetched
+    // during the previous step and replaces row j-1, no longer read
+    const bool have = !(last && j1 == n) && (j + 2 * R) < P;
+    __syncthreads();
+    if (have) store(j + 2 * R, nxt);
+    __syncthreads();
+    const bool want = (j + 1 < j1 || (j + 1 == j1 && j1 < n)) && (j + 2 * R + 1) < P;
+    if (want) fetch(j + 2 * R + 1, nxt);
+    double gb[3] = {0.0, 0.0, 0.0};
+    double fl[3] = {0.0, 0.0, 0.0};
     double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-      for (int h = 0; h < M; ++h) xl[v][h] = xrr[v][h] = yb[v][h] = yt[v][h] = 0.0;
     if (!last) {
-      if (can_rec) {
-        RC rc(qp + (size_t)(j + r) * P + (i + r), P, vs, t);
-        rc.init();
-        double xr[RC::XR];
-        // x-edges
+      weights_init(pc);
+      // x-edges: left trace (px = 0), right trace (px = 1), flux through the left edge
+      double xl[3][M], xrt[3][M];
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        double xr[XR];
+        xpass(v, pc, 0, xr);
+#pragma unroll
+        for (int h = 0; h < M; ++h) xl[v][h] = point(v, 2 + h, h, xr);
+        xpass(v, pc, 1, xr);
+#pragma unroll
+        for (int h = 0; h < M; ++h) xrt[v][h] = point(v, 2 + h, M + h, xr);
+      }
+#pragma unroll
+      for (int h = 0; h < M; ++h) {
+        double qL[3], qR[3];
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
-          rc.xpass(v, 0, xr);
-#pragma unroll
-          for (int h = 0; h < M; ++h) xl[v][h] = rc.point(v, 2 + h, h, xr);
-          rc.xpass(v, 1, xr);
-#pragma unroll
-          for (int h = 0; h < M; ++h) xrr[v][h] = rc.point(v, 2 + h, M + h, xr);
+          qL[v] = __shfl_up(xrt[v][h], 1, 64);
+          qR[v] = xl[v][h];
         }
-        // Gauss-node columns: y-edges and CQPs
+        if (i == 0) {
 #pragma unroll
-        for (int h = 0; h < M; ++h) {
-          double cq[3][M];
+          for (int v = 0; v < 3; ++v) qL[v] = btp[(((size_t)0 * n + j) * M + h) * 3 + v];
+        }
+        if (i == n) {
 #pragma unroll
-          for (int v = 0; v < 3; ++v) {
-            rc.xpass(v, 2 + h, xr);
-            yb[v][h] = rc.point(v, 0, 2 * M + h, xr);
-            yt[v][h] = rc.point(v, 1, 3 * M + h, xr);
+          for (int v = 0; v < 3; ++v) qR[v] = btp[(((size_t)1 * n + j) * M + h) * 3 + v];
+        }
+        if (!(in_strip && i >= 0 && i <= n && lane >= 1)) {
 #pragma unroll
-            for (int w = 0; w < M; ++w) cq[v][w] = rc.point(v, 2 + w, 4 * M + w * M + h, xr);
-          }
-          const double X = t.Xg[i * M + h];
+          for (int v = 0; v < 3; ++v) qL[v] = qR[v] = (v == 0) ? 1.0 : 0.0;
+        }
+        double F[3];
+        const double Y = t.Xg[j * M + h];
+        lmars_fast(qL, qR, Xei, Y, sqxe, t.sqg[j * M + h], 0, t.radius, ia, F);
 #pragma unroll
-          for (int w = 0; w < M; ++w) {
-            const double Y = t.Xg[j * M + w];
-            double a1, a2;
-            sources(cq[0][w], cq[1][w], cq[2][w], X, Y, Lx0 + LxX * X + LxY * Y, t.omega2, a1, a2);
-            const double gw = t.gw[h] * t.gw[w];
-            s1 = fma(gw, a1, s1);
-            s2 = fma(gw, a2, s2);
-          }
+        for (int v = 0; v < 3; ++v) fl[v] = fma(t.gw[h], F[v], fl[v]);
+      }
+      // Gauss-node columns: y-edge traces, y-flux through the bottom edge, CQP sources
+#pragma unroll
+      for (int h = 0; h < M; ++h) {
+        double yb[3], yt[3], cq[3][M];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          double xr[XR];
+          xpass(v, pc, 2 + h, xr);
+          yb[v] = point(v, 0, 2 * M + h, xr);
+          yt[v] = point(v, 1, 3 * M + h, xr);
+#pragma unroll
+          for (int w = 0; w < M; ++w) cq[v][w] = point(v, 2 + w, 4 * M + w * M + h, xr);
+        }
+        const double X = t.Xg[ic * M + h];
+        const double sqx = t.sqg[ic * M + h];
+        if (!real) {
+          yb[0] = ptop[0][h] = 1.0;
+          yb[1] = yb[2] = ptop[1][h] = ptop[2][h] = 0.0;
+#pragma unroll
+          for (int w = 0; w < M; ++w) { cq[0][w] = 1.0; cq[1][w] = cq[2][w] = 0.0; }
+        }
+        double qL[3] = {ptop[0][h], ptop[1][h], ptop[2][h]};
+        double F[3];
+        lmars_fast(qL, yb, X, t.Xe[j], sqx, t.sqe[j], 1, t.radius, ia, F);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) gb[v] = fma(t.gw[h], F[v], gb[v]);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) ptop[v][h] = yt[v];
+#pragma unroll
+        for (int w = 0; w < M; ++w) {
+          const double Y = t.Xg[j * M + w];
+          double a1, a2;
+          sources_fast(cq[0][w], cq[1][w], cq[2][w], X, Y, Lx0 + LxX * X + LxY * Y, t.omega2, a1, a2);
+          const double gw = t.gw[h] * t.gw[w];
+          s1 = fma(gw, a1, s1);
+          s2 = fma(gw, a2, s2);
         }
       }
     } else {
-      // epilogue: bottom traces of row j1 (the row above the segment)
-      if (i >= 0 && i < n && in_strip) {
-        if (j1 == n) {
+      // epilogue: bottom traces of row j1 and the flux through the top edge of row j1-1
+      double yb[3][M];
+      if (j1 == n) {
 #pragma unroll
-          for (int h = 0; h < M; ++h)
+        for (int h = 0; h < M; ++h)
 #pragma unroll
-            for (int v = 0; v < 3; ++v) yb[v][h] = btp[(((size_t)3 * n + i) * M + h) * 3 + v];
-        } else {
-          RC rc(qp + (size_t)(j1 + r) * P + (i + r), P, vs, t);
-          rc.init();
-          rc.side(2, yb);
-        }
+          for (int v = 0; v < 3; ++v) yb[v][h] = real ? btp[(((size_t)3 * n + ic) * M + h) * 3 + v] : (v ? 0.0 : 1.0);
+      } else {
+        weights_init(pc);
+#pragma unroll
+        for (int h = 0; h < M; ++h)
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            double xr[XR];
+            xpass(v, pc, 2 + h, xr);
+            yb[v][h] = point(v, 0, 2 * M + h, xr);
+          }
       }
-    }
-    // ---- y-flux through the bottom edge of (i, j) ------------------------
-    double gb[3] = {0.0, 0.0, 0.0};
-    if (i >= 0 && i < n && in_strip) {
-      const double Ye = t.Xe[j];
 #pragma unroll
       for (int h = 0; h < M; ++h) {
         double qL[3] = {ptop[0][h], ptop[1][h], ptop[2][h]};
         double qR[3] = {yb[0][h], yb[1][h], yb[2][h]};
+        if (!real) {
+          qL[0] = qR[0] = 1.0;
+          qL[1] = qL[2] = qR[1] = qR[2] = 0.0;
+        }
         double F[3];
-        lmars(qL, qR, t.Xg[i * M + h], Ye, 1, t.radius, F);
+        lmars_fast(qL, qR, t.Xg[ic * M + h], t.Xe[j], t.sqg[ic * M + h], t.sqe[j], 1, t.radius, ia, F);
 #pragma unroll
         for (int v = 0; v < 3; ++v) gb[v] = fma(t.gw[h], F[v], gb[v]);
       }
     }
-    // ---- finalize row j-1 -------------------------------------------------
+    // ---- finalize row j-1 ---------------------------------------------------
     if (j > j0 && owner) {
       const int jr = j - 1;
-      const size_t c_in = (size_t)(jr + r) * P + (i + r);
+      const size_t c_in = (size_t)(jr + R) * P + (i + R);
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
-        const double dq = acc[v] - gb[v] * invd;
+        const double dq = fma(-gb[v], invd, acc[v]);
         const size_t o_in = v * vs + p * plane + c_in;
         double val = A.cc * dq;
         if (A.cb != 0.0) val = fma(A.cb, A.q[o_in], val);
@@ -426,45 +717,12 @@ __global__ __launch_bounds__(64) void k_stage(DevTables t, StageArgs A) {
       }
     }
     if (last) break;
-    // ---- x-flux through the left edge of each lane ------------------------
-    double fl[3] = {0.0, 0.0, 0.0};
-    {
-      const double Xe = t.Xe[max(0, min(n, i))];
-#pragma unroll
-      for (int h = 0; h < M; ++h) {
-        double qL[3], qR[3];
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          qL[v] = __shfl_up(xrr[v][h], 1, 64);
-          qR[v] = xl[v][h];
-        }
-        if (i == 0) {
-#pragma unroll
-          for (int v = 0; v < 3; ++v) qL[v] = btp[(((size_t)0 * n + j) * M + h) * 3 + v];
-        }
-        if (i == n && in_strip) {
-#pragma unroll
-          for (int v = 0; v < 3; ++v) qR[v] = btp[(((size_t)1 * n + j) * M + h) * 3 + v];
-        }
-        if (in_strip && i >= 0 && i <= n && lane >= 1) {
-          double F[3];
-          lmars(qL, qR, Xe, t.Xg[j * M + h], 0, t.radius, F);
-#pragma unroll
-          for (int v = 0; v < 3; ++v) fl[v] = fma(t.gw[h], F[v], fl[v]);
-        }
-      }
-    }
     double fr[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) fr[v] = __shfl_down(fl[v], 1, 64);
-    // ---- partial tendency of row j ------------------------------------------
-    acc[0] = -(fr[0] - fl[0]) * invd + gb[0] * invd;
-    acc[1] = -(fr[1] - fl[1]) * invd + gb[1] * invd + s1;
-    acc[2] = -(fr[2] - fl[2]) * invd + gb[2] * invd + s2;
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-      for (int h = 0; h < M; ++h) ptop[v][h] = yt[v][h];
+    acc[0] = (fl[0] - fr[0] + gb[0]) * invd;
+    acc[1] = fma(fl[1] - fr[1] + gb[1], invd, s1);
+    acc[2] = fma(fl[2] - fr[2] + gb[2], invd, s2);
   }
 }
 
