@@ -26,7 +26,9 @@ int hip_fail(hipError_t e, const char* what) {
 
 struct hope_grid {
   HostTables h;
-  DevTables d{};
+  const double* tab = nullptr;     // all constant tables, see tab_offsets
+  const int32_t* itab = nullptr;   // panel-edge map
+  GridScalars gs{};
   GhostDev g{};
   std::vector<void*> allocs;
   double* bt = nullptr;      // panel-edge trace scratch, 24*n*m*3
@@ -149,39 +151,45 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
     return fail(st, msg);
   }
   HostTables& h = G->h;
-  DevTables& d = G->d;
-#define UP(field, src)                         \
-  do {                                         \
-    int e_ = upload(G, src, &d.field);         \
-    if (e_) { free_grid(G); return e_; }       \
-  } while (0)
-  UP(wc, h.wc);
-  UP(wsub, h.wsub);
-  UP(gp, h.gp);
-  UP(gm, h.gm);
-  UP(sp, h.sp);
-  UP(sm, h.sm);
-  UP(V, h.V);
-  UP(lam, h.lam);
-  UP(Xe, h.Xe);
-  UP(Xg, h.Xg);
-  UP(sqe, h.sqe);
-  UP(sqg, h.sqg);
-  UP(gw, h.gw);
-  UP(fcoef, h.fcoef);
-  UP(bt_cell, h.bt_cell);
-  UP(bt_side, h.bt_side);
-  UP(bt_rev, h.bt_rev);
-  UP(bt_conv, h.bt_conv);
-#undef UP
-  d.radius = h.radius;
-  d.omega2 = 2.0 * h.omega;
-  d.eps = h.eps;
-  d.inv_delta = 1.0 / h.delta;
-  d.n = h.n;
-  d.P = h.P;
-  d.r = h.r;
-  d.m = h.m;
+  {
+    // pack the constant tables into one buffer (layout of tab_offsets)
+    const TabOffsets O = tab_offsets(h.k, h.weno != 0, h.m, h.n);
+    std::vector<double> tab(O.total, 0.0);
+    auto put = [&](int64_t off, const std::vector<double>& v) { std::copy(v.begin(), v.end(), tab.begin() + off); };
+    put(O.wc, h.wc);
+    if (h.weno) {
+      put(O.wsub, h.wsub);
+      put(O.gp, h.gp);
+      put(O.gm, h.gm);
+      put(O.sp, h.sp);
+      put(O.sm, h.sm);
+      put(O.V, h.V);
+      put(O.lam, h.lam);
+    }
+    put(O.gw, h.gw);
+    put(O.fcoef, h.fcoef);
+    put(O.Xe, h.Xe);
+    put(O.sqe, h.sqe);
+    put(O.Xg, h.Xg);
+    put(O.sqg, h.sqg);
+    put(O.bt_conv, h.bt_conv);
+    std::vector<int32_t> itab(O.i_total, 0);
+    std::copy(h.bt_cell.begin(), h.bt_cell.end(), itab.begin() + O.i_cell);
+    std::copy(h.bt_side.begin(), h.bt_side.end(), itab.begin() + O.i_side);
+    std::copy(h.bt_rev.begin(), h.bt_rev.end(), itab.begin() + O.i_rev);
+    int e0 = upload(G, tab, &G->tab);
+    if (!e0) e0 = upload(G, itab, &G->itab);
+    if (e0) { free_grid(G); return e0; }
+  }
+  GridScalars& gsc = G->gs;
+  gsc.radius = h.radius;
+  gsc.omega2 = 2.0 * h.omega;
+  gsc.eps = h.eps;
+  gsc.inv_delta = 1.0 / h.delta;
+  gsc.n = h.n;
+  gsc.P = h.P;
+  gsc.r = h.r;
+  gsc.m = h.m;
   GhostDev& g = G->g;
   int e1 = upload(G, h.g_dst, &g.dst);
   if (!e1) e1 = upload(G, h.g_ptr, &g.ptr);
@@ -242,13 +250,13 @@ static int run_stage(const hope_grid* G, double* q, const double* qn, double* ou
   if (e) return hip_fail((hipError_t)e, "fill_halo launch");
   {
     Timed tm(G, 1, stream);
-    e = launch_edge_traces(G->h.k, G->h.weno, G->d, q, G->bt, stream);
+    e = launch_edge_traces(G->h.k, G->h.weno, G->tab, G->itab, G->gs, q, G->bt, stream);
   }
   if (e) return hip_fail((hipError_t)e, "edge_traces launch");
   {
     Timed tm(G, 2, stream);
-    e = launch_stage(G->h.k, G->h.weno, G->d, q, qn, out, out_padded, ca, cb, cc, G->bt, G->strip_w, G->seg_h,
-                     stream);
+    e = launch_stage(G->h.k, G->h.weno, G->tab, G->itab, G->gs, q, qn, out, out_padded, ca, cb, cc, G->bt,
+                     G->strip_w, G->seg_h, stream);
   }
   if (e) return hip_fail((hipError_t)e, "stage launch");
   return HOPE_OK;

@@ -50,27 +50,52 @@ int build_tables(HostTables& t, int n, int k, int weno, double radius, double om
                  double eps, double theta);
 
 // ---------------------------------------------------------------------------
-// Device-side view of the constant tables (passed by value to kernels)
+// All constant tables of a grid live in one FP64 buffer (and one int32
+// buffer for the panel-edge map), so that a kernel carries one base pointer.
+// Section offsets (in elements) depend on (order, scheme, n_gauss) for the
+// fixed part and on n for the rest.
 // ---------------------------------------------------------------------------
-struct DevTables {
-  const double* wc;
-  const double* wsub;
-  const double* gp;
-  const double* gm;
-  const double* sp;
-  const double* sm;
-  const double* V;
-  const double* lam;
-  const double* Xe;
-  const double* Xg;
-  const double* sqe;
-  const double* sqg;
-  const double* gw;
-  const double* fcoef;
-  const int32_t* bt_cell;
-  const int32_t* bt_side;
-  const int32_t* bt_rev;
-  const double* bt_conv;
+#if defined(__HIPCC__) || defined(__HIP__)
+#define HOPE_HD __host__ __device__
+#else
+#define HOPE_HD
+#endif
+
+struct TabOffsets {
+  int64_t wc, wsub, gp, gm, sp, sm, V, lam, gw, fcoef, fixed;
+  int64_t Xe, sqe, Xg, sqg, bt_conv, total;
+  int64_t i_cell, i_side, i_rev, i_total;
+};
+
+HOPE_HD constexpr TabOffsets tab_offsets(int k, bool weno, int m, int n) {
+  const int NA = 2 + m, NP = 4 * m + m * m, L = (k + 1) / 2, S = L * L;
+  TabOffsets o{};
+  o.wc = 0;
+  o.wsub = o.wc + NA * k;
+  o.gp = o.wsub + (weno ? L * NA * L : 0);
+  o.gm = o.gp + (weno ? NP * S : 0);
+  o.sp = o.gm + (weno ? NP * S : 0);
+  o.sm = o.sp + (weno ? NP : 0);
+  o.V = o.sm + (weno ? NP : 0);
+  o.lam = o.V + (weno ? L * L * L : 0);
+  o.gw = o.lam + (weno ? L * L : 0);
+  o.fcoef = o.gw + m;
+  o.fixed = o.fcoef + 18;
+  o.Xe = o.fixed;
+  o.sqe = o.Xe + (n + 1);
+  o.Xg = o.sqe + (n + 1);
+  o.sqg = o.Xg + (int64_t)n * m;
+  o.bt_conv = o.sqg + (int64_t)n * m;
+  o.total = o.bt_conv + 24LL * n * m * 5;
+  o.i_cell = 0;
+  o.i_side = 24LL * n;
+  o.i_rev = 48LL * n;
+  o.i_total = 72LL * n;
+  return o;
+}
+
+// Scalars every kernel needs.
+struct GridScalars {
   double radius, omega2, eps, inv_delta;
   int n, P, r, m;
 };
@@ -87,9 +112,10 @@ struct GhostDev {
 // Launchers implemented in kernels.hip.  All enqueue on `stream` and return a
 // hipError_t value (0 on success).
 int launch_fill_halo(const GhostDev& g, double* q, int plane, void* stream);
-int launch_edge_traces(int k, int weno, const DevTables& t, const double* q, double* bt, void* stream);
-int launch_stage(int k, int weno, const DevTables& t, const double* q, const double* qn, double* out,
-                 int out_padded, double ca, double cb, double cc, const double* bt, int strip_w,
-                 int seg_h, void* stream);
+int launch_edge_traces(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs,
+                       const double* q, double* bt, void* stream);
+int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs,
+                 const double* q, const double* qn, double* out, int out_padded, double ca, double cb, double cc,
+                 const double* bt, int strip_w, int seg_h, void* stream);
 
 }  // namespace hope

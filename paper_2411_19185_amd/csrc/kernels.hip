@@ -10,35 +10,23 @@
 //
 // k_stage marches: one wavefront owns a strip of up to 62 interior columns of
 // one panel (lanes 1..62; lanes 0 and 63 are the strip's ring columns) and a
-// segment of rows, walking up the rows.  At each row every lane reconstructs
-// its cell; the flux through the left edge of lane L takes the left state
-// from lane L-1 by a cross-lane shuffle, and the flux through the bottom edge
-// takes the top trace of the row below, which the lane kept in registers from
-// the previous step.  No trace ever goes to memory.
+// segment of rows, walking up the rows.  The 2r+1 stencil rows of the strip
+// sit in an LDS ring buffer (one new row per step, fetched a step ahead).  At
+// each row every lane reconstructs its cell; the flux through the left edge of
+// lane L takes the left state from lane L-1 by a cross-lane shuffle, and the
+// flux through the bottom edge takes the top trace of the row below, kept from
+// the previous step.  No trace goes to HBM.
+//
+// The grid's constant tables are one buffer read through the constant address
+// space: with uniform addresses those reads are scalar loads into SGPRs.
 #include <hip/hip_runtime.h>
 
 #include "hope_internal.hpp"
 
 namespace hope {
 
-// Constant-address-space view of the grid tables: the tables never change
-// while a kernel runs, and loads through this address space with uniform
-// addresses become scalar loads into SGPRs instead of per-lane vector loads.
 typedef const __attribute__((address_space(4))) double* cdp;
 typedef const __attribute__((address_space(4))) int32_t* cip;
-
-struct CTab {
-  cdp wc, wsub, gp, gm, sp, sm, V, lam, Xe, Xg, sqe, sqg, gw, fcoef, bt_conv;
-  cip bt_cell, bt_side, bt_rev;
-  double radius, omega2, eps, inv_delta;
-  int n, P, r, m;
-  __device__ explicit CTab(const DevTables& d)
-      : wc((cdp)d.wc), wsub((cdp)d.wsub), gp((cdp)d.gp), gm((cdp)d.gm), sp((cdp)d.sp), sm((cdp)d.sm),
-        V((cdp)d.V), lam((cdp)d.lam), Xe((cdp)d.Xe), Xg((cdp)d.Xg), sqe((cdp)d.sqe), sqg((cdp)d.sqg),
-        gw((cdp)d.gw), fcoef((cdp)d.fcoef), bt_conv((cdp)d.bt_conv), bt_cell((cip)d.bt_cell),
-        bt_side((cip)d.bt_side), bt_rev((cip)d.bt_rev), radius(d.radius), omega2(d.omega2), eps(d.eps),
-        inv_delta(d.inv_delta), n(d.n), P(d.P), r(d.r), m(d.m) {}
-};
 
 // ---------------------------------------------------------------------------
 // Ghost fill
@@ -73,239 +61,8 @@ __global__ __launch_bounds__(256) void k_fill_halo(GhostDev g, double* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Reconstruction of one cell.  Axis coordinates: 0 -> -1/2, 1 -> +1/2,
-// 2+h -> Gauss node h.  Point numbering of one cell: x-edge left (h),
-// x-edge right (h), y-edge bottom (h), y-edge top (h), CQP (v outer, h inner).
+// Arithmetic helpers
 // ---------------------------------------------------------------------------
-template <int K, bool W, int M>
-struct Recon {
-  static constexpr int R = (K - 1) / 2;
-  static constexpr int L = (K + 1) / 2;     // sub-stencil width (WENO)
-  static constexpr int S = L * L;
-  static constexpr int NA = 2 + M;
-
-  const double* __restrict__ c0;   // var-0 value of the cell
-  int P;
-  size_t vs;                       // distance between variables
-  const CTab t;
-  double kap[W ? 3 : 1][W ? S : 1];
-
-  __device__ Recon(const double* c, int P_, size_t vs_, const CTab& t_) : c0(c), P(P_), vs(vs_), t(t_) {}
-
-  __device__ __forceinline__ double at(int v, int dy, int dx) const { return c0[v * vs + dy * P + dx]; }
-
-  // WENO: smoothness indicators, tau (3.24) and kappa_j = 1 + tau/(beta_j + eps) (3.23)
-  __device__ void init() {
-    if constexpr (W) {
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        double beta[S];
-#pragma unroll
-        for (int sx = 0; sx < L; ++sx) {
-          double tr[2 * R + 1][L];
-#pragma unroll
-          for (int row = 0; row < 2 * R + 1; ++row)
-#pragma unroll
-            for (int al = 0; al < L; ++al) {
-              double s = 0;
-#pragma unroll
-              for (int a = 0; a < L; ++a) s = fma(t.V[(sx * L + al) * L + a], at(v, row - R, sx - (L - 1) + a), s);
-              tr[row][al] = s;
-            }
-#pragma unroll
-          for (int sy = 0; sy < L; ++sy) {
-            double b = 0;
-#pragma unroll
-            for (int be = 0; be < L; ++be)
-#pragma unroll
-              for (int al = 0; al < L; ++al) {
-                if (al == 0 && be == 0) continue;
-                double c = 0;
-#pragma unroll
-                for (int bb = 0; bb < L; ++bb) c = fma(t.V[(sy * L + be) * L + bb], tr[sy + bb][al], c);
-                b = fma(t.lam[be * L + al] * c, c, b);
-              }
-            beta[sy * L + sx] = b;
-          }
-        }
-        double tau = 0;
-#pragma unroll
-        for (int i = 0; i < S; ++i)
-#pragma unroll
-          for (int j = i + 1; j < S; ++j) tau += fabs(beta[i] - beta[j]);
-        tau *= 2.0 / (S * (S + 1));
-#pragma unroll
-        for (int j = 0; j < S; ++j) kap[v][j] = 1.0 + tau / (beta[j] + t.eps);
-      }
-    }
-  }
-
-  // x-pass at axis px: TPP: xr[row] (2R+1 values); WENO: xr[sx][row] (L x (2R+1))
-  __device__ __forceinline__ void xpass(int v, int px, double* xr) const {
-    if constexpr (!W) {
-#pragma unroll
-      for (int row = 0; row < 2 * R + 1; ++row) {
-        double s = 0;
-#pragma unroll
-        for (int a = 0; a < K; ++a) s = fma(t.wc[px * K + a], at(v, row - R, a - R), s);
-        xr[row] = s;
-      }
-    } else {
-#pragma unroll
-      for (int sx = 0; sx < L; ++sx)
-#pragma unroll
-        for (int row = 0; row < 2 * R + 1; ++row) {
-          double s = 0;
-#pragma unroll
-          for (int a = 0; a < L; ++a)
-            s = fma(t.wsub[(sx * NA + px) * L + a], at(v, row - R, sx - (L - 1) + a), s);
-          xr[sx * (2 * R + 1) + row] = s;
-        }
-    }
-  }
-
-  // value at (px, py) from the x-pass; pt = point number (for WENO weights)
-  __device__ __forceinline__ double point(int v, int py, int pt, const double* xr) const {
-    if constexpr (!W) {
-      double s = 0;
-#pragma unroll
-      for (int b = 0; b < K; ++b) s = fma(t.wc[py * K + b], xr[b], s);
-      return s;
-    } else {
-      double ap = 0, dp = 0, am = 0, dm = 0;
-#pragma unroll
-      for (int sy = 0; sy < L; ++sy)
-#pragma unroll
-        for (int sx = 0; sx < L; ++sx) {
-          double p = 0;
-#pragma unroll
-          for (int b = 0; b < L; ++b) p = fma(t.wsub[(sy * NA + py) * L + b], xr[sx * (2 * R + 1) + sy + b], p);
-          const int j = sy * L + sx;
-          const double kp = kap[v][j];
-          const double gpk = t.gp[pt * S + j] * kp, gmk = t.gm[pt * S + j] * kp;
-          ap = fma(gpk, p, ap);
-          dp += gpk;
-          am = fma(gmk, p, am);
-          dm += gmk;
-        }
-      // sigma+ sum w+ p - sigma- sum w- p, w = alpha / sum alpha
-      return (t.sp[pt] * ap * dm - t.sm[pt] * am * dp) / (dp * dm);
-    }
-  }
-
-  static constexpr int XR = W ? L * (2 * R + 1) : (2 * R + 1);
-
-  // all m values of one side of the cell (0 left, 1 right, 2 bottom, 3 top), 3 vars
-  __device__ void side(int sd, double out[3][M]) const {
-    double xr[XR];
-    if (sd < 2) {
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        xpass(v, sd, xr);
-#pragma unroll
-        for (int h = 0; h < M; ++h) out[v][h] = point(v, 2 + h, sd * M + h, xr);
-      }
-    } else {
-#pragma unroll
-      for (int h = 0; h < M; ++h)
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          xpass(v, 2 + h, xr);
-          out[v][h] = point(v, sd - 2, (sd == 2 ? 2 * M : 3 * M) + h, xr);
-        }
-    }
-  }
-};
-
-// ---------------------------------------------------------------------------
-// LMARS flux (3.30)-(3.38) with upwind term |m|(q_R - q_L); dir 0 = x, 1 = y
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void lmars(const double* qL, const double* qR, double X, double Y, int dir,
-                                      double a, double* F) {
-  const double X2 = X * X, Y2 = Y * Y;
-  const double ox = 1.0 + X2, oy = 1.0 + Y2;
-  const double d2 = ox + Y2;
-  const double dl = sqrt(d2);
-  const double idl = 1.0 / dl;
-  const double sg = a * a * ox * oy * idl * idl * idl;             // (2.8)
-  const double isg = 1.0 / sg;
-  const double sgii = dl / (a * sqrt(dir == 0 ? ox : oy));         // sqrt(G^ii)
-  const int iv = 1 + dir;
-  const double phiL = qL[0] * isg, phiR = qR[0] * isg;
-  const double upL = qL[iv] / (qL[0] * sgii);                      // (3.31)
-  const double upR = qR[iv] / (qR[0] * sgii);
-  const double c = 0.5 * (sqrt(phiL) + sqrt(phiR));                // (3.34)-(3.35)
-  const double ms = 0.5 * (upL + upR - (phiR - phiL) / c);         // (3.32)
-  const double ps = 0.5 * (phiL + phiR - c * (upR - upL));         // (3.33)
-  const double mm = ms * sgii;                                     // (3.36)
-  const double am = fabs(mm);
-#pragma unroll
-  for (int v = 0; v < 3; ++v) F[v] = 0.5 * (mm * (qL[v] + qR[v]) - am * (qR[v] - qL[v]));   // (3.37)
-  const double pr = 0.5 * ps * ps * idl;                           // (3.38): sqrtG G^ij = (..)/delta
-  if (dir == 0) {
-    F[1] += pr * oy;
-    F[2] += pr * X * Y;
-  } else {
-    F[1] += pr * X * Y;
-    F[2] += pr * ox;
-  }
-}
-
-// Metric (2.2) and Coriolis (2.3) sources at one point; L = c0 + cX X + cY Y
-// so that f*delta = 2 Omega L.
-__device__ __forceinline__ void sources(double Q0, double Q1, double Q2, double X, double Y, double Lc,
-                                        double omega2, double& s1, double& s2) {
-  const double X2 = X * X, Y2 = Y * Y;
-  const double id2 = 1.0 / (1.0 + X2 + Y2);
-  const double iq = 2.0 / Q0;
-  const double m1 = iq * (-X * Y2 * Q1 * Q1 + Y * (1.0 + Y2) * Q1 * Q2);
-  const double m2 = iq * (X * (1.0 + X2) * Q1 * Q2 - X2 * Y * Q2 * Q2);
-  const double f = omega2 * Lc;
-  const double c1 = f * (-X * Y * Q1 + (1.0 + Y2) * Q2);
-  const double c2 = f * (-(1.0 + X2) * Q1 + X * Y * Q2);
-  s1 = (m1 + c1) * id2;
-  s2 = (m2 + c2) * id2;
-}
-
-// ---------------------------------------------------------------------------
-// Panel-edge traces: bt[((A*4+side)*n + t)*m + h][var], in A's variables
-// ---------------------------------------------------------------------------
-template <int K, bool W, int M>
-__global__ __launch_bounds__(64) void k_edge_traces(DevTables td, const double* __restrict__ q,
-                                                     double* __restrict__ bt) {
-  const CTab t(td);
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 24 * t.n) return;
-  const size_t vs = (size_t)6 * t.P * t.P;
-  Recon<K, W, M> rc(q + t.bt_cell[idx], t.P, vs, t);
-  rc.init();
-  double vals[3][M];
-  rc.side(t.bt_side[idx], vals);
-  const int rev = t.bt_rev[idx];
-#pragma unroll
-  for (int h = 0; h < M; ++h) {
-    const int hb = rev ? M - 1 - h : h;
-    cdp cv = t.bt_conv + ((size_t)idx * M + h) * 5;
-    double* o = bt + ((size_t)idx * M + h) * 3;
-    o[0] = cv[0] * vals[0][hb];
-    o[1] = cv[1] * vals[1][hb] + cv[2] * vals[2][hb];
-    o[2] = cv[3] * vals[1][hb] + cv[4] * vals[2][hb];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Fused stage kernel
-// ---------------------------------------------------------------------------
-struct StageArgs {
-  const double* q;
-  const double* qn;
-  double* out;
-  const double* bt;
-  double ca, cb, cc;
-  int out_padded;
-  int strip_w, seg_h, n_strips, n_segs;
-};
-
 // reciprocal: hardware estimate refined by two Newton-Raphson steps
 __device__ __forceinline__ double rcp(double x) {
   double y = __builtin_amdgcn_rcp(x);
@@ -329,21 +86,20 @@ __device__ __forceinline__ double sqrt_g(double x) {
   return fma(d, h, g);
 }
 
-// LMARS with the fast reciprocal/root; X-direction (dir 0) or y (dir 1).
-// sqx = sqrt(1 + X^2), sqy = sqrt(1 + Y^2) come from tables.
-__device__ __forceinline__ void lmars_fast(const double* qL, const double* qR, double X, double Y, double sqx,
-                                           double sqy, int dir, double a, double ia, double* F) {
+// LMARS flux (3.30)-(3.38) with upwind term |m|(q_R - q_L); dir 0 = x, 1 = y.
+// sqx = sqrt(1 + X^2), sqy = sqrt(1 + Y^2) come from tables, ia = 1/a.
+__device__ __forceinline__ void lmars(const double* qL, const double* qR, double X, double Y, double sqx,
+                                      double sqy, int dir, double ia, double* F) {
   const double ox = sqx * sqx, oy = sqy * sqy;
   const double d2 = fma(X, X, oy);
   const double dl = sqrt_g(d2);
   const double idl = rcp(dl);
-  // 1/sqrtG = delta^3 / (a^2 (1+X^2)(1+Y^2))
-  const double isg = d2 * dl * ia * ia * rcp(ox * oy);
-  const double sgii = dl * ia * rcp(dir == 0 ? sqx : sqy);      // sqrt(G^ii)
+  const double isg = d2 * dl * ia * ia * rcp(ox * oy);            // 1/sqrtG, (2.8)
+  const double sgii = dl * ia * rcp(dir == 0 ? sqx : sqy);        // sqrt(G^ii), (2.6)
   const int iv = 1 + dir;
   const double phiL = qL[0] * isg, phiR = qR[0] * isg;
-  const double iL = rcp(qL[0] * sgii), iR = rcp(qR[0] * sgii);
-  const double upL = qL[iv] * iL, upR = qR[iv] * iR;              // (3.31)
+  const double upL = qL[iv] * rcp(qL[0] * sgii);                   // (3.31)
+  const double upR = qR[iv] * rcp(qR[0] * sgii);
   const double c = 0.5 * (sqrt_g(phiL) + sqrt_g(phiR));           // (3.34)-(3.35)
   const double ms = 0.5 * (upL + upR - (phiR - phiL) * rcp(c));   // (3.32)
   const double ps = 0.5 * (phiL + phiR - c * (upR - upL));        // (3.33)
@@ -351,7 +107,7 @@ __device__ __forceinline__ void lmars_fast(const double* qL, const double* qR, d
   const double am = fabs(mm);
 #pragma unroll
   for (int v = 0; v < 3; ++v) F[v] = 0.5 * (mm * (qL[v] + qR[v]) - am * (qR[v] - qL[v]));   // (3.37)
-  const double pr = 0.5 * ps * ps * idl;                          // (3.38)
+  const double pr = 0.5 * ps * ps * idl;                          // (3.38): sqrtG G^ij = (..)/delta
   if (dir == 0) {
     F[1] = fma(pr, oy, F[1]);
     F[2] = fma(pr, X * Y, F[2]);
@@ -361,8 +117,10 @@ __device__ __forceinline__ void lmars_fast(const double* qL, const double* qR, d
   }
 }
 
-__device__ __forceinline__ void sources_fast(double Q0, double Q1, double Q2, double X, double Y, double Lc,
-                                             double omega2, double& s1, double& s2) {
+// Metric (2.2) and Coriolis (2.3) sources at one point; Lc = c0 + cX X + cY Y
+// so that f*delta = 2 Omega Lc.
+__device__ __forceinline__ void sources(double Q0, double Q1, double Q2, double X, double Y, double Lc,
+                                        double omega2, double& s1, double& s2) {
   const double X2 = X * X, Y2 = Y * Y;
   const double id2 = rcp(1.0 + X2 + Y2);
   const double iq = 2.0 * rcp(Q0);
@@ -375,30 +133,212 @@ __device__ __forceinline__ void sources_fast(double Q0, double Q1, double Q2, do
   s2 = (m2 + c2) * id2;
 }
 
-// Stencil window in LDS: NR = 2R+1 padded rows of CW = 64 + 2R columns of a
-// strip, 3 variables; LDS column c holds padded column i0 - 1 + c.
+// ---------------------------------------------------------------------------
+// Reconstruction of one cell from a stencil accessor at(dy, dx).  Axis
+// coordinates: 0 -> -1/2, 1 -> +1/2, 2+h -> Gauss node h.  Point numbering of
+// one cell: x-edge left (h), x-edge right (h), y-edge bottom (h), y-edge top
+// (h), CQP (v outer, h inner).
+// ---------------------------------------------------------------------------
 template <int K, bool W, int M>
-struct Window {
+struct Cfg {
   static constexpr int R = (K - 1) / 2;
-  static constexpr int L = (K + 1) / 2;
+  static constexpr int L = (K + 1) / 2;     // sub-stencil width (WENO)
   static constexpr int S = L * L;
   static constexpr int NA = 2 + M;
   static constexpr int NR = 2 * R + 1;
-  static constexpr int CW = 64 + 2 * R;
+  static constexpr int XR = W ? L * NR : NR;
+  static constexpr TabOffsets O = tab_offsets(K, W, M, 0);
 };
 
+// smoothness indicators -> kappa_j = 1 + tau/(beta_j + eps) of one variable,
+// (3.23)-(3.25); out(j, kappa_j)
+template <int K, bool W, int M, typename TP, typename At, typename Out>
+__device__ __forceinline__ void weno_kappa(TP tab, double eps, At at, Out out) {
+  using C = Cfg<K, W, M>;
+  constexpr int L = C::L, S = C::S, NR = C::NR, R = C::R;
+  TP V = tab + C::O.V, lam = tab + C::O.lam;
+  double beta[S];
+#pragma unroll
+  for (int sx = 0; sx < L; ++sx) {
+    double tr[NR][L];
+#pragma unroll
+    for (int row = 0; row < NR; ++row)
+#pragma unroll
+      for (int al = 0; al < L; ++al) {
+        double s = 0;
+#pragma unroll
+        for (int a = 0; a < L; ++a) s = fma(V[(sx * L + al) * L + a], at(row - R, sx - (L - 1) + a), s);
+        tr[row][al] = s;
+      }
+#pragma unroll
+    for (int sy = 0; sy < L; ++sy) {
+      double b = 0;
+#pragma unroll
+      for (int be = 0; be < L; ++be)
+#pragma unroll
+        for (int al = 0; al < L; ++al) {
+          if (al == 0 && be == 0) continue;
+          double c = 0;
+#pragma unroll
+          for (int bb = 0; bb < L; ++bb) c = fma(V[(sy * L + be) * L + bb], tr[sy + bb][al], c);
+          b = fma(lam[be * L + al] * c, c, b);
+        }
+      beta[sy * L + sx] = b;
+    }
+  }
+  double tau = 0;
+#pragma unroll
+  for (int a = 0; a < S; ++a)
+#pragma unroll
+    for (int b = a + 1; b < S; ++b) tau += fabs(beta[a] - beta[b]);
+  tau *= 2.0 / (S * (S + 1));
+#pragma unroll
+  for (int j = 0; j < S; ++j) out(j, fma(tau, rcp(beta[j] + eps), 1.0));
+}
+
+// x-pass at axis px: TPP: xr[row]; WENO: xr[sx*NR + row]
+template <int K, bool W, int M, typename TP, typename At>
+__device__ __forceinline__ void xpass(TP tab, int px, At at, double* xr) {
+  using C = Cfg<K, W, M>;
+  constexpr int L = C::L, NR = C::NR, R = C::R, NA = C::NA;
+  if constexpr (!W) {
+    TP wc = tab + C::O.wc;
+#pragma unroll
+    for (int row = 0; row < NR; ++row) {
+      double s = 0;
+#pragma unroll
+      for (int a = 0; a < K; ++a) s = fma(wc[px * K + a], at(row - R, a - R), s);
+      xr[row] = s;
+    }
+  } else {
+    TP wsub = tab + C::O.wsub;
+#pragma unroll
+    for (int sx = 0; sx < L; ++sx)
+#pragma unroll
+      for (int row = 0; row < NR; ++row) {
+        double s = 0;
+#pragma unroll
+        for (int a = 0; a < L; ++a) s = fma(wsub[(sx * NA + px) * L + a], at(row - R, sx - (L - 1) + a), s);
+        xr[sx * NR + row] = s;
+      }
+  }
+}
+
+// value at axis py from the x-pass; pt = point number; kap(j) gives kappa_j
+template <int K, bool W, int M, typename TP, typename Kap>
+__device__ __forceinline__ double point(TP tab, int py, int pt, const double* xr, Kap kap) {
+  using C = Cfg<K, W, M>;
+  constexpr int L = C::L, S = C::S, NR = C::NR, NA = C::NA;
+  if constexpr (!W) {
+    TP wc = tab + C::O.wc;
+    double s = 0;
+#pragma unroll
+    for (int b = 0; b < K; ++b) s = fma(wc[py * K + b], xr[b], s);
+    return s;
+  } else {
+    TP wsub = tab + C::O.wsub, gp = tab + C::O.gp, gm = tab + C::O.gm;
+    double ap = 0, dp = 0, am = 0, dm = 0;
+#pragma unroll
+    for (int sy = 0; sy < L; ++sy)
+#pragma unroll
+      for (int sx = 0; sx < L; ++sx) {
+        double pv = 0;
+#pragma unroll
+        for (int b = 0; b < L; ++b) pv = fma(wsub[(sy * NA + py) * L + b], xr[sx * NR + sy + b], pv);
+        const int j = sy * L + sx;
+        const double kj = kap(j);
+        const double tk = kj * pv;
+        ap = fma(gp[pt * S + j], tk, ap);
+        am = fma(gm[pt * S + j], tk, am);
+        dp = fma(gp[pt * S + j], kj, dp);
+        dm = fma(gm[pt * S + j], kj, dm);
+      }
+    // (3.20)-(3.22): sigma+ sum w+ p - sigma- sum w- p, w = alpha / sum alpha
+    return (tab[C::O.sp + pt] * ap * dm - tab[C::O.sm + pt] * am * dp) * rcp(dp * dm);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Panel-edge traces: bt[((A*4+side)*n + t)*m + h][var], in A's variables
+// ---------------------------------------------------------------------------
 template <int K, bool W, int M>
+__global__ __launch_bounds__(64) void k_edge_traces(const double* __restrict__ tab_, const int32_t* __restrict__ itab_,
+                                                     GridScalars gs, const double* __restrict__ q,
+                                                     double* __restrict__ bt) {
+  using C = Cfg<K, W, M>;
+  const cdp tab = (cdp)tab_;
+  const cip itab = (cip)itab_;
+  const int n = gs.n, P = gs.P;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 24 * n) return;
+  const TabOffsets O = tab_offsets(K, W, M, n);
+  const size_t vs = (size_t)6 * P * P;
+  const double* c0 = q + itab[O.i_cell + idx];
+  const int sd = itab[O.i_side + idx];
+  const int rev = itab[O.i_rev + idx];
+  double vals[3][M];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    auto at = [&](int dy, int dx) -> double { return c0[v * vs + dy * P + dx]; };
+    double kap[W ? C::S : 1];
+    if constexpr (W) weno_kappa<K, W, M>(tab, gs.eps, at, [&](int j, double x) { kap[j] = x; });
+    auto kf = [&](int j) -> double { return kap[j]; };
+    double xr[C::XR];
+    if (sd < 2) {
+      xpass<K, W, M>(tab, sd, at, xr);
+#pragma unroll
+      for (int h = 0; h < M; ++h) vals[v][h] = point<K, W, M>(tab, 2 + h, sd * M + h, xr, kf);
+    } else {
+#pragma unroll
+      for (int h = 0; h < M; ++h) {
+        xpass<K, W, M>(tab, 2 + h, at, xr);
+        vals[v][h] = point<K, W, M>(tab, sd - 2, (sd == 2 ? 2 * M : 3 * M) + h, xr, kf);
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < M; ++h) {
+    const int hb = rev ? M - 1 - h : h;
+    cdp cv = tab + O.bt_conv + ((size_t)idx * M + h) * 5;
+    double* o = bt + ((size_t)idx * M + h) * 3;
+    o[0] = cv[0] * vals[0][hb];
+    o[1] = cv[1] * vals[1][hb] + cv[2] * vals[2][hb];
+    o[2] = cv[3] * vals[1][hb] + cv[4] * vals[2][hb];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused stage kernel
+// ---------------------------------------------------------------------------
+struct StageArgs {
+  const double* q;
+  const double* qn;
+  double* out;
+  const double* bt;
+  double ca, cb, cc;
+  int out_padded;
+  int strip_w, seg_h, n_strips, n_segs;
+};
+
 #ifndef HOPE_STAGE_WAVES
 #define HOPE_STAGE_WAVES 1
 #endif
-__global__ __launch_bounds__(64, HOPE_STAGE_WAVES) void k_stage(DevTables td, StageArgs A) {
-  const CTab t(td);
-  using Wd = Window<K, W, M>;
-  constexpr int R = Wd::R, L = Wd::L, S = Wd::S, NA = Wd::NA, NR = Wd::NR, CW = Wd::CW;
-  constexpr int XR = W ? L * NR : NR;
-  __shared__ double sq[3][NR][CW];
 
-  const int n = t.n, P = t.P;
+template <int K, bool W, int M>
+__global__ __launch_bounds__(64, HOPE_STAGE_WAVES) void k_stage(const double* __restrict__ tab_, GridScalars gs,
+                                                                StageArgs A) {
+  using C = Cfg<K, W, M>;
+  constexpr int R = C::R, S = C::S, NR = C::NR, XR = C::XR;
+  constexpr int CW = 64 + 2 * R;
+  // stencil window: NR padded rows of CW columns (LDS column c = padded column i0-1+c)
+  __shared__ double sq[3][NR][CW];
+  // WENO weights kappa_j per variable and lane, and the carried top traces
+  __shared__ double skap[W ? 3 : 1][W ? S : 1][64];
+  __shared__ double sptop[3][M][64];
+  const cdp tab = (cdp)tab_;
+  const cdp ltab = tab;
+  const int n = gs.n, P = gs.P;
+  const TabOffsets O = tab_offsets(K, W, M, n);
   const size_t plane = (size_t)P * P;
   const size_t vs = 6 * plane;
   int item = blockIdx.x;
@@ -408,23 +348,26 @@ __global__ __launch_bounds__(64, HOPE_STAGE_WAVES) void k_stage(DevTables td, St
   const int p = item / A.n_strips;
   const int lane = threadIdx.x;
   const int i0 = strip * A.strip_w;
-  const int i1 = min(n, i0 + A.strip_w);
-  const int i = i0 - 1 + lane;
+  const int i1 = min(n, i0 + A.strip_w);          // owned columns [i0, i1)
+  const int i = i0 - 1 + lane;                     // this lane's column
   const bool in_strip = (i >= i0 - 1) && (i <= i1);
-  const bool real = in_strip && i >= 0 && i < n;
-  const bool owner = i >= i0 && i < i1;
+  const bool real = in_strip && i >= 0 && i < n;   // a cell this lane can reconstruct
+  const bool owner = i >= i0 && i < i1;            // a cell whose result this lane writes
   const int j0 = seg * A.seg_h;
   const int j1 = min(n, j0 + A.seg_h);
-  const double invd = t.inv_delta;
-  const double ia = 1.0 / t.radius;
+  const double invd = gs.inv_delta;
+  const double ia = 1.0 / gs.radius;
   const double* qp = A.q + p * plane;
   const double* btp = A.bt + (size_t)p * 4 * n * M * 3;
-  const double Lx0 = t.fcoef[p * 3 + 0], LxX = t.fcoef[p * 3 + 1], LxY = t.fcoef[p * 3 + 2];
-  const int ic = max(0, min(n - 1, i));        // clamped column for table reads
-  const int ie = max(0, min(n, i));            // clamped edge index
-  const double Xei = t.Xe[ie], sqxe = t.sqe[ie];
+  cdp fc = tab + C::O.fcoef + p * 3;
+  const double Lx0 = fc[0], LxX = fc[1], LxY = fc[2];
+  const int ic = max(0, min(n - 1, i));            // clamped column for table reads
+  const int ie = max(0, min(n, i));                // clamped edge index
+  const double Xei = tab[O.Xe + ie], sqxe = tab[O.sqe + ie];
+  const bool xdead = !(in_strip && i >= 0 && i <= n && lane >= 1);   // no x-edge flux on this lane
+  cdp Xg = tab + O.Xg, sqg = tab + O.sqg, Xe = tab + O.Xe, sqe = tab + O.sqe, gw = tab + C::O.gw;
 
-  // ---- window loading --------------------------------------------------
+  // ---- window rows ---------------------------------------------------------
   constexpr int PER = (3 * CW + 63) / 64;
   auto fetch = [&](int pr, double* buf) {
 #pragma unroll
@@ -443,139 +386,57 @@ __global__ __launch_bounds__(64, HOPE_STAGE_WAVES) void k_stage(DevTables td, St
       if (idx < 3 * CW) sq[idx / CW][slot][idx % CW] = buf[k];
     }
   };
-  // stencil value at offset (dy, dx) of this lane's cell in the row centred at padded row pc
-  // pc = interior row of the centre cell, so the padded row is pc + R + dy
-  auto at = [&](int v, int pc, int dy, int dx) -> double { return sq[v][(pc + R + dy) % NR][lane + R + dx]; };
-
-  // ---- reconstruction helpers (centre padded row pc) --------------------
-  double kap[W ? 3 : 1][W ? S : 1];
-  auto weights_init = [&](int pc) {
+  // stencil of variable v at offset (dy, dx) of this lane's cell in interior row pc
+  auto win = [&](int v, int pc) {
+    return [&, v, pc](int dy, int dx) -> double { return sq[v][(pc + R + dy) % NR][lane + R + dx]; };
+  };
+  auto kapv = [&](int v) {
+    return [&, v](int j) -> double { return skap[v][j][lane]; };
+  };
+  auto weights = [&](int pc) {
     if constexpr (W) {
-#pragma unroll
+#pragma unroll 1
       for (int v = 0; v < 3; ++v) {
-        double beta[S];
-#pragma unroll
-        for (int sx = 0; sx < L; ++sx) {
-          double tr[NR][L];
-#pragma unroll
-          for (int row = 0; row < NR; ++row)
-#pragma unroll
-            for (int al = 0; al < L; ++al) {
-              double s = 0;
-#pragma unroll
-              for (int a = 0; a < L; ++a)
-                s = fma(t.V[(sx * L + al) * L + a], at(v, pc, row - R, sx - (L - 1) + a), s);
-              tr[row][al] = s;
-            }
-#pragma unroll
-          for (int sy = 0; sy < L; ++sy) {
-            double b = 0;
-#pragma unroll
-            for (int be = 0; be < L; ++be)
-#pragma unroll
-              for (int al = 0; al < L; ++al) {
-                if (al == 0 && be == 0) continue;
-                double c = 0;
-#pragma unroll
-                for (int bb = 0; bb < L; ++bb) c = fma(t.V[(sy * L + be) * L + bb], tr[sy + bb][al], c);
-                b = fma(t.lam[be * L + al] * c, c, b);
-              }
-            beta[sy * L + sx] = b;
-          }
-        }
-        double tau = 0;
-#pragma unroll
-        for (int a = 0; a < S; ++a)
-#pragma unroll
-          for (int b = a + 1; b < S; ++b) tau += fabs(beta[a] - beta[b]);
-        tau *= 2.0 / (S * (S + 1));
-#pragma unroll
-        for (int j = 0; j < S; ++j) kap[v][j] = fma(tau, rcp(beta[j] + t.eps), 1.0);
+        asm volatile("" ::: "memory");
+        weno_kappa<K, W, M>(ltab, gs.eps, win(v, pc), [&](int j, double x) { skap[v][j][lane] = x; });
       }
     }
   };
-  auto xpass = [&](int v, int pc, int px, double* xr) {
-    // each pass re-reads its stencil from LDS rather than keeping all of it live
+  // each pass re-reads its stencil from LDS rather than keeping all of it live
+  auto pass = [&](int v, int pc, int px, double* xr) {
     asm volatile("" ::: "memory");
-    if constexpr (!W) {
-#pragma unroll
-      for (int row = 0; row < NR; ++row) {
-        double s = 0;
-#pragma unroll
-        for (int a = 0; a < K; ++a) s = fma(t.wc[px * K + a], at(v, pc, row - R, a - R), s);
-        xr[row] = s;
-      }
-    } else {
-#pragma unroll
-      for (int sx = 0; sx < L; ++sx)
-#pragma unroll
-        for (int row = 0; row < NR; ++row) {
-          double s = 0;
-#pragma unroll
-          for (int a = 0; a < L; ++a)
-            s = fma(t.wsub[(sx * NA + px) * L + a], at(v, pc, row - R, sx - (L - 1) + a), s);
-          xr[sx * NR + row] = s;
-        }
-    }
+    xpass<K, W, M>(ltab, px, win(v, pc), xr);
   };
-  auto point = [&](int v, int py, int pt, const double* xr) -> double {
-    if constexpr (!W) {
-      double s = 0;
-#pragma unroll
-      for (int b = 0; b < K; ++b) s = fma(t.wc[py * K + b], xr[b], s);
-      return s;
-    } else {
-      double ap = 0, dp = 0, am = 0, dm = 0;
-#pragma unroll
-      for (int sy = 0; sy < L; ++sy)
-#pragma unroll
-        for (int sx = 0; sx < L; ++sx) {
-          double pv = 0;
-#pragma unroll
-          for (int b = 0; b < L; ++b) pv = fma(t.wsub[(sy * NA + py) * L + b], xr[sx * NR + sy + b], pv);
-          const int j = sy * L + sx;
-          const double tk = kap[v][j] * pv;
-          ap = fma(t.gp[pt * S + j], tk, ap);
-          am = fma(t.gm[pt * S + j], tk, am);
-          dp = fma(t.gp[pt * S + j], kap[v][j], dp);
-          dm = fma(t.gm[pt * S + j], kap[v][j], dm);
-        }
-      return (t.sp[pt] * ap * dm - t.sm[pt] * am * dp) * rcp(dp * dm);
-    }
-  };
+  auto ptop = [&](int v, int h) -> double& { return sptop[v][h][lane]; };
 
   // ---- prologue: window and the top traces of row j0-1 ------------------
-  double ptop[3][M];
   double nxt[PER];
-  {
-    for (int pr = max(0, j0 - 1); pr < j0 + 2 * R; ++pr) {
-      fetch(pr, nxt);
-      store(pr, nxt);
-    }
-    fetch(j0 + 2 * R, nxt);          // row needed by the first step
+  for (int pr = max(0, j0 - 1); pr < j0 + 2 * R; ++pr) {
+    fetch(pr, nxt);
+    store(pr, nxt);
   }
+  fetch(j0 + 2 * R, nxt);          // row needed by the first step
   __syncthreads();
   if (j0 == 0) {
 #pragma unroll
     for (int h = 0; h < M; ++h)
 #pragma unroll
-      for (int v = 0; v < 3; ++v) ptop[v][h] = real ? btp[(((size_t)2 * n + ic) * M + h) * 3 + v] : 1.0;
+      for (int v = 0; v < 3; ++v) ptop(v, h) = real ? btp[(((size_t)2 * n + ic) * M + h) * 3 + v] : (v ? 0.0 : 1.0);
   } else {
-    weights_init(j0 - 1);
-#pragma unroll
+    weights(j0 - 1);
+#pragma unroll 1
     for (int h = 0; h < M; ++h)
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         double xr[XR];
-        xpass(v, j0 - 1, 2 + h, xr);
-        ptop[v][h] = point(v, 1, 3 * M + h, xr);
+        pass(v, j0 - 1, 2 + h, xr);
+        ptop(v, h) = point<K, W, M>(ltab, 1, 3 * M + h, xr, kapv(v));
       }
   }
   double acc[3] = {0.0, 0.0, 0.0};
 
   for (int j = j0; j <= j1; ++j) {
     const bool last = (j == j1);
-    const int pc = j;
     // the window of step j holds padded rows j .. j+2R; row j+2R was fetched
     // during the previous step and replaces row j-1, no longer read
     const bool have = !(last && j1 == n) && (j + 2 * R) < P;
@@ -588,18 +449,18 @@ __global__ __launch_bounds__(64, HOPE_STAGE_WAVES) void k_stage(DevTables td, St
     double fl[3] = {0.0, 0.0, 0.0};
     double s1 = 0.0, s2 = 0.0;
     if (!last) {
-      weights_init(pc);
+      weights(j);
       // x-edges: left trace (px = 0), right trace (px = 1), flux through the left edge
       double xl[3][M], xrt[3][M];
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         double xr[XR];
-        xpass(v, pc, 0, xr);
+        pass(v, j, 0, xr);
 #pragma unroll
-        for (int h = 0; h < M; ++h) xl[v][h] = point(v, 2 + h, h, xr);
-        xpass(v, pc, 1, xr);
+        for (int h = 0; h < M; ++h) xl[v][h] = point<K, W, M>(ltab, 2 + h, h, xr, kapv(v));
+        pass(v, j, 1, xr);
 #pragma unroll
-        for (int h = 0; h < M; ++h) xrt[v][h] = point(v, 2 + h, M + h, xr);
+        for (int h = 0; h < M; ++h) xrt[v][h] = point<K, W, M>(ltab, 2 + h, M + h, xr, kapv(v));
       }
 #pragma unroll
       for (int h = 0; h < M; ++h) {
@@ -609,60 +470,60 @@ __global__ __launch_bounds__(64, HOPE_STAGE_WAVES) void k_stage(DevTables td, St
           qL[v] = __shfl_up(xrt[v][h], 1, 64);
           qR[v] = xl[v][h];
         }
-        if (i == 0) {
+        // panel edges take the neighbour's converted trace; lanes without an
+        // edge of their own get a harmless state (selects, not branches: a
+        // branch here splits the region and the register allocation suffers)
 #pragma unroll
-          for (int v = 0; v < 3; ++v) qL[v] = btp[(((size_t)0 * n + j) * M + h) * 3 + v];
-        }
-        if (i == n) {
-#pragma unroll
-          for (int v = 0; v < 3; ++v) qR[v] = btp[(((size_t)1 * n + j) * M + h) * 3 + v];
-        }
-        if (!(in_strip && i >= 0 && i <= n && lane >= 1)) {
-#pragma unroll
-          for (int v = 0; v < 3; ++v) qL[v] = qR[v] = (v == 0) ? 1.0 : 0.0;
+        for (int v = 0; v < 3; ++v) {
+          const double bl = btp[(((size_t)0 * n + j) * M + h) * 3 + v];
+          const double br = btp[(((size_t)1 * n + j) * M + h) * 3 + v];
+          const double dflt = v == 0 ? 1.0 : 0.0;
+          qL[v] = xdead ? dflt : (i == 0 ? bl : qL[v]);
+          qR[v] = xdead ? dflt : (i == n ? br : qR[v]);
         }
         double F[3];
-        const double Y = t.Xg[j * M + h];
-        lmars_fast(qL, qR, Xei, Y, sqxe, t.sqg[j * M + h], 0, t.radius, ia, F);
+        lmars(qL, qR, Xei, Xg[j * M + h], sqxe, sqg[j * M + h], 0, ia, F);
 #pragma unroll
-        for (int v = 0; v < 3; ++v) fl[v] = fma(t.gw[h], F[v], fl[v]);
+        for (int v = 0; v < 3; ++v) fl[v] = fma(gw[h], F[v], fl[v]);
       }
       // Gauss-node columns: y-edge traces, y-flux through the bottom edge, CQP sources
-#pragma unroll
+#pragma unroll 1
       for (int h = 0; h < M; ++h) {
         double yb[3], yt[3], cq[3][M];
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
           double xr[XR];
-          xpass(v, pc, 2 + h, xr);
-          yb[v] = point(v, 0, 2 * M + h, xr);
-          yt[v] = point(v, 1, 3 * M + h, xr);
+          pass(v, j, 2 + h, xr);
+          yb[v] = point<K, W, M>(ltab, 0, 2 * M + h, xr, kapv(v));
+          yt[v] = point<K, W, M>(ltab, 1, 3 * M + h, xr, kapv(v));
 #pragma unroll
-          for (int w = 0; w < M; ++w) cq[v][w] = point(v, 2 + w, 4 * M + w * M + h, xr);
+          for (int w = 0; w < M; ++w) cq[v][w] = point<K, W, M>(ltab, 2 + w, 4 * M + w * M + h, xr, kapv(v));
         }
-        const double X = t.Xg[ic * M + h];
-        const double sqx = t.sqg[ic * M + h];
-        if (!real) {
-          yb[0] = ptop[0][h] = 1.0;
-          yb[1] = yb[2] = ptop[1][h] = ptop[2][h] = 0.0;
+        const double X = Xg[ic * M + h];
+        const double sqx = sqg[ic * M + h];
+        double qL[3] = {ptop(0, h), ptop(1, h), ptop(2, h)};
 #pragma unroll
-          for (int w = 0; w < M; ++w) { cq[0][w] = 1.0; cq[1][w] = cq[2][w] = 0.0; }
+        for (int v = 0; v < 3; ++v) {
+          const double dflt = v == 0 ? 1.0 : 0.0;
+          qL[v] = real ? qL[v] : dflt;
+          yb[v] = real ? yb[v] : dflt;
+#pragma unroll
+          for (int w = 0; w < M; ++w) cq[v][w] = real ? cq[v][w] : dflt;
         }
-        double qL[3] = {ptop[0][h], ptop[1][h], ptop[2][h]};
         double F[3];
-        lmars_fast(qL, yb, X, t.Xe[j], sqx, t.sqe[j], 1, t.radius, ia, F);
+        lmars(qL, yb, X, Xe[j], sqx, sqe[j], 1, ia, F);
 #pragma unroll
-        for (int v = 0; v < 3; ++v) gb[v] = fma(t.gw[h], F[v], gb[v]);
+        for (int v = 0; v < 3; ++v) gb[v] = fma(gw[h], F[v], gb[v]);
 #pragma unroll
-        for (int v = 0; v < 3; ++v) ptop[v][h] = yt[v];
+        for (int v = 0; v < 3; ++v) ptop(v, h) = yt[v];
 #pragma unroll
         for (int w = 0; w < M; ++w) {
-          const double Y = t.Xg[j * M + w];
+          const double Y = Xg[j * M + w];
           double a1, a2;
-          sources_fast(cq[0][w], cq[1][w], cq[2][w], X, Y, Lx0 + LxX * X + LxY * Y, t.omega2, a1, a2);
-          const double gw = t.gw[h] * t.gw[w];
-          s1 = fma(gw, a1, s1);
-          s2 = fma(gw, a2, s2);
+          sources(cq[0][w], cq[1][w], cq[2][w], X, Y, Lx0 + LxX * X + LxY * Y, gs.omega2, a1, a2);
+          const double g2 = gw[h] * gw[w];
+          s1 = fma(g2, a1, s1);
+          s2 = fma(g2, a2, s2);
         }
       }
     } else {
@@ -674,28 +535,29 @@ __global__ __launch_bounds__(64, HOPE_STAGE_WAVES) void k_stage(DevTables td, St
 #pragma unroll
           for (int v = 0; v < 3; ++v) yb[v][h] = real ? btp[(((size_t)3 * n + ic) * M + h) * 3 + v] : (v ? 0.0 : 1.0);
       } else {
-        weights_init(pc);
+        weights(j);
 #pragma unroll
         for (int h = 0; h < M; ++h)
 #pragma unroll
           for (int v = 0; v < 3; ++v) {
             double xr[XR];
-            xpass(v, pc, 2 + h, xr);
-            yb[v][h] = point(v, 0, 2 * M + h, xr);
+            pass(v, j, 2 + h, xr);
+            yb[v][h] = point<K, W, M>(ltab, 0, 2 * M + h, xr, kapv(v));
           }
       }
 #pragma unroll
       for (int h = 0; h < M; ++h) {
-        double qL[3] = {ptop[0][h], ptop[1][h], ptop[2][h]};
-        double qR[3] = {yb[0][h], yb[1][h], yb[2][h]};
-        if (!real) {
-          qL[0] = qR[0] = 1.0;
-          qL[1] = qL[2] = qR[1] = qR[2] = 0.0;
+        double qL[3], qR[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          const double dflt = v == 0 ? 1.0 : 0.0;
+          qL[v] = real ? ptop(v, h) : dflt;
+          qR[v] = real ? yb[v][h] : dflt;
         }
         double F[3];
-        lmars_fast(qL, qR, t.Xg[ic * M + h], t.Xe[j], t.sqg[ic * M + h], t.sqe[j], 1, t.radius, ia, F);
+        lmars(qL, qR, Xg[ic * M + h], Xe[j], sqg[ic * M + h], sqe[j], 1, ia, F);
 #pragma unroll
-        for (int v = 0; v < 3; ++v) gb[v] = fma(t.gw[h], F[v], gb[v]);
+        for (int v = 0; v < 3; ++v) gb[v] = fma(gw[h], F[v], gb[v]);
       }
     }
     // ---- finalize row j-1 ---------------------------------------------------
@@ -738,17 +600,18 @@ int launch_fill_halo(const GhostDev& g, double* q, int plane, void* stream) {
 }
 
 template <int K, bool W, int M>
-static int edge_traces_t(const DevTables& t, const double* q, double* bt, void* stream) {
-  const int total = 24 * t.n;
-  hipLaunchKernelGGL((k_edge_traces<K, W, M>), dim3((total + 63) / 64), dim3(64), 0, (hipStream_t)stream, t, q,
-                     bt);
+static int edge_traces_t(const double* tab, const int32_t* itab, const GridScalars& gs, const double* q, double* bt,
+                         void* stream) {
+  const int total = 24 * gs.n;
+  hipLaunchKernelGGL((k_edge_traces<K, W, M>), dim3((total + 63) / 64), dim3(64), 0, (hipStream_t)stream, tab,
+                     itab, gs, q, bt);
   return (int)hipGetLastError();
 }
 
 template <int K, bool W, int M>
-static int stage_t(const DevTables& t, const StageArgs& a, void* stream) {
+static int stage_t(const double* tab, const GridScalars& gs, const StageArgs& a, void* stream) {
   const int items = 6 * a.n_strips * a.n_segs;
-  hipLaunchKernelGGL((k_stage<K, W, M>), dim3(items), dim3(64), 0, (hipStream_t)stream, t, a);
+  hipLaunchKernelGGL((k_stage<K, W, M>), dim3(items), dim3(64), 0, (hipStream_t)stream, tab, gs, a);
   return (int)hipGetLastError();
 }
 
@@ -772,13 +635,15 @@ static int stage_t(const DevTables& t, const StageArgs& a, void* stream) {
     return (int)hipErrorInvalidValue;                             \
   } while (0)
 
-int launch_edge_traces(int k, int weno, const DevTables& t, const double* q, double* bt, void* stream) {
-  HOPE_DISPATCH(edge_traces_t, t, q, bt, stream);
+int launch_edge_traces(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs,
+                       const double* q, double* bt, void* stream) {
+  HOPE_DISPATCH(edge_traces_t, tab, itab, gs, q, bt, stream);
 }
 
-int launch_stage(int k, int weno, const DevTables& t, const double* q, const double* qn, double* out,
-                 int out_padded, double ca, double cb, double cc, const double* bt, int strip_w, int seg_h,
-                 void* stream) {
+int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs, const double* q,
+                 const double* qn, double* out, int out_padded, double ca, double cb, double cc, const double* bt,
+                 int strip_w, int seg_h, void* stream) {
+  (void)itab;
   StageArgs a;
   a.q = q;
   a.qn = qn;
@@ -790,9 +655,9 @@ int launch_stage(int k, int weno, const DevTables& t, const double* q, const dou
   a.out_padded = out_padded;
   a.strip_w = strip_w;
   a.seg_h = seg_h;
-  a.n_strips = (t.n + strip_w - 1) / strip_w;
-  a.n_segs = (t.n + seg_h - 1) / seg_h;
-  HOPE_DISPATCH(stage_t, t, a, stream);
+  a.n_strips = (gs.n + strip_w - 1) / strip_w;
+  a.n_segs = (gs.n + seg_h - 1) / seg_h;
+  HOPE_DISPATCH(stage_t, tab, gs, a, stream);
 }
 
 }  // namespace hope
