@@ -9,7 +9,12 @@ quadrature, sources, tendency, Runge-Kutta combination).  The state is
 resident in HBM before the timed region starts.
 
 Metric: FP64 cell-tendency evaluations per second = interior cells x RHS
-evaluations / wall time.  Prints one JSON line.
+evaluations / wall time.  ``value`` is the forward rate; ``fwd_vjp`` holds
+the forward+adjoint rates: a tendency plus its vector-Jacobian product on the
+same state (one unit per cell), and the 20-step adjoint rollout (forward, then
+the backward pass of 0.5 ||h_T - h_target||^2 with checkpoints every 5 steps),
+counted as cells x RHS evaluations of the forward over the whole wall time.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -59,6 +64,61 @@ def flops_per_cell(order: int, scheme: str) -> float:
     return 3 * per_var + lmars + src + 15 + 18
 
 
+STAGE_SOURCES = ("paper_2411_19185_amd/csrc/kernels.hip", "paper_2411_19185_amd/csrc/device_common.hpp",
+                 "paper_2411_19185_amd/csrc/hope_internal.hpp")
+TRAFFIC_FILE = "profiles/k_stage_weno5_c360_traffic.txt"
+
+
+def stage_source_hash() -> str:
+    """sha256 over the sources the stage kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in STAGE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n, order, scheme):
+    """HBM bytes per stage launch from the committed counter summary (rocprofv3
+    FETCH_SIZE and WRITE_SIZE of the stage kernel, each divided by the factor
+    the same counter reads for a copy of known size), or None when the
+    summary is missing, is for another workload, or was taken from other
+    kernel sources."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv.get("source_hash") != stage_source_hash():
+            return None
+        if (int(kv["n"]), int(kv["order"]), kv["scheme"]) != (n, order, scheme):
+            return None
+        return {"bytes_per_launch": float(kv["bytes_per_launch"]), "fetch_bytes": float(kv["fetch_bytes"]),
+                "write_bytes": float(kv["write_bytes"]), "copy_factor_fetch": float(kv["copy_factor_fetch"]),
+                "copy_factor_write": float(kv["copy_factor_write"])}
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device copy of known size (1 GiB read + 1 GiB written), for
+    scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "copies": 3}), flush=True)
+
+
 def stage_bytes_per_cell() -> float:
     """Algorithmic HBM bytes of one fused stage per cell: read q_s and q_n,
     write q_{s+1} (3 FP64 each)."""
@@ -104,6 +164,7 @@ def run(args):
     evals = 3 * args.steps
     value = cells * evals / (ms / 1e3)
     st_ms, st_n = g.profile_read("stage")
+    traffic = measured_traffic(n, order, scheme)
     halo_ms, halo_n = g.profile_read("fill_halo")
     edge_ms, edge_n = g.profile_read("edge_traces")
     stage_avg = st_ms / max(st_n, 1)
@@ -128,7 +189,9 @@ def run(args):
                    "n": n, "order": order, "scheme": scheme, "cells": cells, "rhs_per_step": 3,
                    "launch": list(g.get_launch()), "dt_s": dt, "seed": args.seed},
         "roofline": {"bound": "alu", "kernel": "k_stage", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+                     "traffic": None if traffic is None else traffic["bytes_per_launch"],
+                     "traffic_detail": traffic, "stage_source_hash": stage_source_hash(),
                      "flops_per_cell": fpc, "stage_avg_ms": stage_avg, "stage_launches": st_n,
                      "hbm_effective_GBps": stage_bytes_per_cell() * cells / (stage_avg / 1e3) / 1e9,
                      "hbm_frac": stage_bytes_per_cell() * cells / (stage_avg / 1e3) / PEAK_HBM},
@@ -137,9 +200,92 @@ def run(args):
         "state_finite": finite,
         "setup_s": setup_s,
     }
+    if not args.no_adjoint:
+        out["fwd_vjp"] = adjoint(g, n, args, dt)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(qfin, n, order, scheme)
     print(json.dumps(out), flush=True)
+
+
+def adjoint(g, n, args, dt):
+    """Forward+adjoint throughput: (1) tendency + hope_tendency_vjp pairs on
+    one state, (2) the adjoint rollout of a height-mismatch loss."""
+    import numpy as np
+    import torch
+
+    import hope_inputs as hi
+    from paper_2411_19185_amd import autograd, workloads
+
+    cells = 6 * n * n
+    q0 = torch.from_numpy(workloads.smooth_random_state(n, seed=args.seed)).cuda()
+    w = torch.from_numpy(hi.normal_array(args.seed + 7, (3, 6, n, n))).cuda()
+    qp = g.new_state()
+    g.interior(qp).copy_(q0)
+    ws = g.vjp_workspace()
+    dq = torch.empty(3, 6, n, n, dtype=torch.float64, device="cuda")
+    gq = torch.empty_like(dq)
+    for _ in range(2):
+        g.tendency(qp, dq)
+        g.tendency_vjp(qp, w, gq, ws)
+    torch.cuda.synchronize()
+    g.profile(True)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    reps = args.vjp_reps
+    for _ in range(reps):
+        g.tendency(qp, dq)
+        g.tendency_vjp(qp, w, gq, ws)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    g.profile(False)
+    pair_ms = ev[0].elapsed_time(ev[1]) / reps
+    kern = {}
+    for k in ("vjp_traces", "vjp_points", "vjp_edges", "vjp_weno", "vjp_gather", "vjp_ghost_t"):
+        ms, cnt = g.profile_read(k)
+        if cnt:
+            kern[k] = ms / cnt
+    fill_ms, fill_cnt = g.profile_read("fill_halo")
+    kern["fill_halo"] = fill_ms / max(fill_cnt, 1)
+    vjp_ms = sum(v for k, v in kern.items() if k.startswith("vjp_")) + kern["fill_halo"]
+
+    # adjoint rollout
+    steps, every = args.rollout_steps, args.checkpoint_every
+    sg = torch.from_numpy(workloads.cell_sqrt_g(n)).cuda()
+    hscale = 1.0 / (hi.GRAVITY * sg)
+    qt = g.new_state()
+    g.interior(qt).copy_(torch.from_numpy(workloads.smooth_random_state(n, seed=args.seed + 1)))
+    rws = g.workspace()
+    for _ in range(steps):
+        g.rk_step(qt, dt, "ssp3", rws)
+    h_target = (g.interior(qt)[0] * hscale).contiguous()
+    del qt, rws, qp, ws, dq, gq
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    base_mem = torch.cuda.memory_allocated()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    q = q0.clone().requires_grad_(True)
+    ev[0].record(stream)
+    qT = autograd.rollout(g, q, dt, steps, checkpoint_every=every)
+    ev[1].record(stream)
+    loss = 0.5 * ((qT[0] * hscale - h_target) ** 2).sum()
+    loss.backward()
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = ev[0].elapsed_time(ev[1])
+    bwd_ms = ev[1].elapsed_time(ev[2])
+    peak = torch.cuda.max_memory_allocated() - base_mem
+    grad_finite = bool(torch.isfinite(q.grad).all())
+    return {
+        "pair": {"value": cells / (pair_ms / 1e3), "unit": "cell-(tendency+VJP) evals/s", "ms": pair_ms,
+                 "vjp_ms": vjp_ms, "kernels_ms_avg": kern, "reps": reps},
+        "rollout": {"value": cells * 3 * steps / ((fwd_ms + bwd_ms) / 1e3), "unit": "cell-tendency evals/s (fwd+VJP)",
+                    "steps": steps, "checkpoint_every": every, "fwd_ms": fwd_ms, "bwd_ms": bwd_ms,
+                    "fwd_value": cells * 3 * steps / (fwd_ms / 1e3),
+                    "peak_device_bytes_torch": int(peak), "grid_device_bytes": int(g.layout.device_bytes),
+                    "loss": float(loss), "grad_finite": grad_finite,
+                    "target": f"forward state after {steps} steps from seed {args.seed + 1}"},
+    }
 
 
 def cpu_baseline(q, n, order, scheme):
@@ -170,11 +316,19 @@ def main():
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--launch", default="", help="strip_w,seg_h of the stage kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy (counter scale)")
+    ap.add_argument("--vjp-reps", type=int, default=10)
+    ap.add_argument("--rollout-steps", type=int, default=20)
+    ap.add_argument("--checkpoint-every", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU panel "
               "decomposition is a design, not built", file=sys.stderr)
         raise SystemExit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     run(args)
 
 

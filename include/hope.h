@@ -24,11 +24,13 @@
  * Unpadded buffers (tendencies, cotangents) are FP64 [3][6][n][n].
  *
  * Ownership.  Every state, tendency, cotangent and workspace buffer is a
- * device allocation owned by the caller.  The grid owns only its constant
- * tables and a small scratch buffer for panel-edge traces, allocated by
- * hope_grid_create; no call allocates afterwards.  Calls that use the same
+ * device allocation owned by the caller; hope_grid_layout gives the sizes.
+ * The grid owns only its constant tables and a small scratch buffer for
+ * panel-edge traces, allocated by hope_grid_create; no call allocates
+ * afterwards.  Forward calls (hope_tendency, hope_rk_step) that use the same
  * grid must not run concurrently on different streams (they share that
- * scratch); grids are otherwise independent.
+ * scratch); the adjoint calls use only the caller's workspace.  Grids are
+ * otherwise independent.
  *
  * Errors.  Every int-returning function returns HOPE_OK (0) or a negative
  * status; a thread-local message is available from hope_last_error().
@@ -87,8 +89,11 @@ typedef struct hope_layout {
   int64_t state_elems;      /* 3*6*P*P: one padded state */
   int64_t interior_elems;   /* 3*6*n*n: one unpadded field */
   int64_t rk_workspace_bytes;  /* workspace of hope_rk_step */
+  int64_t vjp_workspace_bytes;     /* workspace of hope_tendency_vjp */
+  int64_t rk_vjp_workspace_bytes;  /* workspace of hope_rk_step_vjp */
   int64_t ghost_cells;      /* ghost cells per variable, all panels */
   int64_t ghost_nnz;        /* stored entries of the ghost map */
+  int64_t device_bytes;     /* device memory owned by the grid (tables, maps, scratch) */
 } hope_layout;
 
 /* Build a grid: equiangular metrics, reconstruction and WENO tables, the
@@ -117,9 +122,12 @@ int hope_tendency(const hope_grid* grid, double* q, double* dqdt, void* stream);
 /* Vector-Jacobian product of hope_tendency: given w = dL/d(dqdt) [3][6][n][n]
  * writes gq = dL/dq over the interior cells [3][6][n][n] (overwritten), the
  * ghost-cell cotangents folded back through G^T.  q's ghost rings are scratch.
- * Non-smooth points (|m|, |beta_i - beta_j|) take the subgradient sign(0)=0. */
-int hope_tendency_vjp(const hope_grid* grid, double* q, const double* w, double* gq,
-                      void* stream);
+ * Non-smooth points (|m|, |beta_i - beta_j|) take the subgradient sign(0)=0.
+ * ws: caller-owned device workspace of at least layout.vjp_workspace_bytes
+ * (8 * (2*3*(4m+m^2) + 3*order^2 [WENO only]) bytes per cell plus one padded
+ * state); gq must not alias w. */
+int hope_tendency_vjp(const hope_grid* grid, double* q, const double* w, double* gq, double* ws,
+                      size_t ws_bytes, void* stream);
 
 /* One three-stage Runge-Kutta step (section 3.5) in place on the padded
  * state q: HOPE_RK_SSP3 (Shu-Osher), or HOPE_RK_WS3 (3.39)-(3.41) with the
@@ -127,6 +135,14 @@ int hope_tendency_vjp(const hope_grid* grid, double* q, const double* w, double*
  * layout.rk_workspace_bytes (two padded states). */
 int hope_rk_step(const hope_grid* grid, double* q, double dt, int32_t scheme, double* ws,
                  size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of one hope_rk_step from the state q = q^n
+ * (padded; its ghost rings are scratch, its interior is read only): given
+ * gout = dL/dq^{n+1} [3][6][n][n] writes gin = dL/dq^n [3][6][n][n]
+ * (gin must not alias gout).  The stage states are recomputed.  ws: at least
+ * layout.rk_vjp_workspace_bytes. */
+int hope_rk_step_vjp(const hope_grid* grid, double* q, double dt, int32_t scheme, const double* gout,
+                     double* gin, double* ws, size_t ws_bytes, void* stream);
 
 /* Message for the last error on this thread ("" if none). */
 const char* hope_last_error(void);
@@ -143,7 +159,9 @@ int hope_grid_get_launch(const hope_grid* grid, int32_t* strip_w, int32_t* seg_h
  * on first use and kept by the grid).  hope_grid_profile(g, 1) clears the
  * record and starts, (g, 0) stops.  hope_grid_profile_read waits for the
  * recorded events and returns the summed elapsed time and launch count of one
- * kernel: 0 ghost fill, 1 panel-edge traces, 2 fused stage. */
+ * kernel: 0 ghost fill, 1 panel-edge traces, 2 fused stage, and the kernels
+ * of the adjoint: 3 point values, 4 flux and source adjoints, 5 panel-edge
+ * adjoints, 6 WENO adjoint, 7 gather to the padded cells, 8 G^T fold. */
 int hope_grid_profile(hope_grid* grid, int32_t enable);
 int hope_grid_profile_read(hope_grid* grid, int32_t kernel, double* total_ms, int64_t* launches);
 

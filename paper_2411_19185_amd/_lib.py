@@ -53,8 +53,11 @@ class Layout(ctypes.Structure):
         ("state_elems", ctypes.c_int64),
         ("interior_elems", ctypes.c_int64),
         ("rk_workspace_bytes", ctypes.c_int64),
+        ("vjp_workspace_bytes", ctypes.c_int64),
+        ("rk_vjp_workspace_bytes", ctypes.c_int64),
         ("ghost_cells", ctypes.c_int64),
         ("ghost_nnz", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
     ]
 
 
@@ -68,8 +71,9 @@ _SIGS = {
     "hope_grid_layout": (_I32, [_P, ctypes.POINTER(Layout)]),
     "hope_fill_halo": (_I32, [_P, _P, _P]),
     "hope_tendency": (_I32, [_P, _P, _P, _P]),
-    "hope_tendency_vjp": (_I32, [_P, _P, _P, _P, _P]),
+    "hope_tendency_vjp": (_I32, [_P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "hope_rk_step": (_I32, [_P, _P, ctypes.c_double, _I32, _P, ctypes.c_size_t, _P]),
+    "hope_rk_step_vjp": (_I32, [_P, _P, ctypes.c_double, _I32, _P, _P, _P, ctypes.c_size_t, _P]),
     "hope_last_error": (ctypes.c_char_p, []),
     "hope_grid_set_launch": (_I32, [_P, _I32, _I32]),
     "hope_grid_get_launch": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhope.so")
 
-SOURCES = ["capi.cpp", "host_tables.cpp", "kernels.hip"]
+SOURCES = ["capi.cpp", "host_tables.cpp", "kernels.hip", "vjp.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -8,6 +8,7 @@
 
 #include "hope.h"
 #include "hope_internal.hpp"
+#include "vjp_internal.hpp"
 
 using namespace hope;
 
@@ -31,8 +32,14 @@ struct hope_grid {
   GridScalars gs{};
   GhostDev g{};
   std::vector<void*> allocs;
+  size_t device_bytes = 0;
   double* bt = nullptr;      // panel-edge trace scratch, 24*n*m*3
   int strip_w = 62, seg_h = 8;
+  // G^T by interior cell (adjoint of the ghost fill)
+  const int32_t* gt_ptr = nullptr;
+  const int32_t* gt_row = nullptr;
+  const double* gt_val = nullptr;
+  int64_t gt_nnz = 0;
   // optional per-kernel timing with HIP events on the launch stream
   bool timing = false;
   std::vector<hipEvent_t> pool;
@@ -82,6 +89,7 @@ static int upload(hope_grid* G, const std::vector<T>& v, const T** out) {
   hipError_t e = hipMalloc(&p, v.size() * sizeof(T));
   if (e != hipSuccess) return hip_fail(e, "hipMalloc");
   G->allocs.push_back(p);
+  G->device_bytes += v.size() * sizeof(T);
   e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
   *out = static_cast<const T*>(p);
@@ -198,10 +206,38 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
   if (e1) { free_grid(G); return e1; }
   g.nnz = (int64_t)h.g_col.size();
   g.rows = (int)h.g_dst.size();
+  {
+    // transpose of G, rows by interior cell
+    const int n = h.n, P = h.P, r = h.r;
+    const int cells = 6 * n * n;
+    std::vector<int32_t> cnt(cells + 1, 0);
+    auto cell_of = [&](int32_t off) {
+      const int p = off / (P * P), jj = (off / P) % P - r, ii = off % P - r;
+      return (p * n + jj) * n + ii;
+    };
+    for (int32_t col : h.g_col) cnt[cell_of(col) + 1]++;
+    for (int c = 0; c < cells; ++c) cnt[c + 1] += cnt[c];
+    const size_t nnz = h.g_col.size();
+    std::vector<int32_t> rows(nnz), fill(cnt.begin(), cnt.end() - 1);
+    std::vector<double> vals(5 * nnz);
+    for (size_t gr = 0; gr + 1 < h.g_ptr.size(); ++gr)
+      for (int32_t k = h.g_ptr[gr]; k < h.g_ptr[gr + 1]; ++k) {
+        const int c = cell_of(h.g_col[k]);
+        const int32_t pos = fill[c]++;
+        rows[pos] = h.g_dst[gr];
+        for (int comp = 0; comp < 5; ++comp) vals[comp * nnz + pos] = h.g_val[comp * nnz + k];
+      }
+    int e2 = upload(G, cnt, &G->gt_ptr);
+    if (!e2) e2 = upload(G, rows, &G->gt_row);
+    if (!e2) e2 = upload(G, vals, &G->gt_val);
+    if (e2) { free_grid(G); return e2; }
+    G->gt_nnz = (int64_t)nnz;
+  }
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, sizeof(double) * 24 * (size_t)n * h.m * 3);
   if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipMalloc (edge traces)"); }
   G->allocs.push_back(p);
+  G->device_bytes += sizeof(double) * 24 * (size_t)n * h.m * 3;
   G->bt = static_cast<double*>(p);
   default_launch(G);
   e = hipDeviceSynchronize();
@@ -216,6 +252,16 @@ void hope_grid_destroy(hope_grid* grid) {
   free_grid(grid);
 }
 
+// adjoint scratch: point values T, their cotangents, WENO stencil cotangents, padded cotangent
+static size_t vjp_elems(const HostTables& h, size_t* nT, size_t* nD, size_t* nG) {
+  const size_t cells = 6ULL * h.n * h.n;
+  const size_t np = 4 * h.m + h.m * h.m;
+  *nT = cells * np * 3;
+  *nD = h.weno ? cells * h.k * h.k * 3 : 0;
+  *nG = 18ULL * h.P * h.P;
+  return 2 * *nT + *nD + *nG;
+}
+
 int hope_grid_layout(const hope_grid* G, hope_layout* out) {
   if (!G || !out) return fail(HOPE_ERR_INVALID, "null argument");
   const HostTables& h = G->h;
@@ -226,8 +272,15 @@ int hope_grid_layout(const hope_grid* G, hope_layout* out) {
   out->state_elems = 18LL * h.P * h.P;
   out->interior_elems = 18LL * h.n * h.n;
   out->rk_workspace_bytes = 2 * out->state_elems * (int64_t)sizeof(double);
+  {
+    size_t nT, nD, nG;
+    out->vjp_workspace_bytes = (int64_t)(vjp_elems(G->h, &nT, &nD, &nG) * sizeof(double));
+  }
+  out->rk_vjp_workspace_bytes =
+      (2 * out->state_elems + 2 * out->interior_elems) * (int64_t)sizeof(double) + out->vjp_workspace_bytes;
   out->ghost_cells = (int64_t)h.g_dst.size();
   out->ghost_nnz = (int64_t)h.g_col.size();
+  out->device_bytes = (int64_t)G->device_bytes;
   return HOPE_OK;
 }
 
@@ -269,10 +322,97 @@ int hope_tendency(const hope_grid* G, double* q, double* dqdt, void* stream) {
   return run_stage(G, q, nullptr, dqdt, 0, 0.0, 0.0, 1.0, stream);
 }
 
-int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq, void* stream) {
-  (void)q; (void)w; (void)gq; (void)stream;
-  if (!G) return fail(HOPE_ERR_INVALID, "null argument");
-  return fail(HOPE_ERR_UNSUPPORTED, "tendency VJP not built yet");
+int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq, double* ws, size_t ws_bytes,
+                      void* stream) {
+  if (!G || !q || !w || !gq || !ws) return fail(HOPE_ERR_INVALID, "null argument");
+  if (reinterpret_cast<uintptr_t>(q) % 8 || reinterpret_cast<uintptr_t>(w) % 8 ||
+      reinterpret_cast<uintptr_t>(gq) % 8 || reinterpret_cast<uintptr_t>(ws) % 8)
+    return fail(HOPE_ERR_INVALID, "misaligned buffer");
+  if (gq == w) return fail(HOPE_ERR_INVALID, "gq must not alias w");
+  const HostTables& h = G->h;
+  size_t nT, nD, nG;
+  if (ws_bytes < vjp_elems(h, &nT, &nD, &nG) * sizeof(double)) return fail(HOPE_ERR_INVALID, "workspace too small");
+  int e;
+  {
+    Timed tm(G, 0, stream);
+    e = launch_fill_halo(G->g, q, 6 * h.P * h.P, stream);
+  }
+  if (e) return hip_fail((hipError_t)e, "fill_halo launch");
+  VjpArgs a;
+  a.tab = G->tab;
+  a.itab = G->itab;
+  a.gs = G->gs;
+  a.q = q;
+  a.w = w;
+  a.gq = gq;
+  a.T = ws;
+  a.Lam = ws + nT;
+  a.Dl = ws + 2 * nT;
+  a.gpad = ws + 2 * nT + nD;
+  a.gt_ptr = G->gt_ptr;
+  a.gt_row = G->gt_row;
+  a.gt_val = G->gt_val;
+  a.gt_nnz = G->gt_nnz;
+  for (int step = 0; step < kVjpSteps; ++step) {
+    if (step == kVjpWeno && !h.weno) continue;
+    Timed tm(G, 3 + step, stream);
+    e = launch_vjp(h.k, h.weno, a, step, stream);
+    if (e) return hip_fail((hipError_t)e, "adjoint launch");
+  }
+  return HOPE_OK;
+}
+
+// stage coefficients: q_{s+1} = a q_0 + b q_s + c dt L(q_s)
+static void rk_coefs(int scheme, double dt, double a[3], double b[3], double c[3]) {
+  if (scheme == HOPE_RK_SSP3) {
+    a[0] = 0.0; b[0] = 1.0; c[0] = dt;
+    a[1] = 0.75; b[1] = 0.25; c[1] = 0.25 * dt;
+    a[2] = 1.0 / 3.0; b[2] = 2.0 / 3.0; c[2] = 2.0 / 3.0 * dt;
+  } else {
+    a[0] = 0.0; b[0] = 1.0; c[0] = dt / 3.0;
+    a[1] = 1.0; b[1] = 0.0; c[1] = 0.5 * dt;
+    a[2] = 1.0; b[2] = 0.0; c[2] = dt;
+  }
+}
+
+int hope_rk_step_vjp(const hope_grid* G, double* q, double dt, int32_t scheme, const double* gout, double* gin,
+                     double* ws, size_t ws_bytes, void* stream) {
+  if (!G || !q || !gout || !gin || !ws) return fail(HOPE_ERR_INVALID, "null argument");
+  if (scheme != HOPE_RK_SSP3 && scheme != HOPE_RK_WS3) return fail(HOPE_ERR_INVALID, "bad RK scheme");
+  if (gin == gout) return fail(HOPE_ERR_INVALID, "gin must not alias gout");
+  const size_t state = 18ULL * G->h.P * G->h.P, field = 18ULL * G->h.n * G->h.n;
+  size_t nT, nD, nG;
+  const size_t nv = vjp_elems(G->h, &nT, &nD, &nG);
+  if (ws_bytes < (2 * state + 2 * field + nv) * sizeof(double)) return fail(HOPE_ERR_INVALID, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(q) % 8 || reinterpret_cast<uintptr_t>(ws) % 8 ||
+      reinterpret_cast<uintptr_t>(gout) % 8 || reinterpret_cast<uintptr_t>(gin) % 8)
+    return fail(HOPE_ERR_INVALID, "misaligned buffer");
+  if (!std::isfinite(dt)) return fail(HOPE_ERR_INVALID, "dt not finite");
+  double a[3], b[3], c[3];
+  rk_coefs(scheme, dt, a, b, c);
+  double* q1 = ws;
+  double* q2 = ws + state;
+  double* cur = ws + 2 * state;
+  double* v = cur + field;
+  double* vws = v + field;
+  int st;
+  // recompute the stage states
+  if ((st = run_stage(G, q, nullptr, q1, 1, 0.0, b[0], c[0], stream))) return st;
+  if ((st = run_stage(G, q1, q, q2, 1, a[1], b[1], c[1], stream))) return st;
+  // reverse sweep: cur = dL/dq_{s+1}; gin accumulates dL/dq_0
+  double* qs[3] = {q, q1, q2};
+  int e = launch_combine(field, cur, gout, nullptr, nullptr, 1.0, 0.0, 0.0, stream);
+  if (!e) e = launch_combine(field, gin, gout, nullptr, nullptr, 0.0, 0.0, 0.0, stream);
+  if (e) return hip_fail((hipError_t)e, "combine launch");
+  for (int s = 2; s >= 0; --s) {
+    if ((st = hope_tendency_vjp(G, qs[s], cur, v, vws, nv * sizeof(double), stream))) return st;
+    e = launch_combine(field, gin, gin, cur, nullptr, 1.0, a[s], 0.0, stream);         // gin += a_s cur
+    if (!e) e = launch_combine(field, cur, cur, v, nullptr, b[s], c[s], 0.0, stream);  // cur = b_s cur + c_s v
+    if (e) return hip_fail((hipError_t)e, "combine launch");
+  }
+  e = launch_combine(field, gin, gin, cur, nullptr, 1.0, 1.0, 0.0, stream);            // gin += cur (q_0 term)
+  if (e) return hip_fail((hipError_t)e, "combine launch");
+  return HOPE_OK;
 }
 
 int hope_rk_step(const hope_grid* G, double* q, double dt, int32_t scheme, double* ws, size_t ws_bytes,
@@ -325,6 +465,7 @@ int hope_grid_profile(hope_grid* G, int32_t enable) {
 
 int hope_grid_profile_read(hope_grid* G, int32_t kernel, double* total_ms, int64_t* launches) {
   if (!G || !total_ms || !launches) return fail(HOPE_ERR_INVALID, "null argument");
+  if (kernel < 0 || kernel > 2 + kVjpSteps) return fail(HOPE_ERR_INVALID, "bad kernel index");
   double tot = 0;
   int64_t cnt = 0;
   for (const auto& r : G->recs) {

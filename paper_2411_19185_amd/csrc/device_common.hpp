@@ -1,0 +1,213 @@
+// Device helpers shared by the forward and adjoint kernels of the HOPE
+// right-hand side: fast reciprocal/root, LMARS, sources, and the
+// reconstruction building blocks (TPP (3.14), genuine 2D WENO (3.16)-(3.25)).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hope_internal.hpp"
+
+namespace hope {
+
+typedef const __attribute__((address_space(4))) double* cdp;
+typedef const __attribute__((address_space(4))) int32_t* cip;
+
+// ---------------------------------------------------------------------------
+// Arithmetic helpers
+// ---------------------------------------------------------------------------
+// reciprocal: hardware estimate refined by two Newton-Raphson steps
+__device__ __forceinline__ double rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// square root: Goldschmidt iteration from the hardware reciprocal square root
+__device__ __forceinline__ double sqrt_g(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+// LMARS flux (3.30)-(3.38) with upwind term |m|(q_R - q_L); dir 0 = x, 1 = y.
+// sqx = sqrt(1 + X^2), sqy = sqrt(1 + Y^2) come from tables, ia = 1/a.
+__device__ __forceinline__ void lmars(const double* qL, const double* qR, double X, double Y, double sqx,
+                                      double sqy, int dir, double ia, double* F) {
+  const double ox = sqx * sqx, oy = sqy * sqy;
+  const double d2 = fma(X, X, oy);
+  const double dl = sqrt_g(d2);
+  const double idl = rcp(dl);
+  const double isg = d2 * dl * ia * ia * rcp(ox * oy);            // 1/sqrtG, (2.8)
+  const double sgii = dl * ia * rcp(dir == 0 ? sqx : sqy);        // sqrt(G^ii), (2.6)
+  const int iv = 1 + dir;
+  const double phiL = qL[0] * isg, phiR = qR[0] * isg;
+  const double upL = qL[iv] * rcp(qL[0] * sgii);                   // (3.31)
+  const double upR = qR[iv] * rcp(qR[0] * sgii);
+  const double c = 0.5 * (sqrt_g(phiL) + sqrt_g(phiR));           // (3.34)-(3.35)
+  const double ms = 0.5 * (upL + upR - (phiR - phiL) * rcp(c));   // (3.32)
+  const double ps = 0.5 * (phiL + phiR - c * (upR - upL));        // (3.33)
+  const double mm = ms * sgii;                                    // (3.36)
+  const double am = fabs(mm);
+#pragma unroll
+  for (int v = 0; v < 3; ++v) F[v] = 0.5 * (mm * (qL[v] + qR[v]) - am * (qR[v] - qL[v]));   // (3.37)
+  const double pr = 0.5 * ps * ps * idl;                          // (3.38): sqrtG G^ij = (..)/delta
+  if (dir == 0) {
+    F[1] = fma(pr, oy, F[1]);
+    F[2] = fma(pr, X * Y, F[2]);
+  } else {
+    F[1] = fma(pr, X * Y, F[1]);
+    F[2] = fma(pr, ox, F[2]);
+  }
+}
+
+// Metric (2.2) and Coriolis (2.3) sources at one point; Lc = c0 + cX X + cY Y
+// so that f*delta = 2 Omega Lc.
+__device__ __forceinline__ void sources(double Q0, double Q1, double Q2, double X, double Y, double Lc,
+                                        double omega2, double& s1, double& s2) {
+  const double X2 = X * X, Y2 = Y * Y;
+  const double id2 = rcp(1.0 + X2 + Y2);
+  const double iq = 2.0 * rcp(Q0);
+  const double m1 = iq * (Y * (1.0 + Y2) * Q1 * Q2 - X * Y2 * Q1 * Q1);
+  const double m2 = iq * (X * (1.0 + X2) * Q1 * Q2 - X2 * Y * Q2 * Q2);
+  const double f = omega2 * Lc;
+  const double c1 = f * ((1.0 + Y2) * Q2 - X * Y * Q1);
+  const double c2 = f * (X * Y * Q2 - (1.0 + X2) * Q1);
+  s1 = (m1 + c1) * id2;
+  s2 = (m2 + c2) * id2;
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction of one cell from a stencil accessor at(dy, dx).  Axis
+// coordinates: 0 -> -1/2, 1 -> +1/2, 2+h -> Gauss node h.  Point numbering of
+// one cell: x-edge left (h), x-edge right (h), y-edge bottom (h), y-edge top
+// (h), CQP (v outer, h inner).
+// ---------------------------------------------------------------------------
+template <int K, bool W, int M>
+struct Cfg {
+  static constexpr int R = (K - 1) / 2;
+  static constexpr int L = (K + 1) / 2;     // sub-stencil width (WENO)
+  static constexpr int S = L * L;
+  static constexpr int NA = 2 + M;
+  static constexpr int NR = 2 * R + 1;
+  static constexpr int XR = W ? L * NR : NR;
+  static constexpr TabOffsets O = tab_offsets(K, W, M, 0);
+};
+
+// smoothness indicators -> kappa_j = 1 + tau/(beta_j + eps) of one variable,
+// (3.23)-(3.25); out(j, kappa_j)
+template <int K, bool W, int M, typename TP, typename At, typename Out>
+__device__ __forceinline__ void weno_kappa(TP tab, double eps, At at, Out out) {
+  using C = Cfg<K, W, M>;
+  constexpr int L = C::L, S = C::S, NR = C::NR, R = C::R;
+  TP V = tab + C::O.V, lam = tab + C::O.lam;
+  double beta[S];
+#pragma unroll
+  for (int sx = 0; sx < L; ++sx) {
+    double tr[NR][L];
+#pragma unroll
+    for (int row = 0; row < NR; ++row)
+#pragma unroll
+      for (int al = 0; al < L; ++al) {
+        double s = 0;
+#pragma unroll
+        for (int a = 0; a < L; ++a) s = fma(V[(sx * L + al) * L + a], at(row - R, sx - (L - 1) + a), s);
+        tr[row][al] = s;
+      }
+#pragma unroll
+    for (int sy = 0; sy < L; ++sy) {
+      double b = 0;
+#pragma unroll
+      for (int be = 0; be < L; ++be)
+#pragma unroll
+        for (int al = 0; al < L; ++al) {
+          if (al == 0 && be == 0) continue;
+          double c = 0;
+#pragma unroll
+          for (int bb = 0; bb < L; ++bb) c = fma(V[(sy * L + be) * L + bb], tr[sy + bb][al], c);
+          b = fma(lam[be * L + al] * c, c, b);
+        }
+      beta[sy * L + sx] = b;
+    }
+  }
+  double tau = 0;
+#pragma unroll
+  for (int a = 0; a < S; ++a)
+#pragma unroll
+    for (int b = a + 1; b < S; ++b) tau += fabs(beta[a] - beta[b]);
+  tau *= 2.0 / (S * (S + 1));
+#pragma unroll
+  for (int j = 0; j < S; ++j) out(j, fma(tau, rcp(beta[j] + eps), 1.0));
+}
+
+// x-pass at axis px: TPP: xr[row]; WENO: xr[sx*NR + row]
+template <int K, bool W, int M, typename TP, typename At>
+__device__ __forceinline__ void xpass(TP tab, int px, At at, double* xr) {
+  using C = Cfg<K, W, M>;
+  constexpr int L = C::L, NR = C::NR, R = C::R, NA = C::NA;
+  if constexpr (!W) {
+    TP wc = tab + C::O.wc;
+#pragma unroll
+    for (int row = 0; row < NR; ++row) {
+      double s = 0;
+#pragma unroll
+      for (int a = 0; a < K; ++a) s = fma(wc[px * K + a], at(row - R, a - R), s);
+      xr[row] = s;
+    }
+  } else {
+    TP wsub = tab + C::O.wsub;
+#pragma unroll
+    for (int sx = 0; sx < L; ++sx)
+#pragma unroll
+      for (int row = 0; row < NR; ++row) {
+        double s = 0;
+#pragma unroll
+        for (int a = 0; a < L; ++a) s = fma(wsub[(sx * NA + px) * L + a], at(row - R, sx - (L - 1) + a), s);
+        xr[sx * NR + row] = s;
+      }
+  }
+}
+
+// value at axis py from the x-pass; pt = point number; kap(j) gives kappa_j
+template <int K, bool W, int M, typename TP, typename Kap>
+__device__ __forceinline__ double point(TP tab, int py, int pt, const double* xr, Kap kap) {
+  using C = Cfg<K, W, M>;
+  constexpr int L = C::L, S = C::S, NR = C::NR, NA = C::NA;
+  if constexpr (!W) {
+    TP wc = tab + C::O.wc;
+    double s = 0;
+#pragma unroll
+    for (int b = 0; b < K; ++b) s = fma(wc[py * K + b], xr[b], s);
+    return s;
+  } else {
+    TP wsub = tab + C::O.wsub, gp = tab + C::O.gp, gm = tab + C::O.gm;
+    double ap = 0, dp = 0, am = 0, dm = 0;
+#pragma unroll
+    for (int sy = 0; sy < L; ++sy)
+#pragma unroll
+      for (int sx = 0; sx < L; ++sx) {
+        double pv = 0;
+#pragma unroll
+        for (int b = 0; b < L; ++b) pv = fma(wsub[(sy * NA + py) * L + b], xr[sx * NR + sy + b], pv);
+        const int j = sy * L + sx;
+        const double kj = kap(j);
+        const double tk = kj * pv;
+        ap = fma(gp[pt * S + j], tk, ap);
+        am = fma(gm[pt * S + j], tk, am);
+        dp = fma(gp[pt * S + j], kj, dp);
+        dm = fma(gm[pt * S + j], kj, dm);
+      }
+    // (3.20)-(3.22): sigma+ sum w+ p - sigma- sum w- p, w = alpha / sum alpha
+    return (tab[C::O.sp + pt] * ap * dm - tab[C::O.sm + pt] * am * dp) * rcp(dp * dm);
+  }
+}
+
+
+}  // namespace hope

@@ -112,6 +112,8 @@ struct GhostDev {
 // Launchers implemented in kernels.hip.  All enqueue on `stream` and return a
 // hipError_t value (0 on success).
 int launch_fill_halo(const GhostDev& g, double* q, int plane, void* stream);
+int launch_combine(size_t len, double* out, const double* x, const double* y, const double* z, double a, double b,
+                   double c, void* stream);
 int launch_edge_traces(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs,
                        const double* q, double* bt, void* stream);
 int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs,

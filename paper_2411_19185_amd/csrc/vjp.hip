@@ -1,0 +1,631 @@
+// Adjoint (vector-Jacobian product) of the HOPE tendency, hand-written.
+//
+// Given w = dL/d(dq/dt) the kernels compute dL/dq in reverse order of the
+// forward evaluation:
+//   k_vjp_traces    recompute every cell's values at its edge and cell Gauss
+//                   points (the forward reconstruction) into scratch T
+//   k_vjp_points    per cell, the cotangent of each of its point values: the
+//                   adjoint of the LMARS flux (3.30)-(3.38) through each edge
+//                   point it feeds (flux cotangent from the tendency (3.1)
+//                   and the quadrature (3.5)), and of the sources (2.2)-(2.3)
+//                   at its cell points (3.6)
+//   k_vjp_edges     adds, at every panel-edge point, the adjoint of the
+//                   neighbour panel's own flux with respect to the converted
+//                   trace, taken back through the transposed conversion
+//                   (3.26)-(3.29)
+//   k_vjp_weno      WENO: cotangents of the stencil cell values through the
+//                   nonlinear weights, tau, beta and the sub-stencil values
+//   k_vjp_gather    cotangent of every padded cell (interior and ghost)
+//   k_vjp_ghost_t   interior cotangent plus G^T times the ghost cotangents
+// Every kernel gathers (each output is written by one thread): no atomics.
+// Non-smooth points take the subgradient sign(0) = 0.
+#include "device_common.hpp"
+#include "vjp_internal.hpp"
+
+namespace hope {
+
+// ---------------------------------------------------------------------------
+// Adjoint helpers
+// ---------------------------------------------------------------------------
+// reverse mode of lmars(): given mu = dL/dF, accumulate dL/dqL and dL/dqR
+__device__ __forceinline__ void lmars_adj(const double* qL, const double* qR, double X, double Y, double sqx,
+                                          double sqy, int dir, double ia, const double* mu, double* bL,
+                                          double* bR) {
+  const double ox = sqx * sqx, oy = sqy * sqy;
+  const double d2 = fma(X, X, oy);
+  const double dl = sqrt_g(d2);
+  const double idl = rcp(dl);
+  const double isg = d2 * dl * ia * ia * rcp(ox * oy);
+  const double sgii = dl * ia * rcp(dir == 0 ? sqx : sqy);
+  const int iv = 1 + dir;
+  const double phiL = qL[0] * isg, phiR = qR[0] * isg;
+  const double iL = rcp(qL[0] * sgii), iR = rcp(qR[0] * sgii);
+  const double upL = qL[iv] * iL, upR = qR[iv] * iR;
+  const double sL = sqrt_g(phiL), sR = sqrt_g(phiR);
+  const double c = 0.5 * (sL + sR);
+  const double ic = rcp(c);
+  const double ms = 0.5 * (upL + upR - (phiR - phiL) * ic);
+  const double ps = 0.5 * (phiL + phiR - c * (upR - upL));
+  const double mm = ms * sgii;
+  const double am = fabs(mm);
+  const double sg = mm > 0.0 ? 1.0 : (mm < 0.0 ? -1.0 : 0.0);
+  // F_v = 1/2((mm + am) qL_v + (mm - am) qR_v) + pressure
+  double mmb = 0.0, amb = 0.0;
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    bL[v] += 0.5 * (mm + am) * mu[v];
+    bR[v] += 0.5 * (mm - am) * mu[v];
+    mmb += 0.5 * (qL[v] + qR[v]) * mu[v];
+    amb -= 0.5 * (qR[v] - qL[v]) * mu[v];
+  }
+  mmb += amb * sg;
+  const double prb = dir == 0 ? mu[1] * oy + mu[2] * X * Y : mu[1] * X * Y + mu[2] * ox;
+  const double psb = prb * ps * idl;
+  const double msb = mmb * sgii;
+  double phiLb = 0.5 * psb, phiRb = 0.5 * psb;
+  double cb = -0.5 * psb * (upR - upL);
+  double upRb = -0.5 * psb * c, upLb = 0.5 * psb * c;
+  upLb += 0.5 * msb;
+  upRb += 0.5 * msb;
+  phiRb -= 0.5 * msb * ic;
+  phiLb += 0.5 * msb * ic;
+  const double icb = -0.5 * msb * (phiR - phiL);
+  cb -= icb * ic * ic;
+  phiLb += 0.5 * cb * 0.5 / sL;
+  phiRb += 0.5 * cb * 0.5 / sR;
+  bL[iv] += upLb * iL;
+  bL[0] -= upLb * upL / qL[0];
+  bR[iv] += upRb * iR;
+  bR[0] -= upRb * upR / qR[0];
+  bL[0] += phiLb * isg;
+  bR[0] += phiRb * isg;
+}
+
+// reverse mode of sources(): given (s1b, s2b) = dL/d(s1, s2), accumulate dL/dQ
+__device__ __forceinline__ void sources_adj(double Q0, double Q1, double Q2, double X, double Y, double Lc,
+                                            double omega2, double s1b, double s2b, double* Qb) {
+  const double X2 = X * X, Y2 = Y * Y;
+  const double id2 = rcp(1.0 + X2 + Y2);
+  const double iq = 2.0 * rcp(Q0);
+  const double A1 = Y * (1.0 + Y2) * Q1 * Q2 - X * Y2 * Q1 * Q1;
+  const double A2 = X * (1.0 + X2) * Q1 * Q2 - X2 * Y * Q2 * Q2;
+  const double f = omega2 * Lc;
+  const double m1b = s1b * id2, c1b = s1b * id2, m2b = s2b * id2, c2b = s2b * id2;
+  Qb[1] += c1b * (-f * X * Y) + c2b * (-f * (1.0 + X2));
+  Qb[2] += c1b * (f * (1.0 + Y2)) + c2b * (f * X * Y);
+  const double iqb = m1b * A1 + m2b * A2;
+  const double A1b = m1b * iq, A2b = m2b * iq;
+  Qb[1] += A1b * (Y * (1.0 + Y2) * Q2 - 2.0 * X * Y2 * Q1) + A2b * (X * (1.0 + X2) * Q2);
+  Qb[2] += A1b * (Y * (1.0 + Y2) * Q1) + A2b * (X * (1.0 + X2) * Q1 - 2.0 * X2 * Y * Q2);
+  Qb[0] -= iqb * iq * iq * 0.5;
+}
+
+// point number of side sd (0 left, 1 right, 2 bottom, 3 top), Gauss node h
+template <int M>
+__device__ __forceinline__ int side_pt(int sd, int h) { return sd * M + h; }
+
+// ---------------------------------------------------------------------------
+// k_vjp_traces: T[(c*NP + pt)*3 + v]
+// ---------------------------------------------------------------------------
+template <int K, bool W, int M>
+__global__ __launch_bounds__(64) void k_vjp_traces(const double* __restrict__ tab_, GridScalars gs,
+                                                    const double* __restrict__ q, double* __restrict__ T) {
+  using C = Cfg<K, W, M>;
+  constexpr int NP = 4 * M + M * M;
+  const cdp tab = (cdp)tab_;
+  const int n = gs.n, P = gs.P;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 6 * n * n) return;
+  const int p = c / (n * n), j = (c / n) % n, i = c % n;
+  const size_t vs = (size_t)6 * P * P;
+  const double* c0 = q + (size_t)p * P * P + (size_t)(j + C::R) * P + (i + C::R);
+  double* out = T + (size_t)c * NP * 3;
+#pragma unroll 1
+  for (int v = 0; v < 3; ++v) {
+    auto at = [&](int dy, int dx) -> double { return c0[v * vs + dy * P + dx]; };
+    double kap[W ? C::S : 1];
+    if constexpr (W) weno_kappa<K, W, M>(tab, gs.eps, at, [&](int jj, double x) { kap[jj] = x; });
+    auto kf = [&](int jj) -> double { return kap[jj]; };
+    double xr[C::XR];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      xpass<K, W, M>(tab, sd, at, xr);
+#pragma unroll
+      for (int h = 0; h < M; ++h) out[(sd * M + h) * 3 + v] = point<K, W, M>(tab, 2 + h, sd * M + h, xr, kf);
+    }
+#pragma unroll 1
+    for (int h = 0; h < M; ++h) {
+      xpass<K, W, M>(tab, 2 + h, at, xr);
+      out[(2 * M + h) * 3 + v] = point<K, W, M>(tab, 0, 2 * M + h, xr, kf);
+      out[(3 * M + h) * 3 + v] = point<K, W, M>(tab, 1, 3 * M + h, xr, kf);
+#pragma unroll
+      for (int w = 0; w < M; ++w)
+        out[(4 * M + w * M + h) * 3 + v] = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+    }
+  }
+}
+
+// the converted neighbour trace at panel side sd, position t, Gauss node h of panel p
+template <int M>
+__device__ __forceinline__ void outside_state(cdp tab, cip itab, const TabOffsets& O, int n, int P, int r,
+                                              const double* __restrict__ T, int p, int sd, int t, int h,
+                                              double* out, cdp* conv, int* bcell, int* bpt) {
+  constexpr int NP = 4 * M + M * M;
+  const int idx = (p * 4 + sd) * n + t;
+  const int off = itab[O.i_cell + idx];
+  const int B = off / (P * P), jb = (off / P) % P - r, ib = off % P - r;
+  const int bs = itab[O.i_side + idx];
+  const int hb = itab[O.i_rev + idx] ? M - 1 - h : h;
+  const int cb = (B * n + jb) * n + ib;
+  const int pt = bs * M + hb;
+  const double* src = T + ((size_t)cb * NP + pt) * 3;
+  cdp cv = tab + O.bt_conv + ((size_t)idx * M + h) * 5;
+  out[0] = cv[0] * src[0];
+  out[1] = cv[1] * src[1] + cv[2] * src[2];
+  out[2] = cv[3] * src[1] + cv[4] * src[2];
+  *conv = cv;
+  *bcell = cb;
+  *bpt = pt;
+}
+
+// ---------------------------------------------------------------------------
+// k_vjp_points: Lam[(c*NP + pt)*3 + v] = dL/d(point value)
+// ---------------------------------------------------------------------------
+template <int K, bool W, int M>
+__global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ tab_, const int32_t* __restrict__ itab_,
+                                                    GridScalars gs, const double* __restrict__ T,
+                                                    const double* __restrict__ w, double* __restrict__ Lam) {
+  using C = Cfg<K, W, M>;
+  constexpr int NP = 4 * M + M * M;
+  const cdp tab = (cdp)tab_;
+  const cip itab = (cip)itab_;
+  const int n = gs.n, P = gs.P;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 6 * n * n) return;
+  const TabOffsets O = tab_offsets(K, W, M, n);
+  const int p = c / (n * n), j = (c / n) % n, i = c % n;
+  const double invd = gs.inv_delta, ia = 1.0 / gs.radius;
+  const size_t nn = (size_t)n * n;
+  auto wv = [&](int v, int cc) -> double { return w[(size_t)v * 6 * nn + cc]; };
+  const double* own = T + (size_t)c * NP * 3;
+  double* lam = Lam + (size_t)c * NP * 3;
+  cdp Xg = tab + O.Xg, sqg = tab + O.sqg, Xe = tab + O.Xe, sqe = tab + O.sqe, gw = tab + C::O.gw;
+#pragma unroll 1
+  for (int sd = 0; sd < 4; ++sd) {
+    // neighbour inside the panel, flux cotangent factor
+    const int ni = i + (sd == 0 ? -1 : sd == 1 ? 1 : 0);
+    const int nj = j + (sd == 2 ? -1 : sd == 3 ? 1 : 0);
+    const bool inside = ni >= 0 && ni < n && nj >= 0 && nj < n;
+    const int nc = (p * n + nj) * n + ni;
+    const int osd = sd ^ 1;                    // facing side of the neighbour
+    const bool own_is_right = (sd == 0 || sd == 2);
+    double dF[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      const double wc = wv(v, c);
+      const double wn = inside ? wv(v, nc) : 0.0;
+      // flux through this edge adds +F/D to the cell on its right/top and -F/D to the other
+      dF[v] = own_is_right ? (wc - wn) * invd : (wn - wc) * invd;
+    }
+    const int dir = sd < 2 ? 0 : 1;
+    const int e = sd == 0 ? i : sd == 1 ? i + 1 : sd == 2 ? j : j + 1;
+#pragma unroll 1
+    for (int h = 0; h < M; ++h) {
+      double qo[3], qn[3];
+#pragma unroll
+      for (int v = 0; v < 3; ++v) qo[v] = own[(sd * M + h) * 3 + v];
+      if (inside) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) qn[v] = T[((size_t)nc * NP + osd * M + h) * 3 + v];
+      } else {
+        cdp cv;
+        int bc, bp;
+        outside_state<M>(tab, itab, O, n, P, gs.r, T, p, sd, dir == 0 ? j : i, h, qn, &cv, &bc, &bp);
+      }
+      double X, Y, sx, sy;
+      if (dir == 0) { X = Xe[e]; sx = sqe[e]; Y = Xg[j * M + h]; sy = sqg[j * M + h]; }
+      else { X = Xg[i * M + h]; sx = sqg[i * M + h]; Y = Xe[e]; sy = sqe[e]; }
+      double mu[3] = {gw[h] * dF[0], gw[h] * dF[1], gw[h] * dF[2]};
+      double bL[3] = {0, 0, 0}, bR[3] = {0, 0, 0};
+      if (own_is_right) lmars_adj(qn, qo, X, Y, sx, sy, dir, ia, mu, bL, bR);
+      else lmars_adj(qo, qn, X, Y, sx, sy, dir, ia, mu, bL, bR);
+      const double* b = own_is_right ? bR : bL;
+#pragma unroll
+      for (int v = 0; v < 3; ++v) lam[(sd * M + h) * 3 + v] = b[v];
+    }
+  }
+  // sources at the cell Gauss points
+  cdp fc = tab + C::O.fcoef + p * 3;
+#pragma unroll 1
+  for (int vv = 0; vv < M; ++vv)
+#pragma unroll 1
+    for (int h = 0; h < M; ++h) {
+      const int pt = 4 * M + vv * M + h;
+      const double X = Xg[i * M + h], Y = Xg[j * M + vv];
+      const double g2 = gw[h] * gw[vv];
+      double Qb[3] = {0, 0, 0};
+      sources_adj(own[pt * 3 + 0], own[pt * 3 + 1], own[pt * 3 + 2], X, Y, fc[0] + fc[1] * X + fc[2] * Y,
+                  gs.omega2, g2 * wv(1, c), g2 * wv(2, c), Qb);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) lam[pt * 3 + v] = Qb[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_vjp_edges: the neighbour panel's flux at its edge points, adjoint w.r.t.
+// the converted trace, added to the owning cell's point cotangent
+// ---------------------------------------------------------------------------
+template <int K, bool W, int M>
+__global__ __launch_bounds__(64) void k_vjp_edges(const double* __restrict__ tab_, const int32_t* __restrict__ itab_,
+                                                   GridScalars gs, const double* __restrict__ T,
+                                                   const double* __restrict__ w, double* __restrict__ Lam) {
+  using C = Cfg<K, W, M>;
+  constexpr int NP = 4 * M + M * M;
+  const cdp tab = (cdp)tab_;
+  const cip itab = (cip)itab_;
+  const int n = gs.n, P = gs.P;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 24 * n * M) return;
+  const TabOffsets O = tab_offsets(K, W, M, n);
+  const int h = k % M;
+  const int t = (k / M) % n;
+  const int sd = (k / (M * n)) % 4;
+  const int p = k / (M * n * 4);
+  const int i = sd == 0 ? 0 : sd == 1 ? n - 1 : t;
+  const int j = sd == 2 ? 0 : sd == 3 ? n - 1 : t;
+  const int c = (p * n + j) * n + i;
+  const size_t nn = (size_t)n * n;
+  const double invd = gs.inv_delta, ia = 1.0 / gs.radius;
+  cdp Xg = tab + O.Xg, sqg = tab + O.sqg, Xe = tab + O.Xe, sqe = tab + O.sqe, gw = tab + C::O.gw;
+  double qo[3], qn[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) qo[v] = T[((size_t)c * NP + sd * M + h) * 3 + v];
+  cdp cv;
+  int bc, bp;
+  outside_state<M>(tab, itab, O, n, P, gs.r, T, p, sd, t, h, qn, &cv, &bc, &bp);
+  const bool own_is_right = (sd == 0 || sd == 2);
+  const int dir = sd < 2 ? 0 : 1;
+  const int e = sd == 0 ? 0 : sd == 1 ? n : sd == 2 ? 0 : n;
+  double X, Y, sx, sy;
+  if (dir == 0) { X = Xe[e]; sx = sqe[e]; Y = Xg[j * M + h]; sy = sqg[j * M + h]; }
+  else { X = Xg[i * M + h]; sx = sqg[i * M + h]; Y = Xe[e]; sy = sqe[e]; }
+  double mu[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const double wc = w[(size_t)v * 6 * nn + c];
+    mu[v] = gw[h] * (own_is_right ? wc : -wc) * invd;
+  }
+  double bL[3] = {0, 0, 0}, bR[3] = {0, 0, 0};
+  if (own_is_right) lmars_adj(qn, qo, X, Y, sx, sy, dir, ia, mu, bL, bR);
+  else lmars_adj(qo, qn, X, Y, sx, sy, dir, ia, mu, bL, bR);
+  const double* ob = own_is_right ? bL : bR;      // cotangent of the converted outside state
+  double* dst = Lam + ((size_t)bc * NP + bp) * 3;
+  dst[0] += cv[0] * ob[0];
+  dst[1] += cv[1] * ob[1] + cv[3] * ob[2];
+  dst[2] += cv[2] * ob[1] + cv[4] * ob[2];
+}
+
+// ---------------------------------------------------------------------------
+// k_vjp_weno: Dl[(c*K*K + o)*3 + v] = cotangent of stencil cell o of cell c
+// ---------------------------------------------------------------------------
+template <int K, bool W, int M>
+__global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_, GridScalars gs,
+                                                  const double* __restrict__ q, const double* __restrict__ Lam,
+                                                  double* __restrict__ Dl) {
+  using C = Cfg<K, W, M>;
+  constexpr int NP = 4 * M + M * M, R = C::R, L = C::L, S = C::S, NR = C::NR, NA = C::NA;
+  const cdp tab = (cdp)tab_;
+  const int n = gs.n, P = gs.P;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 18 * n * n) return;
+  const int v = idx % 3, c = idx / 3;
+  const int p = c / (n * n), j = (c / n) % n, i = c % n;
+  const size_t vs = (size_t)6 * P * P;
+  const double* c0 = q + v * vs + (size_t)p * P * P + (size_t)(j + R) * P + (i + R);
+  auto at = [&](int dy, int dx) -> double { return c0[dy * P + dx]; };
+  const double* lam = Lam + (size_t)c * NP * 3 + v;
+  cdp V = tab + C::O.V, lamq = tab + C::O.lam, wsub = tab + C::O.wsub, gp = tab + C::O.gp, gm = tab + C::O.gm;
+  double dq[K * K];
+#pragma unroll
+  for (int o = 0; o < K * K; ++o) dq[o] = 0.0;
+  // forward smoothness indicators
+  double beta[S];
+#pragma unroll
+  for (int sx = 0; sx < L; ++sx) {
+    double tr[NR][L];
+#pragma unroll
+    for (int row = 0; row < NR; ++row)
+#pragma unroll
+      for (int al = 0; al < L; ++al) {
+        double s = 0;
+#pragma unroll
+        for (int a = 0; a < L; ++a) s = fma(V[(sx * L + al) * L + a], at(row - R, sx - (L - 1) + a), s);
+        tr[row][al] = s;
+      }
+#pragma unroll
+    for (int sy = 0; sy < L; ++sy) {
+      double b = 0;
+#pragma unroll
+      for (int be = 0; be < L; ++be)
+#pragma unroll
+        for (int al = 0; al < L; ++al) {
+          if (al == 0 && be == 0) continue;
+          double cc = 0;
+#pragma unroll
+          for (int bb = 0; bb < L; ++bb) cc = fma(V[(sy * L + be) * L + bb], tr[sy + bb][al], cc);
+          b = fma(lamq[be * L + al] * cc, cc, b);
+        }
+      beta[sy * L + sx] = b;
+    }
+  }
+  double tau = 0;
+#pragma unroll
+  for (int a = 0; a < S; ++a)
+#pragma unroll
+    for (int b = a + 1; b < S; ++b) tau += fabs(beta[a] - beta[b]);
+  const double ctau = 2.0 / (S * (S + 1));
+  tau *= ctau;
+  double kap[S], kapb[S];
+#pragma unroll
+  for (int jj = 0; jj < S; ++jj) {
+    kap[jj] = 1.0 + tau / (beta[jj] + gs.eps);
+    kapb[jj] = 0.0;
+  }
+  // points, grouped by their x-axis coordinate
+#pragma unroll 1
+  for (int px = 0; px < NA; ++px) {
+    double xr[L * NR], xrb[L * NR];
+#pragma unroll
+    for (int sx = 0; sx < L; ++sx)
+#pragma unroll
+      for (int row = 0; row < NR; ++row) {
+        double s = 0;
+#pragma unroll
+        for (int a = 0; a < L; ++a) s = fma(wsub[(sx * NA + px) * L + a], at(row - R, sx - (L - 1) + a), s);
+        xr[sx * NR + row] = s;
+        xrb[sx * NR + row] = 0.0;
+      }
+    const int npy = px < 2 ? M : M + 2;
+#pragma unroll 1
+    for (int k = 0; k < npy; ++k) {
+      int py, pt;
+      if (px < 2) { py = 2 + k; pt = px * M + k; }
+      else {
+        const int h = px - 2;
+        if (k == 0) { py = 0; pt = 2 * M + h; }
+        else if (k == 1) { py = 1; pt = 3 * M + h; }
+        else { py = k; pt = 4 * M + (k - 2) * M + h; }
+      }
+      const double lb = lam[pt * 3];
+      double pv[S];
+      double ap = 0, dp = 0, am = 0, dm = 0;
+#pragma unroll
+      for (int sy = 0; sy < L; ++sy)
+#pragma unroll
+        for (int sx = 0; sx < L; ++sx) {
+          double s = 0;
+#pragma unroll
+          for (int b = 0; b < L; ++b) s = fma(wsub[(sy * NA + py) * L + b], xr[sx * NR + sy + b], s);
+          const int jj = sy * L + sx;
+          pv[jj] = s;
+          ap = fma(gp[pt * S + jj] * kap[jj], s, ap);
+          dp = fma(gp[pt * S + jj], kap[jj], dp);
+          am = fma(gm[pt * S + jj] * kap[jj], s, am);
+          dm = fma(gm[pt * S + jj], kap[jj], dm);
+        }
+      const double sp = tab[C::O.sp + pt], sm = tab[C::O.sm + pt];
+      const double apb = lb * sp / dp, dpb = -lb * sp * ap / (dp * dp);
+      const double amb = -lb * sm / dm, dmb = lb * sm * am / (dm * dm);
+#pragma unroll
+      for (int sy = 0; sy < L; ++sy)
+#pragma unroll
+        for (int sx = 0; sx < L; ++sx) {
+          const int jj = sy * L + sx;
+          const double g1 = gp[pt * S + jj], g2 = gm[pt * S + jj];
+          kapb[jj] += apb * g1 * pv[jj] + dpb * g1 + amb * g2 * pv[jj] + dmb * g2;
+          const double pb = (apb * g1 + amb * g2) * kap[jj];
+#pragma unroll
+          for (int b = 0; b < L; ++b) xrb[sx * NR + sy + b] += pb * wsub[(sy * NA + py) * L + b];
+        }
+    }
+    // x-pass adjoint
+#pragma unroll
+    for (int sx = 0; sx < L; ++sx)
+#pragma unroll
+      for (int row = 0; row < NR; ++row)
+#pragma unroll
+        for (int a = 0; a < L; ++a)
+          dq[row * K + (sx + a)] += wsub[(sx * NA + px) * L + a] * xrb[sx * NR + row];
+  }
+  // kappa_j = 1 + tau/(beta_j + eps)
+  double taub = 0, betab[S];
+#pragma unroll
+  for (int jj = 0; jj < S; ++jj) {
+    const double ib = 1.0 / (beta[jj] + gs.eps);
+    taub += kapb[jj] * ib;
+    betab[jj] = -kapb[jj] * tau * ib * ib;
+  }
+#pragma unroll
+  for (int a = 0; a < S; ++a)
+#pragma unroll
+    for (int b = a + 1; b < S; ++b) {
+      const double d = beta[a] - beta[b];
+      const double sg = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+      betab[a] += taub * ctau * sg;
+      betab[b] -= taub * ctau * sg;
+    }
+  // beta_j = sum lam c^2, c = (V_sy x V_sx) q
+#pragma unroll
+  for (int sx = 0; sx < L; ++sx) {
+    double tr[NR][L], trb[NR][L];
+#pragma unroll
+    for (int row = 0; row < NR; ++row)
+#pragma unroll
+      for (int al = 0; al < L; ++al) {
+        double s = 0;
+#pragma unroll
+        for (int a = 0; a < L; ++a) s = fma(V[(sx * L + al) * L + a], at(row - R, sx - (L - 1) + a), s);
+        tr[row][al] = s;
+        trb[row][al] = 0.0;
+      }
+#pragma unroll
+    for (int sy = 0; sy < L; ++sy) {
+      const double bb_ = betab[sy * L + sx];
+#pragma unroll
+      for (int be = 0; be < L; ++be)
+#pragma unroll
+        for (int al = 0; al < L; ++al) {
+          if (al == 0 && be == 0) continue;
+          double cc = 0;
+#pragma unroll
+          for (int bb = 0; bb < L; ++bb) cc = fma(V[(sy * L + be) * L + bb], tr[sy + bb][al], cc);
+          const double ccb = 2.0 * lamq[be * L + al] * cc * bb_;
+#pragma unroll
+          for (int bb = 0; bb < L; ++bb) trb[sy + bb][al] += V[(sy * L + be) * L + bb] * ccb;
+        }
+    }
+#pragma unroll
+    for (int row = 0; row < NR; ++row)
+#pragma unroll
+      for (int al = 0; al < L; ++al)
+#pragma unroll
+        for (int a = 0; a < L; ++a) dq[row * K + (sx + a)] += V[(sx * L + al) * L + a] * trb[row][al];
+  }
+  double* out = Dl + (size_t)c * K * K * 3 + v;
+#pragma unroll
+  for (int o = 0; o < K * K; ++o) out[o * 3] = dq[o];
+}
+
+// ---------------------------------------------------------------------------
+// k_vjp_gather: cotangent of padded cell (v, p, jj, ii)
+// ---------------------------------------------------------------------------
+template <int K, bool W, int M>
+__global__ __launch_bounds__(256) void k_vjp_gather(const double* __restrict__ tab_, GridScalars gs,
+                                                     const double* __restrict__ Lam, const double* __restrict__ Dl,
+                                                     double* __restrict__ gpad) {
+  using C = Cfg<K, W, M>;
+  constexpr int NP = 4 * M + M * M, R = C::R, NA = C::NA;
+  const cdp tab = (cdp)tab_;
+  const int n = gs.n, P = gs.P;
+  const size_t total = (size_t)18 * P * P;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = idx % P, jj = (idx / P) % P, p = (idx / ((size_t)P * P)) % 6, v = idx / ((size_t)6 * P * P);
+  double acc = 0.0;
+  for (int dy = -R; dy <= R; ++dy) {
+    const int j = jj - R - dy;
+    if (j < 0 || j >= n) continue;
+    for (int dx = -R; dx <= R; ++dx) {
+      const int i = ii - R - dx;
+      if (i < 0 || i >= n) continue;
+      const int c = (p * n + j) * n + i;
+      const int o = (dy + R) * K + (dx + R);
+      if constexpr (W) {
+        acc += Dl[((size_t)c * K * K + o) * 3 + v];
+      } else {
+        // TPP: sum over the cell's points of lam_pt * wy[py][dy] * wx[px][dx]
+        cdp wc = tab + C::O.wc;
+        const double* lam = Lam + (size_t)c * NP * 3 + v;
+        for (int pt = 0; pt < NP; ++pt) {
+          int px, py;
+          if (pt < 2 * M) { px = pt / M; py = 2 + pt % M; }
+          else if (pt < 4 * M) { py = (pt - 2 * M) / M; px = 2 + (pt - 2 * M) % M; }
+          else { const int q2 = pt - 4 * M; px = 2 + q2 % M; py = 2 + q2 / M; }
+          acc += lam[pt * 3] * wc[py * K + (dy + R)] * wc[px * K + (dx + R)];
+        }
+      }
+    }
+  }
+  gpad[idx] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// k_vjp_ghost_t: gq = interior cotangent + G^T (ghost cotangents)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_vjp_ghost_t(int n, int P, int r, const int32_t* __restrict__ gt_ptr,
+                                                      const int32_t* __restrict__ gt_row,
+                                                      const double* __restrict__ gt_val, int64_t gnnz,
+                                                      const double* __restrict__ gpad, double* __restrict__ gq) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 6 * n * n) return;
+  const int p = c / (n * n), j = (c / n) % n, i = c % n;
+  const size_t plane = (size_t)6 * P * P;
+  const size_t off = (size_t)p * P * P + (size_t)(j + r) * P + (i + r);
+  double g0 = gpad[off], g1 = gpad[plane + off], g2 = gpad[2 * plane + off];
+  for (int k = gt_ptr[c]; k < gt_ptr[c + 1]; ++k) {
+    const int d = gt_row[k];
+    const double a0 = gpad[d], a1 = gpad[plane + d], a2 = gpad[2 * plane + d];
+    g0 = fma(gt_val[k], a0, g0);
+    g1 = fma(gt_val[gnnz + k], a1, fma(gt_val[3 * gnnz + k], a2, g1));
+    g2 = fma(gt_val[2 * gnnz + k], a1, fma(gt_val[4 * gnnz + k], a2, g2));
+  }
+  const size_t nn = (size_t)6 * n * n;
+  gq[c] = g0;
+  gq[nn + c] = g1;
+  gq[2 * nn + c] = g2;
+}
+
+// ---------------------------------------------------------------------------
+// Launcher of the whole adjoint
+// ---------------------------------------------------------------------------
+template <int K, bool W, int M>
+static int vjp_t(const VjpArgs& a, int step, void* stream) {
+  const hipStream_t s = (hipStream_t)stream;
+  const GridScalars& gs = a.gs;
+  const int n = gs.n, P = gs.P;
+  const int cells = 6 * n * n;
+  switch (step) {
+    case kVjpTraces:
+      hipLaunchKernelGGL((k_vjp_traces<K, W, M>), dim3((cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q, a.T);
+      break;
+    case kVjpPoints:
+      hipLaunchKernelGGL((k_vjp_points<K, W, M>), dim3((cells + 63) / 64), dim3(64), 0, s, a.tab, a.itab, gs, a.T,
+                         a.w, a.Lam);
+      break;
+    case kVjpEdges: {
+      const int ept = 24 * n * M;
+      hipLaunchKernelGGL((k_vjp_edges<K, W, M>), dim3((ept + 63) / 64), dim3(64), 0, s, a.tab, a.itab, gs, a.T, a.w,
+                         a.Lam);
+      break;
+    }
+    case kVjpWeno:
+      if constexpr (W)
+        hipLaunchKernelGGL((k_vjp_weno<K, W, M>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q, a.Lam,
+                           a.Dl);
+      break;
+    case kVjpGather: {
+      const size_t padded = (size_t)18 * P * P;
+      hipLaunchKernelGGL((k_vjp_gather<K, W, M>), dim3((unsigned)((padded + 255) / 256)), dim3(256), 0, s, a.tab, gs,
+                         a.Lam, a.Dl, a.gpad);
+      break;
+    }
+    case kVjpGhostT:
+      hipLaunchKernelGGL(k_vjp_ghost_t, dim3((cells + 255) / 256), dim3(256), 0, s, n, P, gs.r, a.gt_ptr, a.gt_row,
+                         a.gt_val, a.gt_nnz, a.gpad, a.gq);
+      break;
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_vjp(int k, int weno, const VjpArgs& a, int step, void* stream) {
+  if (!weno) {
+    switch (k) {
+      case 3: return vjp_t<3, false, 2>(a, step, stream);
+      case 5: return vjp_t<5, false, 3>(a, step, stream);
+      case 7: return vjp_t<7, false, 4>(a, step, stream);
+      case 9: return vjp_t<9, false, 5>(a, step, stream);
+      case 11: return vjp_t<11, false, 6>(a, step, stream);
+      case 13: return vjp_t<13, false, 7>(a, step, stream);
+    }
+  } else {
+    switch (k) {
+      case 3: return vjp_t<3, true, 2>(a, step, stream);
+      case 5: return vjp_t<5, true, 3>(a, step, stream);
+    }
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+}  // namespace hope

@@ -74,17 +74,28 @@ class Grid:
         check(lib().hope_tendency(self._h, _ptr(q), _ptr(out), _stream()))
         return out
 
-    def tendency_vjp(self, q: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    def tendency_vjp(self, q: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None,
+                     ws: torch.Tensor | None = None) -> torch.Tensor:
+        """dL/dq (interior) of the tendency at the padded state q, given
+        w = dL/d(dq/dt)."""
         self._check_state(q)
         self._check_field(w)
         if out is None:
             out = torch.empty(3, 6, self.n, self.n, dtype=torch.float64, device=q.device)
         self._check_field(out)
-        check(lib().hope_tendency_vjp(self._h, _ptr(q), _ptr(w), _ptr(out), _stream()))
+        if ws is None:
+            ws = self.vjp_workspace()
+        check(lib().hope_tendency_vjp(self._h, _ptr(q), _ptr(w), _ptr(out), _ptr(ws), ws.numel() * 8, _stream()))
         return out
 
     def workspace(self) -> torch.Tensor:
         return torch.empty(self.layout.rk_workspace_bytes // 8, dtype=torch.float64, device="cuda")
+
+    def vjp_workspace(self) -> torch.Tensor:
+        return torch.empty(self.layout.vjp_workspace_bytes // 8, dtype=torch.float64, device="cuda")
+
+    def rk_vjp_workspace(self) -> torch.Tensor:
+        return torch.empty(self.layout.rk_vjp_workspace_bytes // 8, dtype=torch.float64, device="cuda")
 
     def rk_step(self, q: torch.Tensor, dt: float, scheme: str = "ssp3", ws: torch.Tensor | None = None):
         self._check_state(q)
@@ -93,6 +104,21 @@ class Grid:
         code = {"ssp3": HOPE_RK_SSP3, "ws3": HOPE_RK_WS3}[scheme]
         check(lib().hope_rk_step(self._h, _ptr(q), float(dt), code, _ptr(ws), ws.numel() * 8, _stream()))
         return q
+
+    def rk_step_vjp(self, q: torch.Tensor, dt: float, gout: torch.Tensor, scheme: str = "ssp3",
+                    out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+        """dL/dq^n of one RK step from q^n (padded) and gout = dL/dq^{n+1}."""
+        self._check_state(q)
+        self._check_field(gout)
+        if out is None:
+            out = torch.empty(3, 6, self.n, self.n, dtype=torch.float64, device=q.device)
+        self._check_field(out)
+        if ws is None:
+            ws = self.rk_vjp_workspace()
+        code = {"ssp3": HOPE_RK_SSP3, "ws3": HOPE_RK_WS3}[scheme]
+        check(lib().hope_rk_step_vjp(self._h, _ptr(q), float(dt), code, _ptr(gout), _ptr(out), _ptr(ws),
+                                     ws.numel() * 8, _stream()))
+        return out
 
     def set_launch(self, strip_w: int, seg_h: int):
         check(lib().hope_grid_set_launch(self._h, int(strip_w), int(seg_h)))
@@ -103,7 +129,8 @@ class Grid:
         return a.value, b.value
 
     # ------------------------------------------------------------------
-    KERNELS = {"fill_halo": 0, "edge_traces": 1, "stage": 2}
+    KERNELS = {"fill_halo": 0, "edge_traces": 1, "stage": 2, "vjp_traces": 3, "vjp_points": 4, "vjp_edges": 5,
+               "vjp_weno": 6, "vjp_gather": 7, "vjp_ghost_t": 8}
 
     def profile(self, enable: bool):
         check(lib().hope_grid_profile(self._h, 1 if enable else 0))

@@ -86,6 +86,19 @@ def member_state(n: int, seed: int, nq: int = 2):
     return f.alpha, cell_average(f, n, nq=nq)
 
 
+def cell_sqrt_g(n: int, radius: float = hi.EARTH_RADIUS, nq: int = 4) -> np.ndarray:
+    """(n, n) cell averages over dx dy of sqrtG = a^2 (1+X^2)(1+Y^2) / (1+X^2+Y^2)^(3/2)
+    (the same on every panel); converts a mass cell average to a height."""
+    x0, w0 = np.polynomial.legendre.leggauss(nq)
+    d = 0.5 * math.pi / n
+    xs = ((np.arange(n) + 0.5 - n / 2.0)[:, None] + x0[None, :] / 2) * d
+    X = np.tan(xs)[None, None, :, :]
+    Y = np.tan(xs)[:, :, None, None]
+    sg = radius ** 2 * (1 + X * X) * (1 + Y * Y) / (1 + X * X + Y * Y) ** 1.5
+    w = (w0[None, :, None, None] / 2) * (w0[None, None, None, :] / 2)
+    return (sg * w).sum(axis=(1, 3))
+
+
 def cfl_dt(q: np.ndarray, radius: float = hi.EARTH_RADIUS, cfl: float = 0.5) -> float:
     """Time step for a given Courant number from the largest gravity-wave plus
     advection speed of the state (dt is an input of the method)."""

@@ -40,8 +40,37 @@ def perturbed_balanced(n, seed=0, nq=4):
     return alpha, q * (1.0 + 1e-3 * zeta)
 
 
+def perturbed_member(n, seed=0, nq=4):
+    """A member state with 0.1 % multiplicative noise.  The balanced flow is
+    mirror-symmetric about the plane through the tilted rotation axis, and on
+    that plane pairs of WENO smoothness indicators tie exactly, which puts
+    the kink of |beta_a - beta_b| at the evaluation point: the derivative
+    does not exist there and a gradient comparison is meaningless.  The noise
+    moves every state off such ties."""
+    alpha, q = member(n, seed, nq)
+    zeta = torch.tensor(hi.normal_array(seed + 2000, tuple(q.shape)))
+    return alpha, q * (1.0 + 1e-3 * zeta)
+
+
+def smooth_cell_field(n, seed) -> torch.Tensor:
+    """(6, n, n) values at the cell centres of a seeded smooth random field
+    (spherical harmonics up to degree 20, max |.| = 1)."""
+    from oracle import geometry as geo
+    f = hi.SmoothRandomField(seed=seed)
+    X = np.tan(geo.cell_centres(n, 0) * (0.5 * math.pi / n))
+    return torch.tensor(np.stack([f(geo.panel_xyz(p, X[None, :], X[:, None])) for p in range(6)]))
+
+
+def smooth_perturbed_balanced(n, seed=0, nq=4):
+    """A balanced flow times (1 + 1 % smooth random field): smooth, moving,
+    and without the mirror symmetry of the balanced flow."""
+    alpha, q = balanced(n, seed, nq)
+    return alpha, q * (1.0 + 1e-2 * smooth_cell_field(n, seed + 3000))
+
+
 STATES = {"balanced": balanced, "dam_break": dam_break, "smooth_random": smooth_random, "member": member,
-          "perturbed_balanced": perturbed_balanced}
+          "perturbed_balanced": perturbed_balanced, "perturbed_member": perturbed_member,
+          "smooth_perturbed_balanced": smooth_perturbed_balanced}
 
 
 def oracle_grid(n, order, scheme, alpha):

@@ -1,0 +1,193 @@
+"""GPU parity of the hand-written adjoint: hope_tendency_vjp and
+hope_rk_step_vjp against torch autograd over the FP64 oracle on the same
+seeded state and cotangent, per variable at 1e-11 relative (L-infinity), and
+at the benchmark size the transpose identity <w, J v> = <J^T w, v> against a
+central finite difference of the GPU forward."""
+import pytest
+import torch
+
+import hope_inputs as hi
+from cases import STATES, cfl_dt, oracle_grid, rel_err, to_padded
+from oracle.rk import ssp_rk3, ws_rk3
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def _gpu_grid(n, order, scheme, alpha):
+    from paper_2411_19185_amd import Grid
+    return Grid(n, order, scheme, axis_tilt=alpha)
+
+
+def _oracle_vjp(fn, q, w):
+    qq = q.clone().requires_grad_(True)
+    (fn(qq) * w).sum().backward()
+    return qq.grad
+
+
+VJP_CASES = [
+    # (n, order, scheme, state, seed)
+    (12, 3, "tpp", "perturbed_member", 30),
+    (10, 5, "weno", "perturbed_member", 31),
+    (9, 3, "weno", "dam_break", 32),
+    (12, 11, "tpp", "perturbed_balanced", 33),   # TPP11 differentiation grid
+    (13, 5, "weno", "perturbed_balanced", 34),
+    (7, 5, "tpp", "perturbed_member", 35),
+    (8, 7, "tpp", "perturbed_member", 36),
+    (20, 9, "tpp", "perturbed_member", 37),
+    (26, 13, "tpp", "perturbed_balanced", 38),
+]
+
+
+@pytest.mark.parametrize("n,order,scheme,state,seed", VJP_CASES)
+def test_tendency_vjp_matches_oracle_autograd(n, order, scheme, state, seed):
+    print(f"case n={n} order={order} {scheme} {state} seed={seed}", flush=True)
+    alpha, q = STATES[state](n, seed)
+    w = torch.tensor(hi.normal_array(seed + 500, tuple(q.shape)))
+    og = oracle_grid(n, order, scheme, alpha)
+    ref = _oracle_vjp(og.tendency, q, w)
+    g = _gpu_grid(n, order, scheme, alpha)
+    out = g.tendency_vjp(to_padded(q, g.r), w.cuda())
+    torch.cuda.synchronize()
+    err = rel_err(out, ref)
+    print("rel err", err, flush=True)
+    assert max(err) < TOL, err
+
+
+def test_tendency_vjp_is_repeatable_and_ignores_stale_ghosts():
+    n, order, scheme = 16, 5, "weno"
+    alpha, q = STATES["perturbed_member"](n, 40)
+    w = torch.tensor(hi.normal_array(41, tuple(q.shape))).cuda()
+    g = _gpu_grid(n, order, scheme, alpha)
+    qp = to_padded(q, g.r)
+    a = g.tendency_vjp(qp, w)
+    qp2 = to_padded(q, g.r)
+    qp2.fill_(7.0)
+    g.interior(qp2).copy_(q.cuda())
+    b = g.tendency_vjp(qp2, w)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("n,order,scheme,state,rk,seed", [(12, 3, "tpp", "perturbed_member", "ssp3", 42),
+                                                         (10, 5, "weno", "perturbed_member", "ssp3", 43),
+                                                         (12, 11, "tpp", "perturbed_balanced", "ssp3", 44),
+                                                         (9, 5, "tpp", "perturbed_member", "ws3", 45)])
+def test_rk_step_vjp_matches_oracle_autograd(n, order, scheme, state, rk, seed):
+    print(f"case n={n} order={order} {scheme} {rk}", flush=True)
+    alpha, q = STATES[state](n, seed)
+    w = torch.tensor(hi.normal_array(seed + 500, tuple(q.shape)))
+    dt = cfl_dt(q)
+    og = oracle_grid(n, order, scheme, alpha)
+    step = ssp_rk3 if rk == "ssp3" else ws_rk3
+    ref = _oracle_vjp(lambda x: step(og.tendency, x, dt), q, w)
+    g = _gpu_grid(n, order, scheme, alpha)
+    out = g.rk_step_vjp(to_padded(q, g.r), dt, w.cuda(), rk)
+    torch.cuda.synchronize()
+    err = rel_err(out, ref)
+    print("rel err", err, flush=True)
+    assert max(err) < TOL, err
+
+
+def test_autograd_functions_and_checkpointed_rollout():
+    """The torch.autograd bindings: one tendency, one RK step, and a 6-step
+    rollout with checkpoints every 4 steps (two segments, the last one short)
+    against autograd over the oracle's rollout."""
+    from paper_2411_19185_amd import autograd as ad
+    n, order, scheme = 10, 3, "weno"
+    alpha, q = STATES["perturbed_member"](n, 46)
+    w = torch.tensor(hi.normal_array(47, tuple(q.shape)))
+    dt = cfl_dt(q)
+    og = oracle_grid(n, order, scheme, alpha)
+    g = _gpu_grid(n, order, scheme, alpha)
+
+    qg = q.cuda().requires_grad_(True)
+    (ad.tendency(g, qg) * w.cuda()).sum().backward()
+    assert max(rel_err(qg.grad, _oracle_vjp(og.tendency, q, w))) < TOL
+
+    qg = q.cuda().requires_grad_(True)
+    (ad.rk_step(g, qg, dt) * w.cuda()).sum().backward()
+    assert max(rel_err(qg.grad, _oracle_vjp(lambda x: ssp_rk3(og.tendency, x, dt), q, w))) < TOL
+
+    def oracle_rollout(x):
+        for _ in range(6):
+            x = ssp_rk3(og.tendency, x, dt)
+        return x
+
+    qg = q.cuda().requires_grad_(True)
+    out = ad.rollout(g, qg, dt, 6, checkpoint_every=4)
+    (out * w.cuda()).sum().backward()
+    ref = _oracle_vjp(oracle_rollout, q, w)
+    err = rel_err(qg.grad, ref)
+    print("rollout rel err", err, flush=True)
+    assert max(err) < TOL, err
+    fwd = rel_err(out, oracle_rollout(q))
+    assert max(fwd) < TOL, fwd
+
+
+def test_full_size_weno5_c360_vjp_transpose_identity():
+    """<w_v, (J d)_v> by a central difference of the GPU tendency along a
+    smooth direction d (relative step 1e-7) equals <J^T w_v, d> from the
+    adjoint, for each output variable v, at the benchmark grid and launch.
+    State, direction and cotangents are smooth, so the few kinks of
+    |beta_a - beta_b| that the difference quotient steps over change the sums
+    far less than the tolerance."""
+    from cases import smooth_cell_field
+    n, order, scheme = 360, 5, "weno"
+    print("case C360 WENO5 smooth perturbed balanced flow, transpose identity", flush=True)
+    alpha, q = STATES["smooth_perturbed_balanced"](n, 48, nq=2)
+    d = (q * smooth_cell_field(n, 49)).cuda()
+    zw = smooth_cell_field(n, 50).cuda()
+    g = _gpu_grid(n, order, scheme, alpha)
+    qc = q.cuda()
+    h = 1e-7
+    fp = g.tendency(to_padded((qc + h * d).cpu(), g.r))
+    fm = g.tendency(to_padded((qc - h * d).cpu(), g.r))
+    jd = (fp - fm) / (2 * h)
+    qp = to_padded(q, g.r)
+    for v in range(3):
+        w = torch.zeros_like(jd)
+        w[v] = zw / jd[v].abs().max()
+        lhs = float((jd * w).sum())
+        rhs = float((g.tendency_vjp(qp, w) * d).sum())
+        print("var", v, "lhs", lhs, "rhs", rhs, "rel", abs(lhs - rhs) / abs(rhs), flush=True)
+        assert abs(lhs - rhs) <= 1e-6 * abs(rhs), (v, lhs, rhs)
+
+
+def test_full_jacobian_tpp11_c12_against_finite_differences():
+    """The whole 2592 x 2592 Jacobian of the TPP11 tendency at C12: columns by
+    central differences of the GPU forward (relative step 1e-6 of each input
+    component), rows by the GPU adjoint with unit cotangents."""
+    n, order, scheme = 12, 11, "tpp"
+    print("case C12 TPP11 full Jacobian", flush=True)
+    alpha, q = STATES["perturbed_balanced"](n, 51)
+    g = _gpu_grid(n, order, scheme, alpha)
+    N = q.numel()
+    qc = to_padded(q, g.r)
+    base = g.interior(qc).clone()
+    h = 1e-6
+    Jfd = torch.empty(N, N, dtype=torch.float64, device="cuda")
+    flat = base.reshape(-1)
+    r = g.r
+    for col in range(N):
+        step = h * abs(float(flat[col]))
+        v, rest = divmod(col, 6 * n * n)
+        p, rest = divmod(rest, n * n)
+        j, i = divmod(rest, n)
+        qp = qc.clone()
+        qp[v, p, j + r, i + r] += step
+        qm = qc.clone()
+        qm[v, p, j + r, i + r] -= step
+        Jfd[:, col] = ((g.tendency(qp) - g.tendency(qm)) / (2 * step)).reshape(-1)
+    Jad = torch.empty(N, N, dtype=torch.float64, device="cuda")
+    e = torch.zeros(N, dtype=torch.float64, device="cuda")
+    for row in range(N):
+        e.zero_()
+        e[row] = 1.0
+        Jad[row] = g.tendency_vjp(qc, e.view(3, 6, n, n)).reshape(-1)
+    torch.cuda.synchronize()
+    scale = Jad.abs().amax(dim=0).clamp_min(1e-300)
+    err = float(((Jfd - Jad).abs().amax(dim=0) / scale).max())
+    print("max column-relative error", err, flush=True)
+    assert err < 1e-6, err
