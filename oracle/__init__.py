@@ -41,7 +41,8 @@ READINGS = {
            "exact tie (diagonal of a corner ghost block) the two owners' "
            "converted interpolants are averaged; containing cell by floor, "
            "clamped; central k x k stencil in the owner's padded array",
-    "ghost_fixed_point": "ghost fixed point iterated to convergence (relative change < 1e-16)",
+    "ghost_fixed_point": "ghost fixed point iterated until the relative change of every "
+           "variable is below 1e-15, then three more sweeps",
     "ghost_conversion_order": "interpolate in the owner's variables, convert at each GQP, then average",
     "panel_edge_flux": "at a panel-edge EQP the outside state is the neighbour panel's own "
            "inner trace, converted; each panel evaluates its own flux",
