@@ -175,6 +175,63 @@ int hope_grid_profile_read(hope_grid* grid, int32_t kernel, double* total_ms, in
 int hope_inspect_ghost_map(const hope_grid_desc* desc, int64_t* rows, int64_t* nnz, int32_t* sweeps,
                            int32_t* dst, int32_t* ptr, int32_t* col, double* val);
 
+/* ------------------------------------------------------------------------
+ * Batched ensemble.  Members of one order and scheme, on grids of any
+ * resolutions (members may share a grid), advanced together: each kernel of
+ * a stage (ghost fill, panel-edge traces, fused stage) is one launch over all
+ * members, so a whole Runge-Kutta step is 9 launches whatever the member
+ * count, and no call below except create / set_launch / destroy allocates or
+ * synchronises: the stage and step calls can be captured in a HIP graph.
+ * Each member's result is bitwise the one hope_rk_step / hope_tendency give
+ * on its own grid (with its own axis tilt).
+ *
+ * States of all members live in one caller-owned buffer q_all: member i's
+ * padded state [3][6][P_i][P_i] starts at element state_offsets[i]; fields
+ * (tendencies) likewise at field_offsets[i] of an unpadded buffer.
+ * ------------------------------------------------------------------------ */
+typedef struct hope_batch hope_batch;
+
+typedef struct hope_batch_info {
+  int32_t n_members, n_grids;
+  int64_t state_elems;         /* length of q_all (elements) */
+  int64_t field_elems;         /* length of an unpadded field buffer */
+  int64_t rk_workspace_bytes;  /* workspace of the stage / step calls (two state sets) */
+  int64_t items;               /* fused-stage work items per launch */
+  int64_t blocks;              /* workgroups of the fused stage (0: one per item) */
+  int64_t ghost_rows;          /* ghost rows of all distinct grids */
+} hope_batch_info;
+
+/* grids[i]: the grid of member i (they must outlive the batch).  axis_tilt:
+ * per-member tilt of the rotation axis (radians), or NULL to use each grid's
+ * own.  Allocates device tables; synchronous. */
+int hope_batch_create(const hope_grid* const* grids, int32_t n_members, const double* axis_tilt,
+                      hope_batch** out);
+void hope_batch_destroy(hope_batch* batch);
+/* state_offsets / field_offsets: NULL or arrays of n_members elements. */
+int hope_batch_layout(const hope_batch* batch, hope_batch_info* out, int64_t* state_offsets,
+                      int64_t* field_offsets);
+/* Work-item shape per member (strip width 1..62, segment height 1..n; NULL
+ * keeps the current values) and the fused-stage grid size (0: one workgroup
+ * per item; otherwise that many workgroups stride the item list).  Rebuilds
+ * and uploads the item list: allocates and synchronises.  Any values give
+ * bitwise identical results. */
+int hope_batch_set_launch(hope_batch* batch, const int32_t* strip_w, const int32_t* seg_h, int32_t blocks);
+int hope_batch_get_launch(const hope_batch* batch, int32_t* strip_w, int32_t* seg_h, int32_t* blocks);
+/* Tendencies (3.1) of all members: fills the ghost rings of q_all, writes
+ * dqdt_all (unpadded, at field_offsets). */
+int hope_batch_tendency(const hope_batch* batch, double* q_all, double* dqdt_all, void* stream);
+/* Stage `stage` (0, 1, 2) of one Runge-Kutta step (section 3.5) of every
+ * member with its own time step dt[i] (device array of n_members doubles, read
+ * when the stage runs, so a captured graph can be replayed with new steps).
+ * Stage 0 reads q_all and writes the first workspace state set, stage 1 reads
+ * it and writes the second, stage 2 reads the second and writes q_all.
+ * ws: at least layout.rk_workspace_bytes. */
+int hope_batch_rk_stage(const hope_batch* batch, int32_t stage, int32_t scheme, double* q_all,
+                        const double* dt, double* ws, size_t ws_bytes, void* stream);
+/* The three stages in order. */
+int hope_batch_rk_step(const hope_batch* batch, int32_t scheme, double* q_all, const double* dt, double* ws,
+                       size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,6 +61,19 @@ class Layout(ctypes.Structure):
     ]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_members", ctypes.c_int32),
+        ("n_grids", ctypes.c_int32),
+        ("state_elems", ctypes.c_int64),
+        ("field_elems", ctypes.c_int64),
+        ("rk_workspace_bytes", ctypes.c_int64),
+        ("items", ctypes.c_int64),
+        ("blocks", ctypes.c_int64),
+        ("ghost_rows", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -79,6 +92,15 @@ _SIGS = {
     "hope_grid_get_launch": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "hope_grid_profile": (_I32, [_P, _I32]),
     "hope_grid_profile_read": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "hope_batch_create": (_I32, [ctypes.POINTER(_P), _I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_P)]),
+    "hope_batch_destroy": (None, [_P]),
+    "hope_batch_layout": (_I32, [_P, ctypes.POINTER(BatchInfo), ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int64)]),
+    "hope_batch_set_launch": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _I32]),
+    "hope_batch_get_launch": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "hope_batch_tendency": (_I32, [_P, _P, _P, _P]),
+    "hope_batch_rk_stage": (_I32, [_P, _I32, _I32, _P, _P, _P, ctypes.c_size_t, _P]),
+    "hope_batch_rk_step": (_I32, [_P, _I32, _P, _P, _P, ctypes.c_size_t, _P]),
     "hope_inspect_ghost_map": (_I32, [ctypes.POINTER(GridDesc), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_I32),
                                       _P, _P, _P, _P]),

@@ -1,0 +1,192 @@
+// Batched ensemble kernels (gfx950, FP64): one launch per kernel covers every
+// member of an ensemble of uneven resolutions.  They run the same device
+// bodies as the single-grid kernels (kernel_bodies.hpp), so a member's result
+// is bitwise the one its own grid gives.
+//
+//  k_fill_halo_batch      ghost fill g = G q (appendix (7.12)) of all members:
+//                         one 16-lane group per ghost row of a grid, applied to
+//                         that grid's members while the row's entries sit in
+//                         registers (G is read once per kHaloChunk members)
+//  k_edge_traces_batch    panel-edge traces (3.26)-(3.29) of all members; each
+//                         member's range is padded to whole wavefronts
+//  k_stage_batch          the fused stage over a flattened list of work items
+//                         (member, panel, strip, segment); with blocks < items
+//                         it is persistent, each workgroup striding the list
+#include <hip/hip_runtime.h>
+
+#include "batch_internal.hpp"
+#include "kernel_bodies.hpp"
+
+namespace hope {
+
+__global__ __launch_bounds__(256) void k_fill_halo_batch(const BatchGrid* __restrict__ grids, int n_grids,
+                                                         int total_rows, const int32_t* __restrict__ mlist,
+                                                         const BatchMember* __restrict__ mem,
+                                                         double* __restrict__ base) {
+  const int row = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 4);
+  if (row >= total_rows) return;   // whole 16-lane group leaves together
+  int gi = 0;
+  while (gi + 1 < n_grids && grids[gi + 1].row_begin <= row) ++gi;
+  const BatchGrid& bg = grids[gi];
+  const GhostDev& g = bg.g;
+  const int r = row - bg.row_begin;
+  const int lane = threadIdx.x & 15;
+  const size_t plane = (size_t)6 * bg.P * bg.P;
+  const int b = g.ptr[r], e = g.ptr[r + 1];
+  const int d = g.dst[r];
+  for (int c0 = 0; c0 < bg.member_count; c0 += kHaloChunk) {
+    const int cnt = min(kHaloChunk, bg.member_count - c0);
+    double* qm[kHaloChunk];
+#pragma unroll
+    for (int t = 0; t < kHaloChunk; ++t) qm[t] = base + mem[mlist[bg.member_begin + c0 + min(t, cnt - 1)]].q_off;
+    double acc[kHaloChunk][3];
+#pragma unroll
+    for (int t = 0; t < kHaloChunk; ++t) acc[t][0] = acc[t][1] = acc[t][2] = 0.0;
+    for (int k = b + lane; k < e; k += 16) {
+      const int c = g.col[k];
+      const double v0 = g.val[k], v1 = g.val[g.nnz + k], v2 = g.val[2 * g.nnz + k];
+      const double v3 = g.val[3 * g.nnz + k], v4 = g.val[4 * g.nnz + k];
+#pragma unroll
+      for (int t = 0; t < kHaloChunk; ++t) {
+        if (t < cnt) {
+          const double* q = qm[t];
+          const double a0 = q[c], a1 = q[plane + c], a2 = q[2 * plane + c];
+          acc[t][0] = fma(v0, a0, acc[t][0]);
+          acc[t][1] = fma(v1, a1, fma(v2, a2, acc[t][1]));
+          acc[t][2] = fma(v3, a1, fma(v4, a2, acc[t][2]));
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kHaloChunk; ++t) {
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) {
+        acc[t][0] += __shfl_xor(acc[t][0], off, 16);
+        acc[t][1] += __shfl_xor(acc[t][1], off, 16);
+        acc[t][2] += __shfl_xor(acc[t][2], off, 16);
+      }
+      if (lane == 0 && t < cnt) {
+        double* q = qm[t];
+        q[d] = acc[t][0];
+        q[plane + d] = acc[t][1];
+        q[2 * plane + d] = acc[t][2];
+      }
+    }
+  }
+}
+
+// member whose flattened range [edge_begin, next edge_begin) holds idx
+__device__ __forceinline__ int member_of_edge(const BatchMember* __restrict__ mem, int n_members, int idx) {
+  int lo = 0, hi = n_members - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (mem[mid].edge_begin <= idx) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int K, bool W, int M>
+__global__ __launch_bounds__(64) void k_edge_traces_batch(const BatchMember* __restrict__ mem, int n_members,
+                                                           int total_edges, const double* __restrict__ in,
+                                                           double* __restrict__ bt) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total_edges) return;
+  // every member's range starts on a wavefront boundary, so the member is uniform
+  const int mi = __builtin_amdgcn_readfirstlane(member_of_edge(mem, n_members, idx));
+  const BatchMember& bm = mem[mi];
+  const int local = idx - bm.edge_begin;
+  if (local >= 24 * bm.gs.n) return;
+  edge_trace<K, W, M>((cdp)bm.tab, (cip)bm.itab, bm.gs, in + bm.q_off, bt + bm.bt_off, local);
+}
+
+template <int K, bool W, int M>
+__global__ __launch_bounds__(64, HOPE_STAGE_WAVES) void k_stage_batch(const BatchMember* __restrict__ mem,
+                                                                      const int32_t* __restrict__ items,
+                                                                      int n_items, BatchStage S) {
+  __shared__ StageSmem<K, W, M> sm;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int code = __builtin_amdgcn_readfirstlane(items[it]);
+    const int mi = code >> 20, local = code & 0xFFFFF;
+    const BatchMember& bm = mem[mi];
+    StageArgs A;
+    A.q = S.in + bm.q_off;
+    A.qn = S.qn ? S.qn + bm.q_off : nullptr;
+    A.out = S.out + (S.out_padded ? bm.q_off : bm.f_off);
+    A.bt = S.bt + bm.bt_off;
+    A.ca = S.ca;
+    A.cb = S.cb;
+    A.cc = S.dt ? S.cs * S.dt[mi] : S.cs;
+    A.out_padded = S.out_padded;
+    A.strip_w = bm.strip_w;
+    A.seg_h = bm.seg_h;
+    A.n_strips = bm.n_strips;
+    A.n_segs = bm.n_segs;
+    if (it != (int)blockIdx.x) __syncthreads();   // the previous item's LDS reads are done
+    stage_tile<K, W, M>(bm.tab, (cdp)bm.fcoef, bm.gs, A, local, sm);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+int launch_batch_fill_halo(const BatchGrid* grids, int n_grids, int total_rows, const int32_t* members_by_grid,
+                           const BatchMember* members, double* base, void* stream) {
+  if (total_rows == 0) return 0;
+  const int threads = 256;
+  const int blocks = (int)(((size_t)total_rows * 16 + threads - 1) / threads);
+  hipLaunchKernelGGL(k_fill_halo_batch, dim3(blocks), dim3(threads), 0, (hipStream_t)stream, grids, n_grids,
+                     total_rows, members_by_grid, members, base);
+  return (int)hipGetLastError();
+}
+
+template <int K, bool W, int M>
+static int batch_edges_t(const BatchMember* members, int n_members, int total_edges, const double* in, double* bt,
+                         void* stream) {
+  hipLaunchKernelGGL((k_edge_traces_batch<K, W, M>), dim3((total_edges + 63) / 64), dim3(64), 0,
+                     (hipStream_t)stream, members, n_members, total_edges, in, bt);
+  return (int)hipGetLastError();
+}
+
+template <int K, bool W, int M>
+static int batch_stage_t(const BatchMember* members, const int32_t* items, int n_items, int blocks,
+                         const BatchStage& st, void* stream) {
+  const int grid = (blocks > 0 && blocks < n_items) ? blocks : n_items;
+  hipLaunchKernelGGL((k_stage_batch<K, W, M>), dim3(grid), dim3(64), 0, (hipStream_t)stream, members, items,
+                     n_items, st);
+  return (int)hipGetLastError();
+}
+
+#define HOPE_BATCH_DISPATCH(FN, ...)                  \
+  do {                                                \
+    if (!weno) {                                      \
+      switch (k) {                                    \
+        case 3: return FN<3, false, 2>(__VA_ARGS__);  \
+        case 5: return FN<5, false, 3>(__VA_ARGS__);  \
+        case 7: return FN<7, false, 4>(__VA_ARGS__);  \
+        case 9: return FN<9, false, 5>(__VA_ARGS__);  \
+        case 11: return FN<11, false, 6>(__VA_ARGS__);\
+        case 13: return FN<13, false, 7>(__VA_ARGS__);\
+      }                                               \
+    } else {                                          \
+      switch (k) {                                    \
+        case 3: return FN<3, true, 2>(__VA_ARGS__);   \
+        case 5: return FN<5, true, 3>(__VA_ARGS__);   \
+      }                                               \
+    }                                                 \
+    return (int)hipErrorInvalidValue;                 \
+  } while (0)
+
+int launch_batch_edge_traces(int k, int weno, const BatchMember* members, int n_members, int total_edges,
+                             const double* in, double* bt, void* stream) {
+  if (total_edges == 0) return 0;
+  HOPE_BATCH_DISPATCH(batch_edges_t, members, n_members, total_edges, in, bt, stream);
+}
+
+int launch_batch_stage(int k, int weno, const BatchMember* members, const int32_t* items, int n_items, int blocks,
+                       const BatchStage& st, void* stream) {
+  if (n_items == 0) return 0;
+  HOPE_BATCH_DISPATCH(batch_stage_t, members, items, n_items, blocks, st, stream);
+}
+
+}  // namespace hope

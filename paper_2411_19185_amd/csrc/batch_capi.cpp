@@ -1,0 +1,300 @@
+// C ABI of the batched ensemble (declared in include/hope.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "batch_internal.hpp"
+#include "grid_internal.hpp"
+#include "hope.h"
+
+using namespace hope;
+
+struct hope_batch {
+  int n_members = 0, n_grids = 0, k = 0, weno = 0, m = 0;
+  std::vector<const hope_grid*> member_grid;   // per member
+  std::vector<const hope_grid*> grids;         // distinct grids, in order of first use
+  std::vector<int64_t> q_off, f_off;           // per member
+  int64_t state_elems = 0, field_elems = 0, bt_elems = 0;
+  int total_rows = 0, total_edges = 0, n_items = 0, blocks = 0;
+  std::vector<BatchMember> hmem;               // host copy of the member table
+  BatchMember* mem = nullptr;
+  BatchGrid* dgrids = nullptr;
+  int32_t* mlist = nullptr;
+  int32_t* items = nullptr;
+  double* fcoef = nullptr;
+  double* bt = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+void free_batch(hope_batch* B) {
+  if (!B) return;
+  for (void* p : B->allocs) (void)hipFree(p);
+  if (B->items) (void)hipFree(B->items);
+  delete B;
+}
+
+template <typename T>
+int upload_vec(hope_batch* B, const std::vector<T>& v, T** out) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(1, v.size()) * sizeof(T));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc (batch)");
+  B->allocs.push_back(p);
+  if (!v.empty()) {
+    e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (batch)");
+  }
+  *out = static_cast<T*>(p);
+  return HOPE_OK;
+}
+
+// work items (member << 20 | local item), costliest items first so that the
+// tail of the launch is made of small ones
+int build_items(hope_batch* B) {
+  struct It { int64_t cost; int32_t code; };
+  std::vector<It> its;
+  for (int i = 0; i < B->n_members; ++i) {
+    const BatchMember& bm = B->hmem[i];
+    const int per = 6 * bm.n_strips * bm.n_segs;
+    if (per > (1 << 20)) return fail(HOPE_ERR_INVALID, "too many work items in one member");
+    const int64_t cost = (int64_t)(bm.seg_h + 1) * (bm.strip_w + 2);
+    for (int l = 0; l < per; ++l) its.push_back({cost, (int32_t)((i << 20) | l)});
+  }
+  std::stable_sort(its.begin(), its.end(), [](const It& a, const It& b) { return a.cost > b.cost; });
+  std::vector<int32_t> codes(its.size());
+  for (size_t t = 0; t < its.size(); ++t) codes[t] = its[t].code;
+  if (B->items) (void)hipFree(B->items);
+  B->items = nullptr;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(1, codes.size()) * sizeof(int32_t));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc (batch items)");
+  B->items = static_cast<int32_t*>(p);
+  if (!codes.empty()) {
+    e = hipMemcpy(p, codes.data(), codes.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (batch items)");
+  }
+  B->n_items = (int)codes.size();
+  return HOPE_OK;
+}
+
+int upload_members(hope_batch* B) {
+  hipError_t e = hipMemcpy(B->mem, B->hmem.data(), B->hmem.size() * sizeof(BatchMember), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy (batch members)");
+  return HOPE_OK;
+}
+
+int batch_stage(const hope_batch* B, double* in, const double* qn, double* out, int out_padded, double ca,
+                double cb, double cs, const double* dt, void* stream) {
+  int e = launch_batch_fill_halo(B->dgrids, B->n_grids, B->total_rows, B->mlist, B->mem, in, stream);
+  if (e) return hip_fail((hipError_t)e, "batch fill_halo launch");
+  e = launch_batch_edge_traces(B->k, B->weno, B->mem, B->n_members, B->total_edges, in, B->bt, stream);
+  if (e) return hip_fail((hipError_t)e, "batch edge_traces launch");
+  BatchStage st;
+  st.in = in;
+  st.qn = qn;
+  st.out = out;
+  st.out_padded = out_padded;
+  st.ca = ca;
+  st.cb = cb;
+  st.cs = cs;
+  st.dt = dt;
+  st.bt = B->bt;
+  e = launch_batch_stage(B->k, B->weno, B->mem, B->items, B->n_items, B->blocks, st, stream);
+  if (e) return hip_fail((hipError_t)e, "batch stage launch");
+  return HOPE_OK;
+}
+
+bool misaligned(const void* p) { return reinterpret_cast<uintptr_t>(p) % 8 != 0; }
+
+}  // namespace
+
+extern "C" {
+
+int hope_batch_create(const hope_grid* const* grids, int32_t n_members, const double* axis_tilt, hope_batch** out) {
+  if (!grids || !out) return fail(HOPE_ERR_INVALID, "null argument");
+  *out = nullptr;
+  if (n_members < 1 || n_members > 2047) return fail(HOPE_ERR_INVALID, "n_members must be 1..2047");
+  for (int i = 0; i < n_members; ++i) {
+    if (!grids[i]) return fail(HOPE_ERR_INVALID, "null grid");
+    if (grids[i]->h.k != grids[0]->h.k || grids[i]->h.weno != grids[0]->h.weno)
+      return fail(HOPE_ERR_UNSUPPORTED, "all members must share order and scheme");
+    if (axis_tilt && !std::isfinite(axis_tilt[i])) return fail(HOPE_ERR_INVALID, "axis_tilt not finite");
+  }
+  hope_batch* B = new (std::nothrow) hope_batch();
+  if (!B) return fail(HOPE_ERR_NOMEM, "host allocation");
+  B->n_members = n_members;
+  B->k = grids[0]->h.k;
+  B->weno = grids[0]->h.weno;
+  B->m = grids[0]->h.m;
+  B->member_grid.assign(grids, grids + n_members);
+  std::vector<double> fco(18 * (size_t)n_members);
+  int64_t qo = 0, fo = 0, bo = 0;
+  int eb = 0;
+  B->hmem.resize(n_members);
+  for (int i = 0; i < n_members; ++i) {
+    const hope_grid* G = grids[i];
+    if (std::find(B->grids.begin(), B->grids.end(), G) == B->grids.end()) B->grids.push_back(G);
+    const int n = G->h.n, P = G->h.P;
+    BatchMember& bm = B->hmem[i];
+    bm.tab = G->tab;
+    bm.itab = G->itab;
+    bm.fcoef = nullptr;   // set after upload
+    bm.gs = G->gs;
+    bm.q_off = qo;
+    bm.f_off = fo;
+    bm.bt_off = bo;
+    bm.edge_begin = eb;
+    int sw, strips;
+    balanced_strip(n, &sw, &strips);
+    bm.strip_w = sw;
+    bm.n_strips = strips;
+    bm.seg_h = std::min(8, n);
+    bm.n_segs = (n + bm.seg_h - 1) / bm.seg_h;
+    B->q_off.push_back(qo);
+    B->f_off.push_back(fo);
+    qo += 18LL * P * P;
+    fo += 18LL * n * n;
+    bo += 24LL * n * B->m * 3;
+    eb += ((24 * n + 63) / 64) * 64;
+    if (axis_tilt) coriolis_coefs(axis_tilt[i], &fco[18 * (size_t)i]);
+    else std::copy(G->h.fcoef.begin(), G->h.fcoef.end(), fco.begin() + 18 * (size_t)i);
+  }
+  B->state_elems = qo;
+  B->field_elems = fo;
+  B->bt_elems = bo;
+  B->total_edges = eb;
+  // members grouped by grid, for the ghost fill
+  std::vector<BatchGrid> bgs;
+  std::vector<int32_t> ml;
+  int rows = 0;
+  for (const hope_grid* G : B->grids) {
+    BatchGrid bg;
+    bg.g = G->g;
+    bg.row_begin = rows;
+    bg.member_begin = (int32_t)ml.size();
+    for (int i = 0; i < n_members; ++i)
+      if (grids[i] == G) ml.push_back(i);
+    bg.member_count = (int32_t)ml.size() - bg.member_begin;
+    bg.P = G->h.P;
+    rows += G->g.rows;
+    bgs.push_back(bg);
+  }
+  B->n_grids = (int)bgs.size();
+  B->total_rows = rows;
+  int st = upload_vec(B, fco, &B->fcoef);
+  if (!st) st = upload_vec(B, bgs, &B->dgrids);
+  if (!st) st = upload_vec(B, ml, &B->mlist);
+  if (!st) {
+    for (int i = 0; i < n_members; ++i) B->hmem[i].fcoef = B->fcoef + 18 * (size_t)i;
+    st = upload_vec(B, B->hmem, &B->mem);
+  }
+  if (!st) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<int64_t>(1, bo) * sizeof(double));
+    if (e != hipSuccess) st = hip_fail(e, "hipMalloc (batch traces)");
+    else {
+      B->allocs.push_back(p);
+      B->bt = static_cast<double*>(p);
+    }
+  }
+  if (!st) st = build_items(B);
+  if (st) {
+    free_batch(B);
+    return st;
+  }
+  *out = B;
+  return HOPE_OK;
+}
+
+void hope_batch_destroy(hope_batch* batch) { free_batch(batch); }
+
+int hope_batch_layout(const hope_batch* B, hope_batch_info* out, int64_t* state_offsets, int64_t* field_offsets) {
+  if (!B || !out) return fail(HOPE_ERR_INVALID, "null argument");
+  out->n_members = B->n_members;
+  out->n_grids = B->n_grids;
+  out->state_elems = B->state_elems;
+  out->field_elems = B->field_elems;
+  out->rk_workspace_bytes = 2 * B->state_elems * (int64_t)sizeof(double);
+  out->items = B->n_items;
+  out->blocks = B->blocks;
+  out->ghost_rows = B->total_rows;
+  for (int i = 0; i < B->n_members; ++i) {
+    if (state_offsets) state_offsets[i] = B->q_off[i];
+    if (field_offsets) field_offsets[i] = B->f_off[i];
+  }
+  return HOPE_OK;
+}
+
+int hope_batch_set_launch(hope_batch* B, const int32_t* strip_w, const int32_t* seg_h, int32_t blocks) {
+  if (!B) return fail(HOPE_ERR_INVALID, "null argument");
+  if (blocks < 0) return fail(HOPE_ERR_INVALID, "blocks must be >= 0");
+  for (int i = 0; i < B->n_members; ++i) {
+    const int n = B->hmem[i].gs.n;
+    const int sw = strip_w ? strip_w[i] : B->hmem[i].strip_w;
+    const int sh = seg_h ? seg_h[i] : B->hmem[i].seg_h;
+    if (sw < 1 || sw > 62 || sh < 1 || sh > n) return fail(HOPE_ERR_INVALID, "launch shape out of range");
+  }
+  for (int i = 0; i < B->n_members; ++i) {
+    BatchMember& bm = B->hmem[i];
+    const int n = bm.gs.n;
+    if (strip_w) bm.strip_w = strip_w[i];
+    if (seg_h) bm.seg_h = seg_h[i];
+    bm.n_strips = (n + bm.strip_w - 1) / bm.strip_w;
+    bm.n_segs = (n + bm.seg_h - 1) / bm.seg_h;
+  }
+  B->blocks = blocks;
+  int st = upload_members(B);
+  if (!st) st = build_items(B);
+  if (st) return st;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  return HOPE_OK;
+}
+
+int hope_batch_get_launch(const hope_batch* B, int32_t* strip_w, int32_t* seg_h, int32_t* blocks) {
+  if (!B) return fail(HOPE_ERR_INVALID, "null argument");
+  for (int i = 0; i < B->n_members; ++i) {
+    if (strip_w) strip_w[i] = B->hmem[i].strip_w;
+    if (seg_h) seg_h[i] = B->hmem[i].seg_h;
+  }
+  if (blocks) *blocks = B->blocks;
+  return HOPE_OK;
+}
+
+int hope_batch_tendency(const hope_batch* B, double* q_all, double* dqdt_all, void* stream) {
+  if (!B || !q_all || !dqdt_all) return fail(HOPE_ERR_INVALID, "null argument");
+  if (misaligned(q_all) || misaligned(dqdt_all)) return fail(HOPE_ERR_INVALID, "misaligned buffer");
+  return batch_stage(B, q_all, nullptr, dqdt_all, 0, 0.0, 0.0, 1.0, nullptr, stream);
+}
+
+int hope_batch_rk_stage(const hope_batch* B, int32_t stage, int32_t scheme, double* q_all, const double* dt,
+                        double* ws, size_t ws_bytes, void* stream) {
+  if (!B || !q_all || !dt || !ws) return fail(HOPE_ERR_INVALID, "null argument");
+  if (scheme != HOPE_RK_SSP3 && scheme != HOPE_RK_WS3) return fail(HOPE_ERR_INVALID, "bad RK scheme");
+  if (stage < 0 || stage > 2) return fail(HOPE_ERR_INVALID, "stage must be 0, 1 or 2");
+  if (ws_bytes < 2 * (size_t)B->state_elems * sizeof(double)) return fail(HOPE_ERR_INVALID, "workspace too small");
+  if (misaligned(q_all) || misaligned(dt) || misaligned(ws)) return fail(HOPE_ERR_INVALID, "misaligned buffer");
+  double a[3], b[3], cs[3];
+  rk_coefs(scheme, a, b, cs);
+  double* w0 = ws;
+  double* w1 = ws + B->state_elems;
+  switch (stage) {
+    case 0: return batch_stage(B, q_all, nullptr, w0, 1, a[0], b[0], cs[0], dt, stream);
+    case 1: return batch_stage(B, w0, q_all, w1, 1, a[1], b[1], cs[1], dt, stream);
+    default: return batch_stage(B, w1, q_all, q_all, 1, a[2], b[2], cs[2], dt, stream);
+  }
+}
+
+int hope_batch_rk_step(const hope_batch* B, int32_t scheme, double* q_all, const double* dt, double* ws,
+                       size_t ws_bytes, void* stream) {
+  for (int s = 0; s < 3; ++s)
+    if (int st = hope_batch_rk_stage(B, s, scheme, q_all, dt, ws, ws_bytes, stream)) return st;
+  return HOPE_OK;
+}
+
+}  // extern "C"

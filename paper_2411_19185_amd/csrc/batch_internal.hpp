@@ -1,0 +1,58 @@
+// Internal declarations of the batched ensemble (batch.hip, batch_capi.cpp):
+// members of one or several grids (uneven resolutions) advanced by one launch
+// per kernel over all members.
+#pragma once
+
+#include "hope_internal.hpp"
+
+namespace hope {
+
+// One ensemble member, as the device sees it.  Offsets are in elements from
+// the base pointers of a launch (states: q_all or one workspace state set;
+// fields: the unpadded output).
+struct BatchMember {
+  const double* tab;        // the member's grid tables (shared by members of one grid)
+  const int32_t* itab;
+  const double* fcoef;      // this member's 6 x 3 Coriolis coefficients
+  GridScalars gs;
+  int64_t q_off;            // padded state [3][6][P][P]
+  int64_t f_off;            // unpadded field [3][6][n][n]
+  int64_t bt_off;           // panel-edge traces [24 n m][3]
+  int32_t edge_begin;       // first flattened panel-edge side (multiple of 64)
+  int32_t strip_w, seg_h, n_strips, n_segs;
+};
+
+// The members of one grid, for the ghost fill: rows of that grid's G are
+// applied to all of its members while the row's entries are in registers.
+struct BatchGrid {
+  GhostDev g;
+  int32_t row_begin;        // first flattened ghost row
+  int32_t member_begin;     // into the member list grouped by grid
+  int32_t member_count;
+  int32_t P;
+};
+
+// One launch of a stage: q_{s+1} = ca q^n + cb q_s + cs * dt[member] * L(q_s)
+// (cs alone when dt is null).
+struct BatchStage {
+  const double* in;         // base of the stage inputs (padded)
+  const double* qn;         // base of q^n (padded) or null
+  double* out;              // base of the outputs
+  int32_t out_padded;       // 1: padded states at q_off, 0: fields at f_off
+  double ca, cb, cs;
+  const double* dt;         // per member, device, or null
+  double* bt;               // base of the panel-edge trace scratch
+};
+
+// All enqueue on `stream`; return a hipError_t value.
+int launch_batch_fill_halo(const BatchGrid* grids, int n_grids, int total_rows, const int32_t* members_by_grid,
+                           const BatchMember* members, double* base, void* stream);
+int launch_batch_edge_traces(int k, int weno, const BatchMember* members, int n_members, int total_edges,
+                             const double* in, double* bt, void* stream);
+int launch_batch_stage(int k, int weno, const BatchMember* members, const int32_t* items, int n_items, int blocks,
+                       const BatchStage& st, void* stream);
+
+// members per ghost-fill pass (the accumulators of one pass live in registers)
+constexpr int kHaloChunk = 8;
+
+}  // namespace hope

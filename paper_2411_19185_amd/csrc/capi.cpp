@@ -7,13 +7,15 @@
 #include <string>
 
 #include "hope.h"
-#include "hope_internal.hpp"
+#include "grid_internal.hpp"
 #include "vjp_internal.hpp"
 
 using namespace hope;
 
+namespace hope {
 namespace {
 thread_local std::string g_last_error;
+}
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
@@ -23,30 +25,9 @@ int fail(int code, const std::string& msg) {
 int hip_fail(hipError_t e, const char* what) {
   return fail(HOPE_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
-}  // namespace
 
-struct hope_grid {
-  HostTables h;
-  const double* tab = nullptr;     // all constant tables, see tab_offsets
-  const int32_t* itab = nullptr;   // panel-edge map
-  GridScalars gs{};
-  GhostDev g{};
-  std::vector<void*> allocs;
-  size_t device_bytes = 0;
-  double* bt = nullptr;      // panel-edge trace scratch, 24*n*m*3
-  int strip_w = 62, seg_h = 8;
-  // G^T by interior cell (adjoint of the ghost fill)
-  const int32_t* gt_ptr = nullptr;
-  const int32_t* gt_row = nullptr;
-  const double* gt_val = nullptr;
-  int64_t gt_nnz = 0;
-  // optional per-kernel timing with HIP events on the launch stream
-  bool timing = false;
-  std::vector<hipEvent_t> pool;
-  struct Rec { int kind; int a, b; };
-  std::vector<Rec> recs;
-  size_t used = 0;
-};
+const char* last_error() { return g_last_error.c_str(); }
+}  // namespace hope
 
 namespace {
 // kernels: 0 ghost fill, 1 edge traces, 2 stage
@@ -103,11 +84,15 @@ static void free_grid(hope_grid* G) {
   delete G;
 }
 
+void hope::balanced_strip(int n, int* strip_w, int* strips) {
+  *strips = (n + 61) / 62;
+  *strip_w = (n + *strips - 1) / *strips;          // balance the strips
+}
+
 static void default_launch(hope_grid* G) {
   const int n = G->h.n;
-  int sw = n < 62 ? n : 62;
-  const int strips = (n + 61) / 62;
-  sw = (n + strips - 1) / strips;          // balance the strips
+  int sw, strips;
+  balanced_strip(n, &sw, &strips);
   G->strip_w = sw;
   // enough wavefronts to cover the chip a few times over
   int h = 8;
@@ -117,7 +102,7 @@ static void default_launch(hope_grid* G) {
 
 extern "C" {
 
-const char* hope_last_error(void) { return g_last_error.c_str(); }
+const char* hope_last_error(void) { return last_error(); }
 
 static int validate(const hope_grid_desc* desc) {
   if (desc->struct_size != (int32_t)sizeof(hope_grid_desc)) return fail(HOPE_ERR_INVALID, "struct_size mismatch");
@@ -362,18 +347,22 @@ int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq
   return HOPE_OK;
 }
 
-// stage coefficients: q_{s+1} = a q_0 + b q_s + c dt L(q_s)
-static void rk_coefs(int scheme, double dt, double a[3], double b[3], double c[3]) {
+}  // extern "C"
+
+// stage coefficients: q_{s+1} = a q_0 + b q_s + (cs dt) L(q_s)
+void hope::rk_coefs(int scheme, double a[3], double b[3], double cs[3]) {
   if (scheme == HOPE_RK_SSP3) {
-    a[0] = 0.0; b[0] = 1.0; c[0] = dt;
-    a[1] = 0.75; b[1] = 0.25; c[1] = 0.25 * dt;
-    a[2] = 1.0 / 3.0; b[2] = 2.0 / 3.0; c[2] = 2.0 / 3.0 * dt;
+    a[0] = 0.0; b[0] = 1.0; cs[0] = 1.0;
+    a[1] = 0.75; b[1] = 0.25; cs[1] = 0.25;
+    a[2] = 1.0 / 3.0; b[2] = 2.0 / 3.0; cs[2] = 2.0 / 3.0;
   } else {
-    a[0] = 0.0; b[0] = 1.0; c[0] = dt / 3.0;
-    a[1] = 1.0; b[1] = 0.0; c[1] = 0.5 * dt;
-    a[2] = 1.0; b[2] = 0.0; c[2] = dt;
+    a[0] = 0.0; b[0] = 1.0; cs[0] = 1.0 / 3.0;
+    a[1] = 1.0; b[1] = 0.0; cs[1] = 0.5;
+    a[2] = 1.0; b[2] = 0.0; cs[2] = 1.0;
   }
 }
+
+extern "C" {
 
 int hope_rk_step_vjp(const hope_grid* G, double* q, double dt, int32_t scheme, const double* gout, double* gin,
                      double* ws, size_t ws_bytes, void* stream) {
@@ -389,7 +378,8 @@ int hope_rk_step_vjp(const hope_grid* G, double* q, double dt, int32_t scheme, c
     return fail(HOPE_ERR_INVALID, "misaligned buffer");
   if (!std::isfinite(dt)) return fail(HOPE_ERR_INVALID, "dt not finite");
   double a[3], b[3], c[3];
-  rk_coefs(scheme, dt, a, b, c);
+  rk_coefs(scheme, a, b, c);
+  for (double& x : c) x *= dt;
   double* q1 = ws;
   double* q2 = ws + state;
   double* cur = ws + 2 * state;
@@ -424,16 +414,13 @@ int hope_rk_step(const hope_grid* G, double* q, double dt, int32_t scheme, doubl
   if (!std::isfinite(dt)) return fail(HOPE_ERR_INVALID, "dt not finite");
   double* w0 = ws;
   double* w1 = ws + state;
+  double a[3], b[3], c[3];
+  rk_coefs(scheme, a, b, c);
+  for (double& x : c) x *= dt;
   int st;
-  if (scheme == HOPE_RK_SSP3) {
-    if ((st = run_stage(G, q, nullptr, w0, 1, 0.0, 1.0, dt, stream))) return st;
-    if ((st = run_stage(G, w0, q, w1, 1, 0.75, 0.25, 0.25 * dt, stream))) return st;
-    if ((st = run_stage(G, w1, q, q, 1, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt, stream))) return st;
-  } else {
-    if ((st = run_stage(G, q, nullptr, w0, 1, 0.0, 1.0, dt / 3.0, stream))) return st;
-    if ((st = run_stage(G, w0, q, w1, 1, 1.0, 0.0, 0.5 * dt, stream))) return st;
-    if ((st = run_stage(G, w1, q, q, 1, 1.0, 0.0, dt, stream))) return st;
-  }
+  if ((st = run_stage(G, q, nullptr, w0, 1, a[0], b[0], c[0], stream))) return st;
+  if ((st = run_stage(G, w0, q, w1, 1, a[1], b[1], c[1], stream))) return st;
+  if ((st = run_stage(G, w1, q, q, 1, a[2], b[2], c[2], stream))) return st;
   return HOPE_OK;
 }
 

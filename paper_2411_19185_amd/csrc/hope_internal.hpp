@@ -45,6 +45,9 @@ struct HostTables {
   std::string error;
 };
 
+// Coriolis coefficients of the 6 panels for a rotation axis tilted by tilt (18 values).
+void coriolis_coefs(double tilt, double* out);
+
 // Builds every table; returns 0 on success, else a HOPE_ERR code with error set.
 int build_tables(HostTables& t, int n, int k, int weno, double radius, double omega, double tilt,
                  double eps, double theta);

@@ -697,14 +697,22 @@ int build_tables(HostTables& t, int n, int k, int weno, double radius, double om
       ld X = std::tan(((ld)i + 0.5L - n / 2.0L + gx[h]) * kPi / (2 * (ld)n));
       t.sqg[i * m + h] = (double)std::sqrt(1 + X * X);
     }
-  ld sa = std::sin((ld)tilt), ca = std::cos((ld)tilt);
-  const ld fc[6][3] = {{-sa, 0, ca}, {0, sa, ca}, {sa, 0, ca}, {0, -sa, ca}, {ca, 0, sa}, {-ca, 0, -sa}};
   t.fcoef.resize(18);
-  for (int p = 0; p < 6; ++p)
-    for (int c = 0; c < 3; ++c) t.fcoef[p * 3 + c] = (double)fc[p][c];
+  coriolis_coefs(tilt, t.fcoef.data());
   int st = build_ghost_map(t);
   if (st) return st;
   return build_edge_maps(t);
+}
+
+// Coriolis parameter on panel p: f = 2 Omega (Omega_hat . p_hat) with the axis
+// tilted by alpha towards -x, Omega_hat = (-sin alpha, 0, cos alpha).  With the
+// unnormalised panel point v = (c0 + X cX + Y cY per component), Omega_hat . v =
+// L0 + LX X + LY Y; out[3p..3p+2] = (L0, LX, LY).
+void coriolis_coefs(double tilt, double* out) {
+  ld sa = std::sin((ld)tilt), ca = std::cos((ld)tilt);
+  const ld fc[6][3] = {{-sa, 0, ca}, {0, sa, ca}, {sa, 0, ca}, {0, -sa, ca}, {ca, 0, sa}, {-ca, 0, -sa}};
+  for (int p = 0; p < 6; ++p)
+    for (int c = 0; c < 3; ++c) out[p * 3 + c] = (double)fc[p][c];
 }
 
 }  // namespace hope

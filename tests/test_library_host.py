@@ -65,3 +65,12 @@ def test_library_ghost_map_equals_oracle_fixed_point(n, k):
     for v in range(3):
         assert np.abs(a[v] - b[v]).max() / np.abs(b[v]).max() < 1e-14
     assert sweeps < 40
+
+
+def test_batch_create_rejects_bad_arguments():
+    h = ctypes.c_void_p()
+    assert lib().hope_batch_create(None, 1, None, ctypes.byref(h)) == -1
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib().hope_batch_create(arr, 1, None, ctypes.byref(h)) == -1
+    assert lib().hope_batch_create(arr, 0, None, ctypes.byref(h)) == -1
+    assert "null" in lib().hope_last_error().decode() or "n_members" in lib().hope_last_error().decode()
