@@ -202,9 +202,92 @@ def run(args):
     }
     if not args.no_adjoint:
         out["fwd_vjp"] = adjoint(g, n, args, dt)
+    if not args.no_ensemble:
+        del g
+        torch.cuda.empty_cache()
+        out["ensemble"] = ensemble(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(qfin, n, order, scheme)
     print(json.dumps(out), flush=True)
+
+
+def ensemble(args):
+    """The 64-member uneven ensemble (16 members each at C48, C64, C90, C128,
+    WENO5; each a balanced flow with its own axis tilt and a cap jump, its
+    own CFL time step): tuned work-item shapes, one captured HIP graph per
+    SSP-RK3 step, against looping the single-grid step over the members."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    import hope_inputs as hi
+    from paper_2411_19185_amd import Grid, autotune, workloads
+    from paper_2411_19185_amd.ensemble import Ensemble
+
+    sizes = (48, 64, 90, 128)
+    ns = [sizes[i % 4] for i in range(args.members)]
+    t0 = time.time()
+    grids = {n: Grid(n, 5, "weno") for n in sizes}
+    tilts, states, dts = [], [], []
+    for i, n in enumerate(ns):
+        f = hi.BalancedFlowWithCap(seed=args.seed * 1000 + i)
+        q = workloads.cell_average(f, n)
+        tilts.append(f.alpha)
+        states.append(q)
+        dts.append(workloads.cfl_dt(q))
+    ens = Ensemble([grids[n] for n in ns], axis_tilt=tilts)
+    q_all = ens.new_state()
+    for i, q in enumerate(states):
+        ens.member_interior(q_all, i).copy_(torch.from_numpy(q))
+    dt = torch.tensor(dts, dtype=torch.float64, device="cuda")
+    setup_s = time.time() - t0
+    t0 = time.time()
+    with tempfile.TemporaryDirectory() as tmp:
+        sw, sh, blocks = autotune.tune_ensemble(ens, q_all, cache=os.path.join(tmp, "tune.json"))
+    tune_s = time.time() - t0
+    shapes = {n: [sw[ns.index(n)], sh[ns.index(n)]] for n in sizes}
+    cells = sum(6 * n * n for n in ns)
+    stream = torch.cuda.current_stream()
+    graph = ens.capture_step(q_all, dt)
+    for _ in range(2):
+        graph.replay()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(args.ensemble_steps):
+        graph.replay()
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    batch_ms = ev[0].elapsed_time(ev[1]) / args.ensemble_steps
+    finite = bool(torch.isfinite(q_all).all())
+    # looped single-grid path (each member's own buffers, the grid of its resolution)
+    qps = []
+    for i, q in enumerate(states):
+        qp = grids[ns[i]].new_state()
+        grids[ns[i]].interior(qp).copy_(torch.from_numpy(q))
+        qps.append(qp)
+    wss = {n: grids[n].workspace() for n in sizes}
+    loop_steps = max(1, args.ensemble_steps // 5)
+    for i, qp in enumerate(qps):
+        grids[ns[i]].rk_step(qp, dts[i], "ssp3", wss[ns[i]])
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(loop_steps):
+        for i, qp in enumerate(qps):
+            grids[ns[i]].rk_step(qp, dts[i], "ssp3", wss[ns[i]])
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    loop_ms = ev[0].elapsed_time(ev[1]) / loop_steps
+    return {"value": cells * 3 / (batch_ms / 1e3), "unit": "cell-tendency evals/s",
+            "members": len(ns), "resolutions": list(sizes), "cells": cells, "steps": args.ensemble_steps,
+            "ms_per_step": batch_ms, "state_finite": finite,
+            "looped_value": cells * 3 / (loop_ms / 1e3), "looped_ms_per_step": loop_ms, "looped_steps": loop_steps,
+            "speedup": loop_ms / batch_ms, "tuned_shapes": shapes, "tuned_blocks": blocks,
+            "setup_s": setup_s, "tune_s": tune_s,
+            "launches_per_step": 9,
+            "note": "batched: one captured graph per step (9 kernel launches over all members); looped: "
+                    "hope_rk_step per member on its resolution's grid (timing only)"}
 
 
 def adjoint(g, n, args, dt):
@@ -319,6 +402,9 @@ def main():
     ap.add_argument("--launch", default="", help="strip_w,seg_h of the stage kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--ensemble-steps", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy (counter scale)")
     ap.add_argument("--vjp-reps", type=int, default=10)
     ap.add_argument("--rollout-steps", type=int, default=20)

@@ -192,7 +192,7 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
   g.nnz = (int64_t)h.g_col.size();
   g.rows = (int)h.g_dst.size();
   {
-    // transpose of G, rows by interior cell
+    // transpose of G, rows by interior cell (CSR over the cells it reads)
     const int n = h.n, P = h.P, r = h.r;
     const int cells = 6 * n * n;
     std::vector<int32_t> cnt(cells + 1, 0);
@@ -212,7 +212,16 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
         rows[pos] = h.g_dst[gr];
         for (int comp = 0; comp < 5; ++comp) vals[comp * nnz + pos] = h.g_val[comp * nnz + k];
       }
-    int e2 = upload(G, cnt, &G->gt_ptr);
+    // keep only the cells some ghost row reads
+    std::vector<int32_t> cptr(1, 0), ccell;
+    for (int c = 0; c < cells; ++c)
+      if (cnt[c + 1] > cnt[c]) {
+        ccell.push_back(c);
+        cptr.push_back(cnt[c + 1]);
+      }
+    G->gt_rows = (int32_t)ccell.size();
+    int e2 = upload(G, cptr, &G->gt_ptr);
+    if (!e2) e2 = upload(G, ccell, &G->gt_cell);
     if (!e2) e2 = upload(G, rows, &G->gt_row);
     if (!e2) e2 = upload(G, vals, &G->gt_val);
     if (e2) { free_grid(G); return e2; }
@@ -334,6 +343,8 @@ int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq
   a.Lam = ws + nT;
   a.Dl = ws + 2 * nT;
   a.gpad = ws + 2 * nT + nD;
+  a.gt_rows = G->gt_rows;
+  a.gt_cell = G->gt_cell;
   a.gt_ptr = G->gt_ptr;
   a.gt_row = G->gt_row;
   a.gt_val = G->gt_val;

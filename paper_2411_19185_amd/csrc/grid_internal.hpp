@@ -19,7 +19,9 @@ struct hope_grid {
   size_t device_bytes = 0;
   double* bt = nullptr;      // panel-edge trace scratch, 24*n*m*3
   int strip_w = 62, seg_h = 8;
-  // G^T by interior cell (adjoint of the ghost fill)
+  // G^T by the interior cells some ghost row reads (adjoint of the ghost fill)
+  int32_t gt_rows = 0;
+  const int32_t* gt_cell = nullptr;
   const int32_t* gt_ptr = nullptr;
   const int32_t* gt_row = nullptr;
   const double* gt_val = nullptr;

@@ -16,8 +16,11 @@
 //   k_vjp_weno      WENO: cotangents of the stencil cell values through the
 //                   nonlinear weights, tau, beta and the sub-stencil values
 //   k_vjp_gather    cotangent of every padded cell (interior and ghost)
-//   k_vjp_ghost_t   interior cotangent plus G^T times the ghost cotangents
+//   k_vjp_interior  the interior cotangent
+//   k_vjp_ghost_t   plus G^T times the ghost cotangents
 // Every kernel gathers (each output is written by one thread): no atomics.
+// Scratch arrays are structs of arrays over cells, so that neighbouring lanes
+// (neighbouring cells) read and write neighbouring addresses.
 // Non-smooth points take the subgradient sign(0) = 0.
 #include "device_common.hpp"
 #include "vjp_internal.hpp"
@@ -37,10 +40,11 @@ __device__ __forceinline__ void lmars_adj(const double* qL, const double* qR, do
   const double idl = rcp(dl);
   const double isg = d2 * dl * ia * ia * rcp(ox * oy);
   const double sgii = dl * ia * rcp(dir == 0 ? sqx : sqy);
-  const int iv = 1 + dir;
+  // normal momentum component (selects, not a dynamic index: keeps the arrays in registers)
+  const double qLn = dir == 0 ? qL[1] : qL[2], qRn = dir == 0 ? qR[1] : qR[2];
   const double phiL = qL[0] * isg, phiR = qR[0] * isg;
   const double iL = rcp(qL[0] * sgii), iR = rcp(qR[0] * sgii);
-  const double upL = qL[iv] * iL, upR = qR[iv] * iR;
+  const double upL = qLn * iL, upR = qRn * iR;
   const double sL = sqrt_g(phiL), sR = sqrt_g(phiR);
   const double c = 0.5 * (sL + sR);
   const double ic = rcp(c);
@@ -73,9 +77,11 @@ __device__ __forceinline__ void lmars_adj(const double* qL, const double* qR, do
   cb -= icb * ic * ic;
   phiLb += 0.5 * cb * 0.5 / sL;
   phiRb += 0.5 * cb * 0.5 / sR;
-  bL[iv] += upLb * iL;
+  bL[1] += dir == 0 ? upLb * iL : 0.0;
+  bL[2] += dir == 0 ? 0.0 : upLb * iL;
   bL[0] -= upLb * upL / qL[0];
-  bR[iv] += upRb * iR;
+  bR[1] += dir == 0 ? upRb * iR : 0.0;
+  bR[2] += dir == 0 ? 0.0 : upRb * iR;
   bR[0] -= upRb * upR / qR[0];
   bL[0] += phiLb * isg;
   bR[0] += phiRb * isg;
@@ -105,7 +111,8 @@ template <int M>
 __device__ __forceinline__ int side_pt(int sd, int h) { return sd * M + h; }
 
 // ---------------------------------------------------------------------------
-// k_vjp_traces: T[(c*NP + pt)*3 + v]
+// k_vjp_traces: T[(pt*3 + v)*cells + c] (struct of arrays: lanes of
+// neighbouring cells touch neighbouring addresses)
 // ---------------------------------------------------------------------------
 template <int K, bool W, int M>
 __global__ __launch_bounds__(64) void k_vjp_traces(const double* __restrict__ tab_, GridScalars gs,
@@ -119,7 +126,8 @@ __global__ __launch_bounds__(64) void k_vjp_traces(const double* __restrict__ ta
   const int p = c / (n * n), j = (c / n) % n, i = c % n;
   const size_t vs = (size_t)6 * P * P;
   const double* c0 = q + (size_t)p * P * P + (size_t)(j + C::R) * P + (i + C::R);
-  double* out = T + (size_t)c * NP * 3;
+  const size_t cells = (size_t)6 * n * n;
+  double* out = T + c;
 #pragma unroll 1
   for (int v = 0; v < 3; ++v) {
     auto at = [&](int dy, int dx) -> double { return c0[v * vs + dy * P + dx]; };
@@ -131,16 +139,17 @@ __global__ __launch_bounds__(64) void k_vjp_traces(const double* __restrict__ ta
     for (int sd = 0; sd < 2; ++sd) {
       xpass<K, W, M>(tab, sd, at, xr);
 #pragma unroll
-      for (int h = 0; h < M; ++h) out[(sd * M + h) * 3 + v] = point<K, W, M>(tab, 2 + h, sd * M + h, xr, kf);
+      for (int h = 0; h < M; ++h)
+        out[((sd * M + h) * 3 + v) * cells] = point<K, W, M>(tab, 2 + h, sd * M + h, xr, kf);
     }
 #pragma unroll 1
     for (int h = 0; h < M; ++h) {
       xpass<K, W, M>(tab, 2 + h, at, xr);
-      out[(2 * M + h) * 3 + v] = point<K, W, M>(tab, 0, 2 * M + h, xr, kf);
-      out[(3 * M + h) * 3 + v] = point<K, W, M>(tab, 1, 3 * M + h, xr, kf);
+      out[((2 * M + h) * 3 + v) * cells] = point<K, W, M>(tab, 0, 2 * M + h, xr, kf);
+      out[((3 * M + h) * 3 + v) * cells] = point<K, W, M>(tab, 1, 3 * M + h, xr, kf);
 #pragma unroll
       for (int w = 0; w < M; ++w)
-        out[(4 * M + w * M + h) * 3 + v] = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+        out[((4 * M + w * M + h) * 3 + v) * cells] = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
     }
   }
 }
@@ -158,18 +167,19 @@ __device__ __forceinline__ void outside_state(cdp tab, cip itab, const TabOffset
   const int hb = itab[O.i_rev + idx] ? M - 1 - h : h;
   const int cb = (B * n + jb) * n + ib;
   const int pt = bs * M + hb;
-  const double* src = T + ((size_t)cb * NP + pt) * 3;
+  const size_t cells = (size_t)6 * n * n;
+  const double* src = T + (size_t)pt * 3 * cells + cb;
   cdp cv = tab + O.bt_conv + ((size_t)idx * M + h) * 5;
   out[0] = cv[0] * src[0];
-  out[1] = cv[1] * src[1] + cv[2] * src[2];
-  out[2] = cv[3] * src[1] + cv[4] * src[2];
+  out[1] = cv[1] * src[cells] + cv[2] * src[2 * cells];
+  out[2] = cv[3] * src[cells] + cv[4] * src[2 * cells];
   *conv = cv;
   *bcell = cb;
   *bpt = pt;
 }
 
 // ---------------------------------------------------------------------------
-// k_vjp_points: Lam[(c*NP + pt)*3 + v] = dL/d(point value)
+// k_vjp_points: Lam[(pt*3 + v)*cells + c] = dL/d(point value)
 // ---------------------------------------------------------------------------
 template <int K, bool W, int M>
 __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ tab_, const int32_t* __restrict__ itab_,
@@ -187,8 +197,9 @@ __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ ta
   const double invd = gs.inv_delta, ia = 1.0 / gs.radius;
   const size_t nn = (size_t)n * n;
   auto wv = [&](int v, int cc) -> double { return w[(size_t)v * 6 * nn + cc]; };
-  const double* own = T + (size_t)c * NP * 3;
-  double* lam = Lam + (size_t)c * NP * 3;
+  const size_t cells = (size_t)6 * n * n;
+  auto own = [&](int pt, int v) -> double { return T[((size_t)pt * 3 + v) * cells + c]; };
+  auto lam = [&](int pt, int v) -> double& { return Lam[((size_t)pt * 3 + v) * cells + c]; };
   cdp Xg = tab + O.Xg, sqg = tab + O.sqg, Xe = tab + O.Xe, sqe = tab + O.sqe, gw = tab + C::O.gw;
 #pragma unroll 1
   for (int sd = 0; sd < 4; ++sd) {
@@ -213,10 +224,10 @@ __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ ta
     for (int h = 0; h < M; ++h) {
       double qo[3], qn[3];
 #pragma unroll
-      for (int v = 0; v < 3; ++v) qo[v] = own[(sd * M + h) * 3 + v];
+      for (int v = 0; v < 3; ++v) qo[v] = own(sd * M + h, v);
       if (inside) {
 #pragma unroll
-        for (int v = 0; v < 3; ++v) qn[v] = T[((size_t)nc * NP + osd * M + h) * 3 + v];
+        for (int v = 0; v < 3; ++v) qn[v] = T[((size_t)(osd * M + h) * 3 + v) * cells + nc];
       } else {
         cdp cv;
         int bc, bp;
@@ -229,9 +240,8 @@ __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ ta
       double bL[3] = {0, 0, 0}, bR[3] = {0, 0, 0};
       if (own_is_right) lmars_adj(qn, qo, X, Y, sx, sy, dir, ia, mu, bL, bR);
       else lmars_adj(qo, qn, X, Y, sx, sy, dir, ia, mu, bL, bR);
-      const double* b = own_is_right ? bR : bL;
 #pragma unroll
-      for (int v = 0; v < 3; ++v) lam[(sd * M + h) * 3 + v] = b[v];
+      for (int v = 0; v < 3; ++v) lam(sd * M + h, v) = own_is_right ? bR[v] : bL[v];
     }
   }
   // sources at the cell Gauss points
@@ -244,10 +254,10 @@ __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ ta
       const double X = Xg[i * M + h], Y = Xg[j * M + vv];
       const double g2 = gw[h] * gw[vv];
       double Qb[3] = {0, 0, 0};
-      sources_adj(own[pt * 3 + 0], own[pt * 3 + 1], own[pt * 3 + 2], X, Y, fc[0] + fc[1] * X + fc[2] * Y,
+      sources_adj(own(pt, 0), own(pt, 1), own(pt, 2), X, Y, fc[0] + fc[1] * X + fc[2] * Y,
                   gs.omega2, g2 * wv(1, c), g2 * wv(2, c), Qb);
 #pragma unroll
-      for (int v = 0; v < 3; ++v) lam[pt * 3 + v] = Qb[v];
+      for (int v = 0; v < 3; ++v) lam(pt, v) = Qb[v];
     }
 }
 
@@ -279,7 +289,7 @@ __global__ __launch_bounds__(64) void k_vjp_edges(const double* __restrict__ tab
   cdp Xg = tab + O.Xg, sqg = tab + O.sqg, Xe = tab + O.Xe, sqe = tab + O.sqe, gw = tab + C::O.gw;
   double qo[3], qn[3];
 #pragma unroll
-  for (int v = 0; v < 3; ++v) qo[v] = T[((size_t)c * NP + sd * M + h) * 3 + v];
+  for (int v = 0; v < 3; ++v) qo[v] = T[((size_t)(sd * M + h) * 3 + v) * nn * 6 + c];
   cdp cv;
   int bc, bp;
   outside_state<M>(tab, itab, O, n, P, gs.r, T, p, sd, t, h, qn, &cv, &bc, &bp);
@@ -298,15 +308,18 @@ __global__ __launch_bounds__(64) void k_vjp_edges(const double* __restrict__ tab
   double bL[3] = {0, 0, 0}, bR[3] = {0, 0, 0};
   if (own_is_right) lmars_adj(qn, qo, X, Y, sx, sy, dir, ia, mu, bL, bR);
   else lmars_adj(qo, qn, X, Y, sx, sy, dir, ia, mu, bL, bR);
-  const double* ob = own_is_right ? bL : bR;      // cotangent of the converted outside state
-  double* dst = Lam + ((size_t)bc * NP + bp) * 3;
+  double ob[3];                                   // cotangent of the converted outside state
+#pragma unroll
+  for (int v = 0; v < 3; ++v) ob[v] = own_is_right ? bL[v] : bR[v];
+  const size_t cells = 6 * nn;
+  double* dst = Lam + (size_t)bp * 3 * cells + bc;
   dst[0] += cv[0] * ob[0];
-  dst[1] += cv[1] * ob[1] + cv[3] * ob[2];
-  dst[2] += cv[2] * ob[1] + cv[4] * ob[2];
+  dst[cells] += cv[1] * ob[1] + cv[3] * ob[2];
+  dst[2 * cells] += cv[2] * ob[1] + cv[4] * ob[2];
 }
 
 // ---------------------------------------------------------------------------
-// k_vjp_weno: Dl[(c*K*K + o)*3 + v] = cotangent of stencil cell o of cell c
+// k_vjp_weno: Dl[(o*3 + v)*cells + c] = cotangent of stencil cell o of cell c
 // ---------------------------------------------------------------------------
 template <int K, bool W, int M>
 __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_, GridScalars gs,
@@ -318,12 +331,13 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
   const int n = gs.n, P = gs.P;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 18 * n * n) return;
-  const int v = idx % 3, c = idx / 3;
+  const int cells = 6 * n * n;
+  const int v = idx / cells, c = idx % cells;
   const int p = c / (n * n), j = (c / n) % n, i = c % n;
   const size_t vs = (size_t)6 * P * P;
   const double* c0 = q + v * vs + (size_t)p * P * P + (size_t)(j + R) * P + (i + R);
   auto at = [&](int dy, int dx) -> double { return c0[dy * P + dx]; };
-  const double* lam = Lam + (size_t)c * NP * 3 + v;
+  const double* lam = Lam + (size_t)v * cells + c;     // point pt at lam[pt * 3 * cells]
   cdp V = tab + C::O.V, lamq = tab + C::O.lam, wsub = tab + C::O.wsub, gp = tab + C::O.gp, gm = tab + C::O.gm;
   double dq[K * K];
 #pragma unroll
@@ -396,7 +410,7 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
         else if (k == 1) { py = 1; pt = 3 * M + h; }
         else { py = k; pt = 4 * M + (k - 2) * M + h; }
       }
-      const double lb = lam[pt * 3];
+      const double lb = lam[(size_t)pt * 3 * cells];
       double pv[S];
       double ap = 0, dp = 0, am = 0, dm = 0;
 #pragma unroll
@@ -491,9 +505,9 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
 #pragma unroll
         for (int a = 0; a < L; ++a) dq[row * K + (sx + a)] += V[(sx * L + al) * L + a] * trb[row][al];
   }
-  double* out = Dl + (size_t)c * K * K * 3 + v;
+  double* out = Dl + (size_t)v * cells + c;
 #pragma unroll
-  for (int o = 0; o < K * K; ++o) out[o * 3] = dq[o];
+  for (int o = 0; o < K * K; ++o) out[(size_t)o * 3 * cells] = dq[o];
 }
 
 // ---------------------------------------------------------------------------
@@ -511,6 +525,7 @@ __global__ __launch_bounds__(256) void k_vjp_gather(const double* __restrict__ t
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const int ii = idx % P, jj = (idx / P) % P, p = (idx / ((size_t)P * P)) % 6, v = idx / ((size_t)6 * P * P);
+  const size_t cells = (size_t)6 * n * n;
   double acc = 0.0;
   for (int dy = -R; dy <= R; ++dy) {
     const int j = jj - R - dy;
@@ -521,17 +536,17 @@ __global__ __launch_bounds__(256) void k_vjp_gather(const double* __restrict__ t
       const int c = (p * n + j) * n + i;
       const int o = (dy + R) * K + (dx + R);
       if constexpr (W) {
-        acc += Dl[((size_t)c * K * K + o) * 3 + v];
+        acc += Dl[((size_t)o * 3 + v) * cells + c];
       } else {
         // TPP: sum over the cell's points of lam_pt * wy[py][dy] * wx[px][dx]
         cdp wc = tab + C::O.wc;
-        const double* lam = Lam + (size_t)c * NP * 3 + v;
+        const double* lam = Lam + (size_t)v * cells + c;
         for (int pt = 0; pt < NP; ++pt) {
           int px, py;
           if (pt < 2 * M) { px = pt / M; py = 2 + pt % M; }
           else if (pt < 4 * M) { py = (pt - 2 * M) / M; px = 2 + (pt - 2 * M) % M; }
           else { const int q2 = pt - 4 * M; px = 2 + q2 % M; py = 2 + q2 / M; }
-          acc += lam[pt * 3] * wc[py * K + (dy + R)] * wc[px * K + (dx + R)];
+          acc += lam[(size_t)pt * 3 * cells] * wc[py * K + (dy + R)] * wc[px * K + (dx + R)];
         }
       }
     }
@@ -540,29 +555,55 @@ __global__ __launch_bounds__(256) void k_vjp_gather(const double* __restrict__ t
 }
 
 // ---------------------------------------------------------------------------
-// k_vjp_ghost_t: gq = interior cotangent + G^T (ghost cotangents)
+// k_vjp_interior: gq = the interior part of the padded cotangent
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_vjp_ghost_t(int n, int P, int r, const int32_t* __restrict__ gt_ptr,
-                                                      const int32_t* __restrict__ gt_row,
-                                                      const double* __restrict__ gt_val, int64_t gnnz,
-                                                      const double* __restrict__ gpad, double* __restrict__ gq) {
+__global__ __launch_bounds__(256) void k_vjp_interior(int n, int P, int r, const double* __restrict__ gpad,
+                                                      double* __restrict__ gq) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= 6 * n * n) return;
   const int p = c / (n * n), j = (c / n) % n, i = c % n;
   const size_t plane = (size_t)6 * P * P;
   const size_t off = (size_t)p * P * P + (size_t)(j + r) * P + (i + r);
-  double g0 = gpad[off], g1 = gpad[plane + off], g2 = gpad[2 * plane + off];
-  for (int k = gt_ptr[c]; k < gt_ptr[c + 1]; ++k) {
+  const size_t nn = (size_t)6 * n * n;
+  gq[c] = gpad[off];
+  gq[nn + c] = gpad[plane + off];
+  gq[2 * nn + c] = gpad[2 * plane + off];
+}
+
+// ---------------------------------------------------------------------------
+// k_vjp_ghost_t: gq += G^T (ghost cotangents), 16 lanes per interior cell
+// that some ghost row reads (the only rows of G^T with entries)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_vjp_ghost_t(int rows, int n, int P, const int32_t* __restrict__ gt_cell,
+                                                     const int32_t* __restrict__ gt_ptr,
+                                                     const int32_t* __restrict__ gt_row,
+                                                     const double* __restrict__ gt_val, int64_t gnnz,
+                                                     const double* __restrict__ gpad, double* __restrict__ gq) {
+  const int row = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 4);
+  if (row >= rows) return;   // whole 16-lane group leaves together
+  const int lane = threadIdx.x & 15;
+  const size_t plane = (size_t)6 * P * P;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int k = gt_ptr[row] + lane; k < gt_ptr[row + 1]; k += 16) {
     const int d = gt_row[k];
     const double a0 = gpad[d], a1 = gpad[plane + d], a2 = gpad[2 * plane + d];
     g0 = fma(gt_val[k], a0, g0);
     g1 = fma(gt_val[gnnz + k], a1, fma(gt_val[3 * gnnz + k], a2, g1));
     g2 = fma(gt_val[2 * gnnz + k], a1, fma(gt_val[4 * gnnz + k], a2, g2));
   }
-  const size_t nn = (size_t)6 * n * n;
-  gq[c] = g0;
-  gq[nn + c] = g1;
-  gq[2 * nn + c] = g2;
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) {
+    g0 += __shfl_xor(g0, off, 16);
+    g1 += __shfl_xor(g1, off, 16);
+    g2 += __shfl_xor(g2, off, 16);
+  }
+  if (lane == 0) {
+    const int c = gt_cell[row];
+    const size_t nn = (size_t)6 * n * n;
+    gq[c] += g0;
+    gq[nn + c] += g1;
+    gq[2 * nn + c] += g2;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -600,8 +641,10 @@ static int vjp_t(const VjpArgs& a, int step, void* stream) {
       break;
     }
     case kVjpGhostT:
-      hipLaunchKernelGGL(k_vjp_ghost_t, dim3((cells + 255) / 256), dim3(256), 0, s, n, P, gs.r, a.gt_ptr, a.gt_row,
-                         a.gt_val, a.gt_nnz, a.gpad, a.gq);
+      hipLaunchKernelGGL(k_vjp_interior, dim3((cells + 255) / 256), dim3(256), 0, s, n, P, gs.r, a.gpad, a.gq);
+      if (a.gt_rows > 0)
+        hipLaunchKernelGGL(k_vjp_ghost_t, dim3((unsigned)(((size_t)a.gt_rows * 16 + 255) / 256)), dim3(256), 0, s,
+                           a.gt_rows, n, P, a.gt_cell, a.gt_ptr, a.gt_row, a.gt_val, a.gt_nnz, a.gpad, a.gq);
       break;
     default:
       return (int)hipErrorInvalidValue;

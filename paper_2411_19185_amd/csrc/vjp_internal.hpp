@@ -13,12 +13,15 @@ struct VjpArgs {
   const double* q;
   const double* w;
   double* gq;
-  double* T;       // point values of every cell, 6n^2 x NP x 3
+  double* T;       // point values of every cell, [NP][3][6n^2]
   double* Lam;     // their cotangents, same layout
-  double* Dl;      // WENO: stencil cotangents, 6n^2 x K^2 x 3
+  double* Dl;      // WENO: stencil cotangents, [K^2][3][6n^2]
   double* gpad;    // padded cotangent, 3 x 6 x P x P
-  const int32_t* gt_ptr;   // G^T by interior cell: 6n^2 + 1
-  const int32_t* gt_row;   // padded offset of the ghost cell
+  // G^T by the interior cells that some ghost row reads (gt_rows of them)
+  int32_t gt_rows;
+  const int32_t* gt_cell;  // the interior cell of each row
+  const int32_t* gt_ptr;   // rows + 1
+  const int32_t* gt_row;   // padded offset (in one variable plane) of the ghost cell
   const double* gt_val;    // 5 x nnz, same component order as G
   int64_t gt_nnz;
 };
