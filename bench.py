@@ -64,13 +64,15 @@ def flops_per_cell(order: int, scheme: str) -> float:
     return 3 * per_var + lmars + src + 15 + 18
 
 
-STAGE_SOURCES = ("paper_2411_19185_amd/csrc/kernels.hip", "paper_2411_19185_amd/csrc/device_common.hpp",
-                 "paper_2411_19185_amd/csrc/hope_internal.hpp")
+STAGE_SOURCES = ("paper_2411_19185_amd/csrc/kernels.hip", "paper_2411_19185_amd/csrc/kernel_bodies.hpp",
+                 "paper_2411_19185_amd/csrc/device_common.hpp", "paper_2411_19185_amd/csrc/hope_internal.hpp",
+                 "paper_2411_19185_amd/build.py")
 TRAFFIC_FILE = "profiles/k_stage_weno5_c360_traffic.txt"
 
 
 def stage_source_hash() -> str:
-    """sha256 over the sources the stage kernel is compiled from."""
+    """sha256 over the sources the stage kernel is compiled from and the
+    build flags."""
     import hashlib
     h = hashlib.sha256()
     for f in STAGE_SOURCES:
