@@ -101,7 +101,7 @@ __global__ __launch_bounds__(64) void k_edge_traces_batch(const BatchMember* __r
 }
 
 template <int K, bool W, int M>
-__global__ __launch_bounds__(64, HOPE_STAGE_WAVES) void k_stage_batch(const BatchMember* __restrict__ mem,
+__global__ __launch_bounds__(kStageThreads) void k_stage_batch(const BatchMember* __restrict__ mem,
                                                                       const int32_t* __restrict__ items,
                                                                       int n_items, BatchStage S) {
   __shared__ StageSmem<K, W, M> sm;
@@ -152,7 +152,7 @@ template <int K, bool W, int M>
 static int batch_stage_t(const BatchMember* members, const int32_t* items, int n_items, int blocks,
                          const BatchStage& st, void* stream) {
   const int grid = (blocks > 0 && blocks < n_items) ? blocks : n_items;
-  hipLaunchKernelGGL((k_stage_batch<K, W, M>), dim3(grid), dim3(64), 0, (hipStream_t)stream, members, items,
+  hipLaunchKernelGGL((k_stage_batch<K, W, M>), dim3(grid), dim3(kStageThreads), 0, (hipStream_t)stream, members, items,
                      n_items, st);
   return (int)hipGetLastError();
 }

@@ -106,33 +106,40 @@ struct StageArgs {
   int strip_w, seg_h, n_strips, n_segs;
 };
 
-#ifndef HOPE_STAGE_WAVES
-#define HOPE_STAGE_WAVES 1
-#endif
+// The fused stage runs three wavefronts per work item: in the reconstruction
+// phase wavefront v reconstructs variable v, so that each keeps only one
+// variable's stencil passes and WENO weights live; the flux, source and
+// assembly phases are then split between the three.
+constexpr int kStageThreads = 192;
 
 template <int K, bool W, int M>
 struct StageSmem {
-  static constexpr int R = (K - 1) / 2, NR = 2 * R + 1, CW = 64 + 2 * R, S = ((K + 1) / 2) * ((K + 1) / 2);
-  // stencil window: NR padded rows of CW columns (LDS column c = padded column i0-1+c)
-  double sq[3][NR][CW];
-  // WENO weights kappa_j per variable and lane, and the carried top traces
-  double skap[W ? 3 : 1][W ? S : 1][64];
-  double sptop[3][M][64];
+  static constexpr int R = (K - 1) / 2, NR = 2 * R + 1, CW = 64 + 2 * R, NP = 4 * M + M * M;
+  double sq[3][NR][CW];     // stencil window: NR padded rows (LDS column c = padded column i0-1+c)
+  double pts[3][NP][64];    // the current row's values at every point of every lane's cell
+  double ptop[3][M][64];    // top traces of the row below
+  double fx[3][64];         // Gauss-quadrature flux through each lane's left edge
+  double fy[3][64];         // ... through each lane's bottom edge
+  double src[2][64];        // momentum sources (cell quadrature)
 };
 
 // one work item (panel, strip, segment) of the fused stage; fcb = the 6 x 3
-// Coriolis coefficients of the grid (or of one ensemble member)
+// Coriolis coefficients of the grid (or of one ensemble member).  Called by
+// all kStageThreads threads of the workgroup.
+//
+// The strip's lanes: lane L works on column i0-1+L; lanes 1..strip_w own the
+// strip's cells, lanes 0 and strip_w+1 are its ring columns.  Walking up the
+// rows j0..j1 of the segment, each step j (j < j1) reconstructs row j,
+// evaluates the flux through every lane's left and bottom edge and the
+// sources, finishes row j-1 (whose top flux is row j's bottom flux) and forms
+// row j's partial tendency.  Step j1 only supplies the top flux of row j1-1.
 template <int K, bool W, int M>
 __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp fcb, const GridScalars& gs,
                                            const StageArgs& A, int item, StageSmem<K, W, M>& sm) {
   using C = Cfg<K, W, M>;
   constexpr int R = C::R, S = C::S, NR = C::NR, XR = C::XR;
   constexpr int CW = 64 + 2 * R;
-  auto& sq = sm.sq;
-  auto& skap = sm.skap;
-  auto& sptop = sm.sptop;
   const cdp tab = (cdp)tab_;
-  const cdp ltab = tab;
   const int n = gs.n, P = gs.P;
   const TabOffsets O = tab_offsets(K, W, M, n);
   const size_t plane = (size_t)P * P;
@@ -141,7 +148,9 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
   item /= A.n_segs;
   const int strip = item % A.n_strips;
   const int p = item / A.n_strips;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wavefront's variable / role
   const int i0 = strip * A.strip_w;
   const int i1 = min(n, i0 + A.strip_w);          // owned columns [i0, i1)
   const int i = i0 - 1 + lane;                     // this lane's column
@@ -154,20 +163,15 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
   const double ia = 1.0 / gs.radius;
   const double* qp = A.q + p * plane;
   const double* btp = A.bt + (size_t)p * 4 * n * M * 3;
-  cdp fc = fcb + p * 3;
-  const double Lx0 = fc[0], LxX = fc[1], LxY = fc[2];
   const int ic = max(0, min(n - 1, i));            // clamped column for table reads
-  const int ie = max(0, min(n, i));                // clamped edge index
-  const double Xei = tab[O.Xe + ie], sqxe = tab[O.sqe + ie];
-  const bool xdead = !(in_strip && i >= 0 && i <= n && lane >= 1);   // no x-edge flux on this lane
   cdp Xg = tab + O.Xg, sqg = tab + O.sqg, Xe = tab + O.Xe, sqe = tab + O.sqe, gw = tab + C::O.gw;
 
-  // ---- window rows ---------------------------------------------------------
-  constexpr int PER = (3 * CW + 63) / 64;
+  // ---- window rows (all threads) -------------------------------------------
+  constexpr int PER = (3 * CW + kStageThreads - 1) / kStageThreads;
   auto fetch = [&](int pr, double* buf) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = lane + 64 * k;
+      const int idx = tid + kStageThreads * k;
       const int v = idx / CW, c = idx % CW;
       const int gc = i0 - 1 + c;
       buf[k] = (idx < 3 * CW && pr >= 0 && pr < P && gc >= 0 && gc < P) ? qp[v * vs + (size_t)pr * P + gc] : 0.0;
@@ -177,32 +181,134 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     const int slot = pr % NR;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = lane + 64 * k;
-      if (idx < 3 * CW) sq[idx / CW][slot][idx % CW] = buf[k];
+      const int idx = tid + kStageThreads * k;
+      if (idx < 3 * CW) sm.sq[idx / CW][slot][idx % CW] = buf[k];
     }
   };
-  // stencil of variable v at offset (dy, dx) of this lane's cell in interior row pc
-  auto win = [&](int v, int pc) {
-    return [&, v, pc](int dy, int dx) -> double { return sq[v][(pc + R + dy) % NR][lane + R + dx]; };
+  // stencil of this wavefront's variable at offset (dy, dx) of the lane's cell in interior row pc
+  auto win = [&](int pc) {
+    return [&, pc](int dy, int dx) -> double { return sm.sq[wv][(pc + R + dy) % NR][lane + R + dx]; };
   };
-  auto kapv = [&](int v) {
-    return [&, v](int j) -> double { return skap[v][j][lane]; };
+  // WENO weights kappa_j of this wavefront's variable in row pc
+  auto kappa = [&](int pc, double* kap) {
+    if constexpr (W) weno_kappa<K, W, M>(tab, gs.eps, win(pc), [&](int j, double x) { kap[j] = x; });
   };
-  auto weights = [&](int pc) {
-    if constexpr (W) {
+  auto pt = [&](int v, int k) -> double& { return sm.pts[v][k][lane]; };
+
+  // ---- reconstruction phase: wavefront wv, variable wv ----------------------
+  // every point of row pc
+  auto recon_row = [&](int pc) {
+    double kap[W ? S : 1];
+    kappa(pc, kap);
+    auto kf = [&](int j) -> double { return kap[j]; };
+    double xr[XR];
+    asm volatile("" ::: "memory");
+    xpass<K, W, M>(tab, 0, win(pc), xr);
+#pragma unroll
+    for (int h = 0; h < M; ++h) pt(wv, h) = point<K, W, M>(tab, 2 + h, h, xr, kf);
+    asm volatile("" ::: "memory");
+    xpass<K, W, M>(tab, 1, win(pc), xr);
+#pragma unroll
+    for (int h = 0; h < M; ++h) pt(wv, M + h) = point<K, W, M>(tab, 2 + h, M + h, xr, kf);
 #pragma unroll 1
+    for (int h = 0; h < M; ++h) {
+      asm volatile("" ::: "memory");
+      xpass<K, W, M>(tab, 2 + h, win(pc), xr);
+      pt(wv, 2 * M + h) = point<K, W, M>(tab, 0, 2 * M + h, xr, kf);
+      pt(wv, 3 * M + h) = point<K, W, M>(tab, 1, 3 * M + h, xr, kf);
+#pragma unroll
+      for (int w = 0; w < M; ++w) pt(wv, 4 * M + w * M + h) = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+    }
+  };
+  // top (side 1) or bottom (side 0) traces of row pc, into dst(h)
+  auto recon_side = [&](int pc, int side, auto dst) {
+    double kap[W ? S : 1];
+    kappa(pc, kap);
+    auto kf = [&](int j) -> double { return kap[j]; };
+#pragma unroll 1
+    for (int h = 0; h < M; ++h) {
+      double xr[XR];
+      asm volatile("" ::: "memory");
+      xpass<K, W, M>(tab, 2 + h, win(pc), xr);
+      dst(h) = point<K, W, M>(tab, side, (2 + side) * M + h, xr, kf);
+    }
+  };
+
+  // ---- flux phase ------------------------------------------------------------
+  // wavefront 1: flux through the bottom edge of row j (qL: top trace of row
+  // j-1 in ptop, qR: bottom trace of row j in pts)
+  auto yflux = [&](int j) {
+    double gb[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int h = 0; h < M; ++h) {
+      double qL[3], qR[3];
+#pragma unroll
       for (int v = 0; v < 3; ++v) {
-        asm volatile("" ::: "memory");
-        weno_kappa<K, W, M>(ltab, gs.eps, win(v, pc), [&](int j, double x) { skap[v][j][lane] = x; });
+        const double dflt = v == 0 ? 1.0 : 0.0;
+        qL[v] = real ? sm.ptop[v][h][lane] : dflt;
+        qR[v] = real ? pt(v, 2 * M + h) : dflt;
+      }
+      double F[3];
+      lmars(qL, qR, Xg[ic * M + h], Xe[j], sqg[ic * M + h], sqe[j], 1, ia, F);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) gb[v] = fma(gw[h], F[v], gb[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 3; ++v) sm.fy[v][lane] = gb[v];
+  };
+  // wavefront 0: flux through the left edge of each lane's column in row j;
+  // panel edges take the neighbour's converted trace
+  auto xflux = [&](int j) {
+    const int ie = max(0, min(n, i));
+    const double Xei = tab[O.Xe + ie], sqxe = tab[O.sqe + ie];
+    const bool xdead = !(in_strip && i >= 0 && i <= n && lane >= 1);
+    const int ll = max(lane - 1, 0);
+    double fl[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int h = 0; h < M; ++h) {
+      double qL[3], qR[3];
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        const double bl = btp[(((size_t)0 * n + j) * M + h) * 3 + v];
+        const double br = btp[(((size_t)1 * n + j) * M + h) * 3 + v];
+        const double dflt = v == 0 ? 1.0 : 0.0;
+        const double l = sm.pts[v][M + h][ll];
+        const double r = pt(v, h);
+        qL[v] = xdead ? dflt : (i == 0 ? bl : l);
+        qR[v] = xdead ? dflt : (i == n ? br : r);
+      }
+      double F[3];
+      lmars(qL, qR, Xei, Xg[j * M + h], sqxe, sqg[j * M + h], 0, ia, F);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) fl[v] = fma(gw[h], F[v], fl[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 3; ++v) sm.fx[v][lane] = fl[v];
+  };
+  // wavefront 2: metric and Coriolis sources of row j (cell quadrature)
+  auto sources_row = [&](int j) {
+    cdp fc = fcb + p * 3;
+    const double Lx0 = fc[0], LxX = fc[1], LxY = fc[2];
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll 1
+    for (int h = 0; h < M; ++h) {
+      const double X = Xg[ic * M + h];
+#pragma unroll
+      for (int w = 0; w < M; ++w) {
+        double cq[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) cq[v] = real ? pt(v, 4 * M + w * M + h) : (v == 0 ? 1.0 : 0.0);
+        const double Y = Xg[j * M + w];
+        double a1, a2;
+        sources(cq[0], cq[1], cq[2], X, Y, Lx0 + LxX * X + LxY * Y, gs.omega2, a1, a2);
+        const double g2 = gw[h] * gw[w];
+        s1 = fma(g2, a1, s1);
+        s2 = fma(g2, a2, s2);
       }
     }
+    sm.src[0][lane] = s1;
+    sm.src[1][lane] = s2;
   };
-  // each pass re-reads its stencil from LDS rather than keeping all of it live
-  auto pass = [&](int v, int pc, int px, double* xr) {
-    asm volatile("" ::: "memory");
-    xpass<K, W, M>(ltab, px, win(v, pc), xr);
-  };
-  auto ptop = [&](int v, int h) -> double& { return sptop[v][h][lane]; };
 
   // ---- prologue: window and the top traces of row j0-1 ------------------
   double nxt[PER];
@@ -215,20 +321,11 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
   if (j0 == 0) {
 #pragma unroll
     for (int h = 0; h < M; ++h)
-#pragma unroll
-      for (int v = 0; v < 3; ++v) ptop(v, h) = real ? btp[(((size_t)2 * n + ic) * M + h) * 3 + v] : (v ? 0.0 : 1.0);
+      sm.ptop[wv][h][lane] = real ? btp[(((size_t)2 * n + ic) * M + h) * 3 + wv] : (wv ? 0.0 : 1.0);
   } else {
-    weights(j0 - 1);
-#pragma unroll 1
-    for (int h = 0; h < M; ++h)
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        double xr[XR];
-        pass(v, j0 - 1, 2 + h, xr);
-        ptop(v, h) = point<K, W, M>(ltab, 1, 3 * M + h, xr, kapv(v));
-      }
+    recon_side(j0 - 1, 1, [&](int h) -> double& { return sm.ptop[wv][h][lane]; });
   }
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc = 0.0;                // this wavefront's variable: partial tendency of the previous row
 
   for (int j = j0; j <= j1; ++j) {
     const bool last = (j == j1);
@@ -240,146 +337,44 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     __syncthreads();
     const bool want = (j + 1 < j1 || (j + 1 == j1 && j1 < n)) && (j + 2 * R + 1) < P;
     if (want) fetch(j + 2 * R + 1, nxt);
-    double gb[3] = {0.0, 0.0, 0.0};
-    double fl[3] = {0.0, 0.0, 0.0};
-    double s1 = 0.0, s2 = 0.0;
     if (!last) {
-      weights(j);
-      // x-edges: left trace (px = 0), right trace (px = 1), flux through the left edge
-      double xl[3][M], xrt[3][M];
+      recon_row(j);
+    } else if (j1 == n) {
+      // bottom traces of the panel's top row: the neighbour's converted trace
 #pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        double xr[XR];
-        pass(v, j, 0, xr);
-#pragma unroll
-        for (int h = 0; h < M; ++h) xl[v][h] = point<K, W, M>(ltab, 2 + h, h, xr, kapv(v));
-        pass(v, j, 1, xr);
-#pragma unroll
-        for (int h = 0; h < M; ++h) xrt[v][h] = point<K, W, M>(ltab, 2 + h, M + h, xr, kapv(v));
-      }
-#pragma unroll
-      for (int h = 0; h < M; ++h) {
-        double qL[3], qR[3];
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          qL[v] = __shfl_up(xrt[v][h], 1, 64);
-          qR[v] = xl[v][h];
-        }
-        // panel edges take the neighbour's converted trace; lanes without an
-        // edge of their own get a harmless state (selects, not branches: a
-        // branch here splits the region and the register allocation suffers)
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          const double bl = btp[(((size_t)0 * n + j) * M + h) * 3 + v];
-          const double br = btp[(((size_t)1 * n + j) * M + h) * 3 + v];
-          const double dflt = v == 0 ? 1.0 : 0.0;
-          qL[v] = xdead ? dflt : (i == 0 ? bl : qL[v]);
-          qR[v] = xdead ? dflt : (i == n ? br : qR[v]);
-        }
-        double F[3];
-        lmars(qL, qR, Xei, Xg[j * M + h], sqxe, sqg[j * M + h], 0, ia, F);
-#pragma unroll
-        for (int v = 0; v < 3; ++v) fl[v] = fma(gw[h], F[v], fl[v]);
-      }
-      // Gauss-node columns: y-edge traces, y-flux through the bottom edge, CQP sources
-#pragma unroll 1
-      for (int h = 0; h < M; ++h) {
-        double yb[3], yt[3], cq[3][M];
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          double xr[XR];
-          pass(v, j, 2 + h, xr);
-          yb[v] = point<K, W, M>(ltab, 0, 2 * M + h, xr, kapv(v));
-          yt[v] = point<K, W, M>(ltab, 1, 3 * M + h, xr, kapv(v));
-#pragma unroll
-          for (int w = 0; w < M; ++w) cq[v][w] = point<K, W, M>(ltab, 2 + w, 4 * M + w * M + h, xr, kapv(v));
-        }
-        const double X = Xg[ic * M + h];
-        const double sqx = sqg[ic * M + h];
-        double qL[3] = {ptop(0, h), ptop(1, h), ptop(2, h)};
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          const double dflt = v == 0 ? 1.0 : 0.0;
-          qL[v] = real ? qL[v] : dflt;
-          yb[v] = real ? yb[v] : dflt;
-#pragma unroll
-          for (int w = 0; w < M; ++w) cq[v][w] = real ? cq[v][w] : dflt;
-        }
-        double F[3];
-        lmars(qL, yb, X, Xe[j], sqx, sqe[j], 1, ia, F);
-#pragma unroll
-        for (int v = 0; v < 3; ++v) gb[v] = fma(gw[h], F[v], gb[v]);
-#pragma unroll
-        for (int v = 0; v < 3; ++v) ptop(v, h) = yt[v];
-#pragma unroll
-        for (int w = 0; w < M; ++w) {
-          const double Y = Xg[j * M + w];
-          double a1, a2;
-          sources(cq[0][w], cq[1][w], cq[2][w], X, Y, Lx0 + LxX * X + LxY * Y, gs.omega2, a1, a2);
-          const double g2 = gw[h] * gw[w];
-          s1 = fma(g2, a1, s1);
-          s2 = fma(g2, a2, s2);
-        }
-      }
+      for (int h = 0; h < M; ++h) pt(wv, 2 * M + h) = real ? btp[(((size_t)3 * n + ic) * M + h) * 3 + wv] : 0.0;
     } else {
-      // epilogue: bottom traces of row j1 and the flux through the top edge of row j1-1
-      double yb[3][M];
-      if (j1 == n) {
-#pragma unroll
-        for (int h = 0; h < M; ++h)
-#pragma unroll
-          for (int v = 0; v < 3; ++v) yb[v][h] = real ? btp[(((size_t)3 * n + ic) * M + h) * 3 + v] : (v ? 0.0 : 1.0);
-      } else {
-        weights(j);
-#pragma unroll
-        for (int h = 0; h < M; ++h)
-#pragma unroll
-          for (int v = 0; v < 3; ++v) {
-            double xr[XR];
-            pass(v, j, 2 + h, xr);
-            yb[v][h] = point<K, W, M>(ltab, 0, 2 * M + h, xr, kapv(v));
-          }
-      }
-#pragma unroll
-      for (int h = 0; h < M; ++h) {
-        double qL[3], qR[3];
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          const double dflt = v == 0 ? 1.0 : 0.0;
-          qL[v] = real ? ptop(v, h) : dflt;
-          qR[v] = real ? yb[v][h] : dflt;
-        }
-        double F[3];
-        lmars(qL, qR, Xg[ic * M + h], Xe[j], sqg[ic * M + h], sqe[j], 1, ia, F);
-#pragma unroll
-        for (int v = 0; v < 3; ++v) gb[v] = fma(gw[h], F[v], gb[v]);
-      }
+      recon_side(j, 0, [&](int h) -> double& { return pt(wv, 2 * M + h); });
     }
-    // ---- finalize row j-1 ---------------------------------------------------
+    __syncthreads();
+    if (wv == 1) yflux(j);
+    if (!last) {
+      if (wv == 0) xflux(j);
+      if (wv == 2) sources_row(j);
+    }
+    __syncthreads();
+    // ---- assembly: wavefront wv, variable wv -----------------------------
+    const double gb = sm.fy[wv][lane];
     if (j > j0 && owner) {
+      // finish row j-1: its top flux is row j's bottom flux
       const int jr = j - 1;
-      const size_t c_in = (size_t)(jr + R) * P + (i + R);
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        const double dq = fma(-gb[v], invd, acc[v]);
-        const size_t o_in = v * vs + p * plane + c_in;
-        double val = A.cc * dq;
-        if (A.cb != 0.0) val = fma(A.cb, A.q[o_in], val);
-        if (A.qn) val = fma(A.ca, A.qn[o_in], val);
-        if (A.out_padded) {
-          A.out[o_in] = val;
-        } else {
-          A.out[((size_t)(v * 6 + p) * n + jr) * n + i] = val;
-        }
+      const size_t o_in = wv * vs + p * plane + (size_t)(jr + R) * P + (i + R);
+      const double dq = fma(-gb, invd, acc);
+      double val = A.cc * dq;
+      if (A.cb != 0.0) val = fma(A.cb, A.q[o_in], val);
+      if (A.qn) val = fma(A.ca, A.qn[o_in], val);
+      if (A.out_padded) {
+        A.out[o_in] = val;
+      } else {
+        A.out[((size_t)(wv * 6 + p) * n + jr) * n + i] = val;
       }
     }
     if (last) break;
-    double fr[3];
+    const double fl = sm.fx[wv][lane];
+    const double fr = sm.fx[wv][min(lane + 1, 63)];
+    acc = wv == 0 ? (fl - fr + gb) * invd : fma(fl - fr + gb, invd, sm.src[wv - 1][lane]);
 #pragma unroll
-    for (int v = 0; v < 3; ++v) fr[v] = __shfl_down(fl[v], 1, 64);
-    acc[0] = (fl[0] - fr[0] + gb[0]) * invd;
-    acc[1] = fma(fl[1] - fr[1] + gb[1], invd, s1);
-    acc[2] = fma(fl[2] - fr[2] + gb[2], invd, s2);
+    for (int h = 0; h < M; ++h) sm.ptop[wv][h][lane] = pt(wv, 3 * M + h);
   }
 }
 

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(64) void k_edge_traces(const double* __restrict__ t
 // Fused stage kernel: one work item per workgroup
 // ---------------------------------------------------------------------------
 template <int K, bool W, int M>
-__global__ __launch_bounds__(64, HOPE_STAGE_WAVES) void k_stage(const double* __restrict__ tab_, GridScalars gs,
+__global__ __launch_bounds__(kStageThreads) void k_stage(const double* __restrict__ tab_, GridScalars gs,
                                                                 StageArgs A) {
   using C = Cfg<K, W, M>;
   __shared__ StageSmem<K, W, M> sm;
@@ -90,7 +90,7 @@ static int edge_traces_t(const double* tab, const int32_t* itab, const GridScala
 template <int K, bool W, int M>
 static int stage_t(const double* tab, const GridScalars& gs, const StageArgs& a, void* stream) {
   const int items = 6 * a.n_strips * a.n_segs;
-  hipLaunchKernelGGL((k_stage<K, W, M>), dim3(items), dim3(64), 0, (hipStream_t)stream, tab, gs, a);
+  hipLaunchKernelGGL((k_stage<K, W, M>), dim3(items), dim3(kStageThreads), 0, (hipStream_t)stream, tab, gs, a);
   return (int)hipGetLastError();
 }
 
