@@ -204,6 +204,8 @@ def run(args):
     }
     if not args.no_adjoint:
         out["fwd_vjp"] = adjoint(g, n, args, dt)
+    if not args.no_tpp11:
+        out["tpp11_c90"] = tpp11(args)
     if not args.no_ensemble:
         del g
         torch.cuda.empty_cache()
@@ -211,6 +213,54 @@ def run(args):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(qfin, n, order, scheme)
     print(json.dumps(out), flush=True)
+
+
+def tpp11(args):
+    """Order-11 TPP at C90 (the differentiation configuration at its timing
+    size): forward tendency, its adjoint, and one SSP-RK3 step and its
+    adjoint, on the balanced flow with 1e-3 relative noise."""
+    import torch
+
+    import hope_inputs as hi
+    from paper_2411_19185_amd import Grid, workloads
+
+    n = 90
+    f = hi.BalancedFlow(alpha=hi.draw_tilt(args.seed), radius=hi.EARTH_RADIUS)
+    q = workloads.cell_average(f, n)
+    q = q * (1.0 + 1e-3 * hi.normal_array(args.seed + 1000, q.shape))
+    dt = workloads.cfl_dt(q)
+    g = Grid(n, 11, "tpp", axis_tilt=f.alpha)
+    qp = g.new_state()
+    g.interior(qp).copy_(torch.from_numpy(q))
+    w = torch.from_numpy(hi.normal_array(args.seed + 7, (3, 6, n, n))).cuda()
+    dq = torch.empty_like(w)
+    gq = torch.empty_like(w)
+    vws = g.vjp_workspace()
+    rws = g.rk_vjp_workspace()
+    ws = g.workspace()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    t_fwd = timed(lambda: g.tendency(qp, dq))
+    t_vjp = timed(lambda: g.tendency_vjp(qp, w, gq, vws))
+    qs = qp.clone()
+    t_step = timed(lambda: g.rk_step(qs, dt, "ssp3", ws))
+    t_step_vjp = timed(lambda: g.rk_step_vjp(qp, dt, w, "ssp3", gq, rws))
+    cells = 6 * n * n
+    return {"cells": cells, "tendency_ms": t_fwd, "tendency_vjp_ms": t_vjp, "rk_step_ms": t_step,
+            "rk_step_vjp_ms": t_step_vjp, "fwd_value": cells / (t_fwd / 1e3),
+            "fwd_vjp_value": cells / ((t_fwd + t_vjp) / 1e3), "unit": "cell-tendency evals/s"}
 
 
 def ensemble(args):
@@ -405,6 +455,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-tpp11", action="store_true")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--ensemble-steps", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy (counter scale)")
