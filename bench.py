@@ -331,12 +331,32 @@ def ensemble(args):
     ev[1].record(stream)
     torch.cuda.synchronize()
     loop_ms = ev[0].elapsed_time(ev[1]) / loop_steps
+    # per-member adjoint of the final-state loss 0.5 ||q_T||^2 over the same steps
+    vjp_steps = args.ensemble_steps if args.ensemble_vjp else 0
+    vjp_ms, grads_finite = 0.0, True
+    if vjp_steps:
+        q0s = [torch.from_numpy(q).cuda() for q in states]
+        for i in range(len(ns)):          # derived member grids, made before timing
+            ens.member_grid(i)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for i in range(len(ns)):
+            gr = ens.member_loss_gradient(i, q0s[i], dts[i], vjp_steps, checkpoint_every=5)
+            grads_finite = grads_finite and bool(torch.isfinite(gr).all())
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        vjp_ms = ev[0].elapsed_time(ev[1])
     return {"value": cells * 3 / (batch_ms / 1e3), "unit": "cell-tendency evals/s",
             "members": len(ns), "resolutions": list(sizes), "cells": cells, "steps": args.ensemble_steps,
             "ms_per_step": batch_ms, "state_finite": finite,
             "looped_value": cells * 3 / (loop_ms / 1e3), "looped_ms_per_step": loop_ms, "looped_steps": loop_steps,
             "speedup": loop_ms / batch_ms, "tuned_shapes": shapes, "tuned_blocks": blocks,
             "setup_s": setup_s, "tune_s": tune_s,
+            "member_vjp": {"steps": vjp_steps, "checkpoint_every": 5, "ms_total": vjp_ms,
+                           "value": (cells * 3 * vjp_steps / (vjp_ms / 1e3)) if vjp_ms else None,
+                           "unit": "cell-tendency evals/s (fwd+VJP)", "grads_finite": grads_finite,
+                           "loss": "0.5 ||q_T||^2 per member; each member's checkpointed rollout and step "
+                                   "adjoints on its own derived grid, members looped"},
             "launches_per_step": 9,
             "note": "batched: one captured graph per step (9 kernel launches over all members); looped: "
                     "hope_rk_step per member on its resolution's grid (timing only)"}
@@ -458,6 +478,7 @@ def main():
     ap.add_argument("--no-tpp11", action="store_true")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--ensemble-steps", type=int, default=50)
+    ap.add_argument("--no-ensemble-vjp", dest="ensemble_vjp", action="store_false")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy (counter scale)")
     ap.add_argument("--vjp-reps", type=int, default=10)
     ap.add_argument("--rollout-steps", type=int, default=20)

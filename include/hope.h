@@ -103,6 +103,12 @@ typedef struct hope_layout {
  * On success *out owns device memory until hope_grid_destroy. */
 int hope_grid_create(const hope_grid_desc* desc, hope_grid** out);
 void hope_grid_destroy(hope_grid* grid);
+/* A grid equal to base except for the tilt of the rotation axis (the
+ * Coriolis term (2.3) with f of a tilted axis): it shares base's ghost map,
+ * its transpose and the panel-edge map on the device and copies only the small
+ * constant tables, so it is cheap to make one per ensemble member.  base must
+ * outlive it.  Synchronous. */
+int hope_grid_derive(const hope_grid* base, double axis_tilt, hope_grid** out);
 int hope_grid_layout(const hope_grid* grid, hope_layout* out);
 
 /* Ghost fill g = G q (7.12): overwrites the ghost rings of the padded state q

@@ -81,6 +81,7 @@ _I32 = ctypes.c_int32
 _SIGS = {
     "hope_grid_create": (_I32, [ctypes.POINTER(GridDesc), ctypes.POINTER(_P)]),
     "hope_grid_destroy": (None, [_P]),
+    "hope_grid_derive": (_I32, [_P, ctypes.c_double, ctypes.POINTER(_P)]),
     "hope_grid_layout": (_I32, [_P, ctypes.POINTER(Layout)]),
     "hope_fill_halo": (_I32, [_P, _P, _P]),
     "hope_tendency": (_I32, [_P, _P, _P, _P]),

@@ -236,6 +236,60 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
   default_launch(G);
   e = hipDeviceSynchronize();
   if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipDeviceSynchronize"); }
+  // the device holds the ghost map and edge maps now; drop the host copies
+  std::vector<int32_t>().swap(h.g_dst);
+  std::vector<int32_t>().swap(h.g_ptr);
+  std::vector<int32_t>().swap(h.g_col);
+  std::vector<double>().swap(h.g_val);
+  std::vector<double>().swap(h.bt_conv);
+  *out = G;
+  return HOPE_OK;
+}
+
+int hope_grid_derive(const hope_grid* base, double axis_tilt, hope_grid** out) {
+  if (!base || !out) return fail(HOPE_ERR_INVALID, "null argument");
+  *out = nullptr;
+  if (!std::isfinite(axis_tilt)) return fail(HOPE_ERR_INVALID, "axis_tilt not finite");
+  hope_grid* G = new (std::nothrow) hope_grid();
+  if (!G) return fail(HOPE_ERR_NOMEM, "host allocation");
+  // scalars and small tables of the base; the large device maps are shared
+  const HostTables& b = base->h;
+  HostTables& h = G->h;
+  h.n = b.n; h.k = b.k; h.r = b.r; h.m = b.m; h.P = b.P; h.weno = b.weno; h.l = b.l; h.s = b.s;
+  h.radius = b.radius; h.omega = b.omega; h.tilt = axis_tilt; h.eps = b.eps; h.theta = b.theta;
+  h.delta = b.delta; h.ghost_sweeps = b.ghost_sweeps;
+  h.fcoef.resize(18);
+  coriolis_coefs(axis_tilt, h.fcoef.data());
+  G->gs = base->gs;
+  G->g = base->g;
+  G->itab = base->itab;
+  G->gt_rows = base->gt_rows;
+  G->gt_cell = base->gt_cell;
+  G->gt_ptr = base->gt_ptr;
+  G->gt_row = base->gt_row;
+  G->gt_val = base->gt_val;
+  G->gt_nnz = base->gt_nnz;
+  G->strip_w = base->strip_w;
+  G->seg_h = base->seg_h;
+  const TabOffsets O = tab_offsets(h.k, h.weno != 0, h.m, h.n);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, sizeof(double) * O.total);
+  if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipMalloc (derived tables)"); }
+  G->allocs.push_back(p);
+  G->device_bytes += sizeof(double) * O.total;
+  e = hipMemcpy(p, base->tab, sizeof(double) * O.total, hipMemcpyDeviceToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(static_cast<double*>(p) + O.fcoef, h.fcoef.data(), 18 * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipMemcpy (derived tables)"); }
+  G->tab = static_cast<const double*>(p);
+  p = nullptr;
+  e = hipMalloc(&p, sizeof(double) * 24 * (size_t)h.n * h.m * 3);
+  if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipMalloc (edge traces)"); }
+  G->allocs.push_back(p);
+  G->device_bytes += sizeof(double) * 24 * (size_t)h.n * h.m * 3;
+  G->bt = static_cast<double*>(p);
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipDeviceSynchronize"); }
   *out = G;
   return HOPE_OK;
 }
@@ -272,8 +326,8 @@ int hope_grid_layout(const hope_grid* G, hope_layout* out) {
   }
   out->rk_vjp_workspace_bytes =
       (2 * out->state_elems + 2 * out->interior_elems) * (int64_t)sizeof(double) + out->vjp_workspace_bytes;
-  out->ghost_cells = (int64_t)h.g_dst.size();
-  out->ghost_nnz = (int64_t)h.g_col.size();
+  out->ghost_cells = G->g.rows;
+  out->ghost_nnz = G->g.nnz;
   out->device_bytes = (int64_t)G->device_bytes;
   return HOPE_OK;
 }

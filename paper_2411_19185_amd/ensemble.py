@@ -31,6 +31,8 @@ class Ensemble:
         if n == 0:
             raise ValueError("an ensemble needs at least one member")
         self.grids = list(grids)       # the grids must outlive the batch
+        self.axis_tilt = list(axis_tilt) if axis_tilt is not None else None
+        self._member_grids: dict[int, Grid] = {}
         arr = (ctypes.c_void_p * n)(*[g._h.value for g in grids])
         tilt = (ctypes.c_double * n)(*axis_tilt) if axis_tilt is not None else None
         h = ctypes.c_void_p()
@@ -124,6 +126,25 @@ class Ensemble:
         with torch.cuda.graph(graph):
             self.rk_step(q_all, dt, ws, scheme)
         return graph
+
+    def member_grid(self, i: int) -> Grid:
+        """A single-grid handle for member i (its grid with its own axis tilt,
+        sharing the grid's ghost map), for per-member work such as adjoints."""
+        if i not in self._member_grids:
+            g = self.grids[i]
+            self._member_grids[i] = g if self.axis_tilt is None else g.derive(self.axis_tilt[i])
+        return self._member_grids[i]
+
+    def member_loss_gradient(self, i: int, q0: torch.Tensor, dt: float, steps: int, checkpoint_every: int = 5,
+                             scheme: str = "ssp3") -> torch.Tensor:
+        """d/dq0 of 0.5 ||q_T||^2 for member i after ``steps`` Runge-Kutta steps
+        from its interior state q0 (3, 6, n, n): checkpointed forward, then the
+        hand-written step adjoints in reverse."""
+        from .autograd import rollout
+        q = q0.detach().clone().requires_grad_(True)
+        qT = rollout(self.member_grid(i), q, dt, steps, checkpoint_every, scheme)
+        (0.5 * (qT * qT).sum()).backward()
+        return q.grad
 
     # ------------------------------------------------------------------
     def set_launch(self, strip_w: list[int] | None = None, seg_h: list[int] | None = None, blocks: int = 0):

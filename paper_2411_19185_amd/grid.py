@@ -36,6 +36,23 @@ class Grid:
         self.P = lay.padded
         self.m = lay.n_gauss
 
+    def derive(self, axis_tilt: float) -> "Grid":
+        """The same grid with another tilt of the rotation axis, sharing this
+        grid's ghost map on the device (this grid is kept alive with it)."""
+        h = ctypes.c_void_p()
+        check(lib().hope_grid_derive(self._h, float(axis_tilt), ctypes.byref(h)))
+        g = Grid.__new__(Grid)
+        g.desc = make_desc(self.n, self.order, self.scheme, self.desc.radius, self.desc.omega, axis_tilt,
+                           self.desc.weno_eps, self.desc.split_theta)
+        g._h = h
+        g._base = self
+        lay = Layout()
+        check(lib().hope_grid_layout(h, ctypes.byref(lay)))
+        g.layout = lay
+        g.n, g.order, g.scheme = self.n, self.order, self.scheme
+        g.r, g.P, g.m = self.r, self.P, self.m
+        return g
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:

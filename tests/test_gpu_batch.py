@@ -20,14 +20,14 @@ def _grid(n, order, scheme, alpha=0.0):
     return Grid(n, order, scheme, axis_tilt=alpha)
 
 
-def _setup(ns, order=5, scheme="weno", seed=0):
+def _setup(ns, order=5, scheme="weno", seed=0, state="member"):
     """A batch whose members share one grid per resolution, each member with
     its own tilt and state (seeded), plus per-member reference grids."""
     from paper_2411_19185_amd.ensemble import Ensemble
     shared = {n: _grid(n, order, scheme) for n in sorted(set(ns))}
     tilts, states = [], []
     for i, n in enumerate(ns):
-        alpha, q = STATES["member"](n, seed + i, nq=2)
+        alpha, q = STATES[state](n, seed + i, nq=2)
         tilts.append(alpha)
         states.append(q)
     ens = Ensemble([shared[n] for n in ns], axis_tilt=tilts)
@@ -159,4 +159,38 @@ def test_full_size_uneven_ensemble_against_member_grids_and_oracle():
     ref = ssp_rk3(og.tendency, states[0], dts[0])
     err = rel_err(first, ref)
     print("oracle rel err", err, flush=True)
+    assert max(err) < TOL, err
+
+
+def test_derived_member_grid_equals_a_fresh_grid_and_member_gradient():
+    """A member's derived grid (its tilt, the shared ghost map) gives bitwise
+    the tendency and adjoint of a grid built from scratch with that tilt, and
+    the ensemble's per-member loss gradient matches autograd over the oracle."""
+    ns = [10, 12]
+    ens, q_all, tilts, states, _ = _setup(ns, seed=500, state="perturbed_member")
+    for i, n in enumerate(ns):
+        g = ens.member_grid(i)
+        fresh = _grid(n, 5, "weno", tilts[i])
+        qa = to_padded(states[i], g.r)
+        a = g.tendency(qa)
+        b = fresh.tendency(to_padded(states[i], g.r))
+        w = torch.tensor(hi.normal_array(600 + i, (3, 6, n, n))).cuda()
+        va = g.tendency_vjp(to_padded(states[i], g.r), w)
+        vb = fresh.tendency_vjp(to_padded(states[i], g.r), w)
+        torch.cuda.synchronize()
+        same = torch.equal(a, b) and torch.equal(va, vb)
+        assert same, i
+    # gradient of 0.5 ||q_T||^2 after 2 steps, member 0, against the oracle
+    from oracle.rk import ssp_rk3 as oracle_step
+    q0 = states[0]
+    dt = cfl_dt(q0)
+    grad = ens.member_loss_gradient(0, ens.member_interior(q_all, 0).contiguous(), dt, 2, checkpoint_every=1)
+    og = oracle_grid(ns[0], 5, "weno", tilts[0])
+    qq = q0.clone().requires_grad_(True)
+    x = qq
+    for _ in range(2):
+        x = oracle_step(og.tendency, x, dt)
+    (0.5 * (x * x).sum()).backward()
+    err = rel_err(grad, qq.grad)
+    print("member gradient rel err", err, flush=True)
     assert max(err) < TOL, err
