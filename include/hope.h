@@ -130,8 +130,8 @@ int hope_tendency(const hope_grid* grid, double* q, double* dqdt, void* stream);
  * ghost-cell cotangents folded back through G^T.  q's ghost rings are scratch.
  * Non-smooth points (|m|, |beta_i - beta_j|) take the subgradient sign(0)=0.
  * ws: caller-owned device workspace of at least layout.vjp_workspace_bytes
- * (8 * (2*3*(4m+m^2) + 3*order^2 [WENO only]) bytes per cell plus one padded
- * state); gq must not alias w. */
+ * (8 * (2*3*(4m+m^2) + 3*order^2) bytes per cell plus one padded state); gq
+ * must not alias w. */
 int hope_tendency_vjp(const hope_grid* grid, double* q, const double* w, double* gq, double* ws,
                       size_t ws_bytes, void* stream);
 

@@ -305,7 +305,7 @@ static size_t vjp_elems(const HostTables& h, size_t* nT, size_t* nD, size_t* nG)
   const size_t cells = 6ULL * h.n * h.n;
   const size_t np = 4 * h.m + h.m * h.m;
   *nT = cells * np * 3;
-  *nD = h.weno ? cells * h.k * h.k * 3 : 0;
+  *nD = cells * h.k * h.k * 3;
   *nG = 18ULL * h.P * h.P;
   return 2 * *nT + *nD + *nG;
 }
@@ -404,7 +404,6 @@ int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq
   a.gt_val = G->gt_val;
   a.gt_nnz = G->gt_nnz;
   for (int step = 0; step < kVjpSteps; ++step) {
-    if (step == kVjpWeno && !h.weno) continue;
     Timed tm(G, 3 + step, stream);
     e = launch_vjp(h.k, h.weno, a, step, stream);
     if (e) return hip_fail((hipError_t)e, "adjoint launch");

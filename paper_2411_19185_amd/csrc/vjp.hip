@@ -15,6 +15,7 @@
 //                   (3.26)-(3.29)
 //   k_vjp_weno      WENO: cotangents of the stencil cell values through the
 //                   nonlinear weights, tau, beta and the sub-stencil values
+//   k_vjp_tpp       TPP: the same for the linear reconstruction (separable)
 //   k_vjp_gather    cotangent of every padded cell (interior and ghost)
 //   k_vjp_interior  the interior cotangent
 //   k_vjp_ghost_t   plus G^T times the ghost cotangents
@@ -75,14 +76,14 @@ __device__ __forceinline__ void lmars_adj(const double* qL, const double* qR, do
   phiLb += 0.5 * msb * ic;
   const double icb = -0.5 * msb * (phiR - phiL);
   cb -= icb * ic * ic;
-  phiLb += 0.5 * cb * 0.5 / sL;
-  phiRb += 0.5 * cb * 0.5 / sR;
+  phiLb += 0.25 * cb * rcp(sL);
+  phiRb += 0.25 * cb * rcp(sR);
   bL[1] += dir == 0 ? upLb * iL : 0.0;
   bL[2] += dir == 0 ? 0.0 : upLb * iL;
-  bL[0] -= upLb * upL / qL[0];
+  bL[0] -= upLb * upL * (iL * sgii);        // upL / qL[0]
   bR[1] += dir == 0 ? upRb * iR : 0.0;
   bR[2] += dir == 0 ? 0.0 : upRb * iR;
-  bR[0] -= upRb * upR / qR[0];
+  bR[0] -= upRb * upR * (iR * sgii);
   bL[0] += phiLb * isg;
   bR[0] += phiRb * isg;
 }
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
   double kap[S], kapb[S];
 #pragma unroll
   for (int jj = 0; jj < S; ++jj) {
-    kap[jj] = 1.0 + tau / (beta[jj] + gs.eps);
+    kap[jj] = fma(tau, rcp(beta[jj] + gs.eps), 1.0);
     kapb[jj] = 0.0;
   }
   // points, grouped by their x-axis coordinate
@@ -428,8 +429,9 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
           dm = fma(gm[pt * S + jj], kap[jj], dm);
         }
       const double sp = tab[C::O.sp + pt], sm = tab[C::O.sm + pt];
-      const double apb = lb * sp / dp, dpb = -lb * sp * ap / (dp * dp);
-      const double amb = -lb * sm / dm, dmb = lb * sm * am / (dm * dm);
+      const double idp = rcp(dp), idm = rcp(dm);
+      const double apb = lb * sp * idp, dpb = -apb * ap * idp;
+      const double amb = -lb * sm * idm, dmb = -amb * am * idm;
 #pragma unroll
       for (int sy = 0; sy < L; ++sy)
 #pragma unroll
@@ -455,7 +457,7 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
   double taub = 0, betab[S];
 #pragma unroll
   for (int jj = 0; jj < S; ++jj) {
-    const double ib = 1.0 / (beta[jj] + gs.eps);
+    const double ib = rcp(beta[jj] + gs.eps);
     taub += kapb[jj] * ib;
     betab[jj] = -kapb[jj] * tau * ib * ib;
   }
@@ -511,15 +513,66 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
 }
 
 // ---------------------------------------------------------------------------
-// k_vjp_gather: cotangent of padded cell (v, p, jj, ii)
+// k_vjp_tpp: TPP (linear) reconstruction adjoint, Dl as in k_vjp_weno.  A
+// point value is wy[py] (x) wx[px] applied to the stencil, so the cotangent of
+// stencil cell (row, col) is sum over points of lam_pt wc[py][row] wc[px][col];
+// per row: first the y-sums for each x axis point, then the x-sums.
+// ---------------------------------------------------------------------------
+template <int K, bool W, int M>
+__global__ __launch_bounds__(64) void k_vjp_tpp(const double* __restrict__ tab_, GridScalars gs,
+                                                 const double* __restrict__ Lam, double* __restrict__ Dl) {
+  using C = Cfg<K, W, M>;
+  constexpr int NA = C::NA;
+  const cdp tab = (cdp)tab_;
+  const int n = gs.n;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 18 * n * n) return;
+  const int cells = 6 * n * n;
+  const int v = idx / cells, c = idx % cells;
+  cdp wc = tab + C::O.wc;
+  const double* lam = Lam + (size_t)v * cells + c;     // point pt at lam[pt * 3 * cells]
+  auto L = [&](int pt) -> double { return lam[(size_t)pt * 3 * cells]; };
+  double* out = Dl + (size_t)v * cells + c;
+#pragma unroll 1
+  for (int row = 0; row < K; ++row) {
+    double yr[NA];
+#pragma unroll
+    for (int px = 0; px < 2; ++px) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) s = fma(L(px * M + k), wc[(2 + k) * K + row], s);
+      yr[px] = s;
+    }
+#pragma unroll
+    for (int h = 0; h < M; ++h) {
+      double s = L(2 * M + h) * wc[0 * K + row];
+      s = fma(L(3 * M + h), wc[1 * K + row], s);
+#pragma unroll
+      for (int w = 0; w < M; ++w) s = fma(L(4 * M + w * M + h), wc[(2 + w) * K + row], s);
+      yr[2 + h] = s;
+    }
+#pragma unroll
+    for (int col = 0; col < K; ++col) {
+      double s = 0.0;
+#pragma unroll
+      for (int px = 0; px < NA; ++px) s = fma(yr[px], wc[px * K + col], s);
+      out[(size_t)(row * K + col) * 3 * cells] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_vjp_gather: cotangent of padded cell (v, p, jj, ii) = sum of the stencil
+// cotangents Dl of the cells whose stencil holds it
 // ---------------------------------------------------------------------------
 template <int K, bool W, int M>
 __global__ __launch_bounds__(256) void k_vjp_gather(const double* __restrict__ tab_, GridScalars gs,
                                                      const double* __restrict__ Lam, const double* __restrict__ Dl,
                                                      double* __restrict__ gpad) {
   using C = Cfg<K, W, M>;
-  constexpr int NP = 4 * M + M * M, R = C::R, NA = C::NA;
-  const cdp tab = (cdp)tab_;
+  constexpr int R = C::R;
+  (void)tab_;
+  (void)Lam;
   const int n = gs.n, P = gs.P;
   const size_t total = (size_t)18 * P * P;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -535,20 +588,7 @@ __global__ __launch_bounds__(256) void k_vjp_gather(const double* __restrict__ t
       if (i < 0 || i >= n) continue;
       const int c = (p * n + j) * n + i;
       const int o = (dy + R) * K + (dx + R);
-      if constexpr (W) {
-        acc += Dl[((size_t)o * 3 + v) * cells + c];
-      } else {
-        // TPP: sum over the cell's points of lam_pt * wy[py][dy] * wx[px][dx]
-        cdp wc = tab + C::O.wc;
-        const double* lam = Lam + (size_t)v * cells + c;
-        for (int pt = 0; pt < NP; ++pt) {
-          int px, py;
-          if (pt < 2 * M) { px = pt / M; py = 2 + pt % M; }
-          else if (pt < 4 * M) { py = (pt - 2 * M) / M; px = 2 + (pt - 2 * M) % M; }
-          else { const int q2 = pt - 4 * M; px = 2 + q2 % M; py = 2 + q2 / M; }
-          acc += lam[(size_t)pt * 3 * cells] * wc[py * K + (dy + R)] * wc[px * K + (dx + R)];
-        }
-      }
+      acc += Dl[((size_t)o * 3 + v) * cells + c];
     }
   }
   gpad[idx] = acc;
@@ -632,6 +672,9 @@ static int vjp_t(const VjpArgs& a, int step, void* stream) {
     case kVjpWeno:
       if constexpr (W)
         hipLaunchKernelGGL((k_vjp_weno<K, W, M>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q, a.Lam,
+                           a.Dl);
+      else
+        hipLaunchKernelGGL((k_vjp_tpp<K, W, M>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.Lam,
                            a.Dl);
       break;
     case kVjpGather: {
