@@ -32,16 +32,22 @@ PEAK_FP64 = 78.6e12        # MI355X FP64 vector, FLOP/s
 PEAK_HBM = 8.0e12          # bytes/s
 
 
-def flops_per_cell(order: int, scheme: str) -> float:
+def flops_per_cell(order: int, scheme: str, direct: bool = False) -> float:
     """FLOPs of one tendency evaluation of one cell as the fused kernel
     computes it for an owned cell (FMA = 2, add/mul/div/sqrt = 1).
 
-    Per variable: WENO x-pass 5 axis points x l sub-stencils x (2r+1) rows x l
-    taps, and for every one of the 4m+m^2 points l^2 sub-stencil values (l
-    taps) plus the split combination; smoothness indicators by an l x l
-    transform per sub-stencil and weighted squares; tau and kappa.  TPP: (2+m)
-    axis points x k rows x k taps and k taps per point.  Per cell: LMARS at 2m
-    edge points (64 FLOPs + quadrature), sources at m^2 points (43 FLOPs +
+    Per variable: the x-pass at the m+2 axis points (l sub-stencils x (2r+1)
+    rows x l taps), the smoothness indicators (an l x l transform per
+    sub-stencil and weighted squares), tau and kappa.  The 4m+m^2 point values
+    are evaluated by columns: the linear weights factor as gamma = d(py) d(px),
+    so per x axis point the sums over sub-stencil columns (l^2 products with
+    kappa, l^3 FMAs with the x-pass) are shared by its points, and a point
+    costs 2 l^2 + 4 l + 2 where all its gamma are positive and more where the
+    split of negative weights is needed (the centre Gauss node of order 5).
+    ``direct`` counts the point-by-point evaluation instead (l^2 sub-stencil
+    values of l taps each and the split sums per point).  TPP: (2+m) axis
+    points x k rows x k taps and k taps per point.  Per cell: LMARS at 2m edge
+    points (64 FLOPs + quadrature), sources at m^2 points (43 FLOPs +
     quadrature), assembly and the Runge-Kutta combination.
     """
     k = order
@@ -55,8 +61,18 @@ def flops_per_cell(order: int, scheme: str) -> float:
         tau = 2 * (s * (s - 1) // 2) + 1
         kappa = 3 * s
         xpass = (2 + m) * l * (2 * r + 1) * 2 * l
-        point = 2 * s * l + 8 * s + 7
-        per_var = beta + tau + kappa + xpass + npts * point
+        if direct:
+            points = npts * (2 * s * l + 8 * s + 7)
+        else:
+            nm = 1 if k == 5 else 0                     # Gauss nodes whose 1D weights change sign
+            col = 2 * l * l + 2 * l ** 3
+            cols = (2 + m - nm) * col + nm * 2 * col
+            n_xm = nm * (2 + m)
+            n_ym = 2 * nm + nm * (m - nm)
+            n_pos = npts - n_xm - n_ym
+            points = cols + n_pos * (2 * l * l + 4 * l + 2) + n_ym * (2 * l * l + 8 * l + 16) \
+                + n_xm * (4 * l * l + 8 * l + 16)
+        per_var = beta + tau + kappa + xpass + points
     else:
         per_var = (2 + m) * k * 2 * k + npts * 2 * k
     lmars = 2 * m * (64 + 2)
@@ -194,7 +210,8 @@ def run(args):
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
                      "traffic": None if traffic is None else traffic["bytes_per_launch"],
                      "traffic_detail": traffic, "stage_source_hash": stage_source_hash(),
-                     "flops_per_cell": fpc, "stage_avg_ms": stage_avg, "stage_launches": st_n,
+                     "flops_per_cell": fpc, "flops_per_cell_direct": flops_per_cell(order, scheme, direct=True),
+                     "stage_avg_ms": stage_avg, "stage_launches": st_n,
                      "hbm_effective_GBps": stage_bytes_per_cell() * cells / (stage_avg / 1e3) / 1e9,
                      "hbm_frac": stage_bytes_per_cell() * cells / (stage_avg / 1e3) / PEAK_HBM},
         "kernels_ms_avg": {"stage": stage_avg, "fill_halo": halo_ms / max(halo_n, 1),

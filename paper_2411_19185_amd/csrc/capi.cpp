@@ -156,6 +156,8 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
       put(O.gm, h.gm);
       put(O.sp, h.sp);
       put(O.sm, h.sm);
+      put(O.d1, h.d1);
+      tab[O.theta] = h.theta;
       put(O.V, h.V);
       put(O.lam, h.lam);
     }

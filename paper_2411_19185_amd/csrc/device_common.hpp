@@ -210,4 +210,102 @@ __device__ __forceinline__ double point(TP tab, int py, int pt, const double* xr
 }
 
 
+// ---------------------------------------------------------------------------
+// Genuine 2D WENO by columns.  The linear weights of a point factor as
+// gamma_j = d_sy(py) d_sx(px) (tensor product of the 1D linear weights), and
+// the split (3.20) gives gamma+- = (theta |gamma| +- gamma) / 2, so with
+//   B = sum_j gamma_j kappa_j p_j,  A = sum_j |gamma_j| kappa_j p_j,
+//   D = sum_j gamma_j kappa_j,      C = sum_j |gamma_j| kappa_j
+// the value (3.21) is sigma+ (theta A + B)/(theta C + D)
+//                     - sigma- (theta A - B)/(theta C - D),
+// and where every gamma of the point is positive (A = B, C = D) it is B / D.
+// The sums over the sub-stencil columns sx are shared by all points of one x
+// axis point px: with the x-pass xr (sub-stencil sx, stencil row) and
+//   Z[sy][b] = sum_sx d_sx kappa_(sy,sx) xr[sx][sy+b],  E[sy] = sum_sx d_sx kappa_(sy,sx)
+// a point needs only B = sum_sy d_sy(py) sum_b w_(sy,b)(py) Z[sy][b] and
+// D = sum_sy d_sy(py) E[sy] (and their |d| versions).
+// ---------------------------------------------------------------------------
+template <int K, int M>
+struct WCol {
+  static constexpr int L = (K + 1) / 2;
+  double E[L], Z[L][L];       // with d_sx
+  double Ea[L], Za[L][L];     // with |d_sx| (axis points of mixed sign only)
+};
+
+// column sums of x axis point px from its x-pass xr and the weights kappa
+template <int K, bool W, int M, typename TP, typename Kap>
+__device__ __forceinline__ void wcol(TP tab, int px, const double* xr, Kap kap, WCol<K, M>& c) {
+  using C = Cfg<K, W, M>;
+  constexpr int L = C::L, NR = C::NR;
+  TP d1 = tab + C::O.d1;
+  const bool mixed = weno_mixed_axis(K, M, px);
+#pragma unroll
+  for (int sy = 0; sy < L; ++sy) {
+    double e[L];
+    double E = 0.0;
+#pragma unroll
+    for (int sx = 0; sx < L; ++sx) {
+      e[sx] = d1[px * L + sx] * kap(sy * L + sx);
+      E += e[sx];
+    }
+    c.E[sy] = E;
+#pragma unroll
+    for (int b = 0; b < L; ++b) {
+      double z = 0.0;
+#pragma unroll
+      for (int sx = 0; sx < L; ++sx) z = fma(e[sx], xr[sx * NR + sy + b], z);
+      c.Z[sy][b] = z;
+    }
+    if (mixed) {
+      double Ea = 0.0;
+#pragma unroll
+      for (int sx = 0; sx < L; ++sx) {
+        e[sx] = fabs(d1[px * L + sx]) * kap(sy * L + sx);
+        Ea += e[sx];
+      }
+      c.Ea[sy] = Ea;
+#pragma unroll
+      for (int b = 0; b < L; ++b) {
+        double z = 0.0;
+#pragma unroll
+        for (int sx = 0; sx < L; ++sx) z = fma(e[sx], xr[sx * NR + sy + b], z);
+        c.Za[sy][b] = z;
+      }
+    }
+  }
+}
+
+// value at y axis point py (point number pt) of the column px prepared by wcol
+template <int K, bool W, int M, typename TP>
+__device__ __forceinline__ double wpoint(TP tab, int px, int py, int pt, const WCol<K, M>& c) {
+  using C = Cfg<K, W, M>;
+  constexpr int L = C::L, NA = C::NA;
+  TP wsub = tab + C::O.wsub, d1 = tab + C::O.d1;
+  const bool xm = weno_mixed_axis(K, M, px), ym = weno_mixed_axis(K, M, py);
+  double B = 0.0, D = 0.0, A = 0.0, Cs = 0.0;
+#pragma unroll
+  for (int sy = 0; sy < L; ++sy) {
+    double T = 0.0;
+#pragma unroll
+    for (int b = 0; b < L; ++b) T = fma(wsub[(sy * NA + py) * L + b], c.Z[sy][b], T);
+    const double dy = d1[py * L + sy];
+    B = fma(dy, T, B);
+    D = fma(dy, c.E[sy], D);
+    if (xm) {
+      double Ta = 0.0;
+#pragma unroll
+      for (int b = 0; b < L; ++b) Ta = fma(wsub[(sy * NA + py) * L + b], c.Za[sy][b], Ta);
+      A = fma(fabs(dy), Ta, A);
+      Cs = fma(fabs(dy), c.Ea[sy], Cs);
+    } else if (ym) {
+      A = fma(fabs(dy), T, A);
+      Cs = fma(fabs(dy), c.E[sy], Cs);
+    }
+  }
+  if (!xm && !ym) return B * rcp(D);
+  const double th = tab[C::O.theta];
+  const double np = fma(th, A, B), dp = fma(th, Cs, D), nm = fma(th, A, -B), dm = fma(th, Cs, -D);
+  return (tab[C::O.sp + pt] * np * dm - tab[C::O.sm + pt] * nm * dp) * rcp(dp * dm);
+}
+
 }  // namespace hope

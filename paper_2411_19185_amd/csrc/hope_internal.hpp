@@ -25,6 +25,7 @@ struct HostTables {
   std::vector<double> wc;              // (2+m) x k   centred TPP weights
   std::vector<double> wsub;            // l starts x (2+m) x l   sub-stencil weights
   std::vector<double> gp, gm, sp, sm;  // npts x s, npts x s, npts, npts
+  std::vector<double> d1;              // (2+m) x l   1D linear weights d_s at each axis point
   std::vector<double> V;               // l starts x l x l   smoothness transform
   std::vector<double> lam;             // l x l   smoothness eigen-weights
   std::vector<double> Xe;              // n+1   X at cell edges
@@ -65,7 +66,7 @@ int build_tables(HostTables& t, int n, int k, int weno, double radius, double om
 #endif
 
 struct TabOffsets {
-  int64_t wc, wsub, gp, gm, sp, sm, V, lam, gw, fcoef, fixed;
+  int64_t wc, wsub, gp, gm, sp, sm, d1, theta, V, lam, gw, fcoef, fixed;
   int64_t Xe, sqe, Xg, sqg, bt_conv, total;
   int64_t i_cell, i_side, i_rev, i_total;
 };
@@ -79,7 +80,9 @@ HOPE_HD constexpr TabOffsets tab_offsets(int k, bool weno, int m, int n) {
   o.gm = o.gp + (weno ? NP * S : 0);
   o.sp = o.gm + (weno ? NP * S : 0);
   o.sm = o.sp + (weno ? NP : 0);
-  o.V = o.sm + (weno ? NP : 0);
+  o.d1 = o.sm + (weno ? NP : 0);
+  o.theta = o.d1 + (weno ? NA * L : 0);
+  o.V = o.theta + (weno ? 1 : 0);
   o.lam = o.V + (weno ? L * L * L : 0);
   o.gw = o.lam + (weno ? L * L : 0);
   o.fcoef = o.gw + m;
@@ -96,6 +99,14 @@ HOPE_HD constexpr TabOffsets tab_offsets(int k, bool weno, int m, int n) {
   o.i_total = 72LL * n;
   return o;
 }
+
+// Axis points (0: -1/2, 1: +1/2, 2+h: Gauss node h) at which the 1D linear
+// weights of genuine 2D WENO (tensor factors of gamma, (3.19)) have mixed
+// signs: for order 5 the middle Gauss node (the cell centre); none for order
+// 3.  Elsewhere every gamma of a point is positive and the split (3.20)-(3.21)
+// reduces to the unsplit weights.  The host checks the computed weights
+// against this rule when it builds a grid.
+HOPE_HD constexpr bool weno_mixed_axis(int k, int m, int a) { return k == 5 && m % 2 == 1 && a == 2 + m / 2; }
 
 // Scalars every kernel needs.
 struct GridScalars {

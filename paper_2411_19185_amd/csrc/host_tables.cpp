@@ -647,6 +647,18 @@ int build_tables(HostTables& t, int n, int k, int weno, double radius, double om
         t.error = "WENO linear weights: no exact solution";
         return HOPE_ERR_NUMERIC;
       }
+    t.d1.resize((2 + m) * l);
+    for (int a = 0; a < 2 + m; ++a) {
+      bool neg = false;
+      for (int i = 0; i < l; ++i) {
+        t.d1[a * l + i] = (double)d[a * l + i];
+        neg = neg || d[a * l + i] < 0;
+      }
+      if (neg != weno_mixed_axis(k, m, a)) {
+        t.error = "WENO linear weights: sign pattern differs from the one the kernels are built for";
+        return HOPE_ERR_NUMERIC;
+      }
+    }
     // point order: x-edge left (h), x-edge right (h), y-edge bottom (h), y-edge top (h), CQP (v outer, h inner)
     auto pt_axes = [&](int pt, int& ax, int& ay) {
       if (pt < m) { ax = 0; ay = 2 + pt; }

@@ -75,13 +75,26 @@ __device__ __forceinline__ void edge_trace(cdp tab, cip itab, const GridScalars&
     double xr[C::XR];
     if (sd < 2) {
       xpass<K, W, M>(tab, sd, at, xr);
+      if constexpr (W) {
+        WCol<K, M> col;
+        wcol<K, W, M>(tab, sd, xr, kf, col);
 #pragma unroll
-      for (int h = 0; h < M; ++h) vals[v][h] = point<K, W, M>(tab, 2 + h, sd * M + h, xr, kf);
+        for (int h = 0; h < M; ++h) vals[v][h] = wpoint<K, W, M>(tab, sd, 2 + h, sd * M + h, col);
+      } else {
+#pragma unroll
+        for (int h = 0; h < M; ++h) vals[v][h] = point<K, W, M>(tab, 2 + h, sd * M + h, xr, kf);
+      }
     } else {
 #pragma unroll
       for (int h = 0; h < M; ++h) {
         xpass<K, W, M>(tab, 2 + h, at, xr);
-        vals[v][h] = point<K, W, M>(tab, sd - 2, (sd == 2 ? 2 * M : 3 * M) + h, xr, kf);
+        if constexpr (W) {
+          WCol<K, M> col;
+          wcol<K, W, M>(tab, 2 + h, xr, kf, col);
+          vals[v][h] = wpoint<K, W, M>(tab, 2 + h, sd - 2, (sd == 2 ? 2 * M : 3 * M) + h, col);
+        } else {
+          vals[v][h] = point<K, W, M>(tab, sd - 2, (sd == 2 ? 2 * M : 3 * M) + h, xr, kf);
+        }
       }
     }
   }
@@ -202,22 +215,48 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     kappa(pc, kap);
     auto kf = [&](int j) -> double { return kap[j]; };
     double xr[XR];
-    asm volatile("" ::: "memory");
-    xpass<K, W, M>(tab, 0, win(pc), xr);
+    if constexpr (W) {
+      // WENO by columns: the sums over sub-stencil columns are shared by the
+      // points of one x axis point
+      WCol<K, M> col;
 #pragma unroll
-    for (int h = 0; h < M; ++h) pt(wv, h) = point<K, W, M>(tab, 2 + h, h, xr, kf);
-    asm volatile("" ::: "memory");
-    xpass<K, W, M>(tab, 1, win(pc), xr);
+      for (int sd = 0; sd < 2; ++sd) {
+        asm volatile("" ::: "memory");
+        xpass<K, W, M>(tab, sd, win(pc), xr);
+        wcol<K, W, M>(tab, sd, xr, kf, col);
 #pragma unroll
-    for (int h = 0; h < M; ++h) pt(wv, M + h) = point<K, W, M>(tab, 2 + h, M + h, xr, kf);
-#pragma unroll 1
-    for (int h = 0; h < M; ++h) {
+        for (int h = 0; h < M; ++h) pt(wv, sd * M + h) = wpoint<K, W, M>(tab, sd, 2 + h, sd * M + h, col);
+      }
+#pragma unroll
+      for (int h = 0; h < M; ++h) {
+        asm volatile("" ::: "memory");
+        xpass<K, W, M>(tab, 2 + h, win(pc), xr);
+        wcol<K, W, M>(tab, 2 + h, xr, kf, col);
+        pt(wv, 2 * M + h) = wpoint<K, W, M>(tab, 2 + h, 0, 2 * M + h, col);
+        pt(wv, 3 * M + h) = wpoint<K, W, M>(tab, 2 + h, 1, 3 * M + h, col);
+#pragma unroll
+        for (int w = 0; w < M; ++w)
+          pt(wv, 4 * M + w * M + h) = wpoint<K, W, M>(tab, 2 + h, 2 + w, 4 * M + w * M + h, col);
+      }
+    } else {
       asm volatile("" ::: "memory");
-      xpass<K, W, M>(tab, 2 + h, win(pc), xr);
-      pt(wv, 2 * M + h) = point<K, W, M>(tab, 0, 2 * M + h, xr, kf);
-      pt(wv, 3 * M + h) = point<K, W, M>(tab, 1, 3 * M + h, xr, kf);
+      xpass<K, W, M>(tab, 0, win(pc), xr);
 #pragma unroll
-      for (int w = 0; w < M; ++w) pt(wv, 4 * M + w * M + h) = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+      for (int h = 0; h < M; ++h) pt(wv, h) = point<K, W, M>(tab, 2 + h, h, xr, kf);
+      asm volatile("" ::: "memory");
+      xpass<K, W, M>(tab, 1, win(pc), xr);
+#pragma unroll
+      for (int h = 0; h < M; ++h) pt(wv, M + h) = point<K, W, M>(tab, 2 + h, M + h, xr, kf);
+#pragma unroll 1
+      for (int h = 0; h < M; ++h) {
+        asm volatile("" ::: "memory");
+        xpass<K, W, M>(tab, 2 + h, win(pc), xr);
+        pt(wv, 2 * M + h) = point<K, W, M>(tab, 0, 2 * M + h, xr, kf);
+        pt(wv, 3 * M + h) = point<K, W, M>(tab, 1, 3 * M + h, xr, kf);
+#pragma unroll
+        for (int w = 0; w < M; ++w)
+          pt(wv, 4 * M + w * M + h) = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+      }
     }
   };
   // top (side 1) or bottom (side 0) traces of row pc, into dst(h)
@@ -230,7 +269,15 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       double xr[XR];
       asm volatile("" ::: "memory");
       xpass<K, W, M>(tab, 2 + h, win(pc), xr);
-      dst(h) = point<K, W, M>(tab, side, (2 + side) * M + h, xr, kf);
+      if constexpr (W) {
+        // the same arithmetic as recon_row, so that a trace does not depend on
+        // whether its row is reconstructed whole or only for its side
+        WCol<K, M> col;
+        wcol<K, W, M>(tab, 2 + h, xr, kf, col);
+        dst(h) = wpoint<K, W, M>(tab, 2 + h, side, (2 + side) * M + h, col);
+      } else {
+        dst(h) = point<K, W, M>(tab, side, (2 + side) * M + h, xr, kf);
+      }
     }
   };
 

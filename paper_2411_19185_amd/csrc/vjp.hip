@@ -136,22 +136,31 @@ __global__ __launch_bounds__(64) void k_vjp_traces(const double* __restrict__ ta
     if constexpr (W) weno_kappa<K, W, M>(tab, gs.eps, at, [&](int jj, double x) { kap[jj] = x; });
     auto kf = [&](int jj) -> double { return kap[jj]; };
     double xr[C::XR];
+    // a point's value as the forward computes it (WENO by columns)
+    auto column = [&](int px, auto&& emit) {
+      xpass<K, W, M>(tab, px, at, xr);
+      if constexpr (W) {
+        WCol<K, M> col;
+        wcol<K, W, M>(tab, px, xr, kf, col);
+        emit([&](int py, int pt) { return wpoint<K, W, M>(tab, px, py, pt, col); });
+      } else {
+        emit([&](int py, int pt) { return point<K, W, M>(tab, py, pt, xr, kf); });
+      }
+    };
 #pragma unroll
-    for (int sd = 0; sd < 2; ++sd) {
-      xpass<K, W, M>(tab, sd, at, xr);
+    for (int sd = 0; sd < 2; ++sd)
+      column(sd, [&](auto val) {
 #pragma unroll
-      for (int h = 0; h < M; ++h)
-        out[((sd * M + h) * 3 + v) * cells] = point<K, W, M>(tab, 2 + h, sd * M + h, xr, kf);
-    }
+        for (int h = 0; h < M; ++h) out[((sd * M + h) * 3 + v) * cells] = val(2 + h, sd * M + h);
+      });
 #pragma unroll 1
-    for (int h = 0; h < M; ++h) {
-      xpass<K, W, M>(tab, 2 + h, at, xr);
-      out[((2 * M + h) * 3 + v) * cells] = point<K, W, M>(tab, 0, 2 * M + h, xr, kf);
-      out[((3 * M + h) * 3 + v) * cells] = point<K, W, M>(tab, 1, 3 * M + h, xr, kf);
+    for (int h = 0; h < M; ++h)
+      column(2 + h, [&](auto val) {
+        out[((2 * M + h) * 3 + v) * cells] = val(0, 2 * M + h);
+        out[((3 * M + h) * 3 + v) * cells] = val(1, 3 * M + h);
 #pragma unroll
-      for (int w = 0; w < M; ++w)
-        out[((4 * M + w * M + h) * 3 + v) * cells] = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
-    }
+        for (int w = 0; w < M; ++w) out[((4 * M + w * M + h) * 3 + v) * cells] = val(2 + w, 4 * M + w * M + h);
+      });
   }
 }
 
