@@ -348,7 +348,7 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
   const double* c0 = q + v * vs + (size_t)p * P * P + (size_t)(j + R) * P + (i + R);
   auto at = [&](int dy, int dx) -> double { return c0[dy * P + dx]; };
   const double* lam = Lam + (size_t)v * cells + c;     // point pt at lam[pt * 3 * cells]
-  cdp V = tab + C::O.V, lamq = tab + C::O.lam, wsub = tab + C::O.wsub, gp = tab + C::O.gp, gm = tab + C::O.gm;
+  cdp V = tab + C::O.V, lamq = tab + C::O.lam, wsub = tab + C::O.wsub;
   double dq[K * K];
 #pragma unroll
   for (int o = 0; o < K * K; ++o) dq[o] = 0.0;
@@ -395,10 +395,16 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
     kap[jj] = fma(tau, rcp(beta[jj] + gs.eps), 1.0);
     kapb[jj] = 0.0;
   }
-  // points, grouped by their x-axis coordinate
+  // points, grouped by their x axis point px, evaluated by columns as the
+  // forward does (wcol / wpoint): per column Z[sy][b] = sum_sx e[sy][sx]
+  // xr[sx][sy+b] and E[sy] = sum_sx e[sy][sx] with e = d_sx kappa (and the
+  // |d_sx| versions Za, Ea for the centre node); per point B, D (and A, C)
+  cdp d1 = tab + C::O.d1;
+  const double th = tab[C::O.theta];
 #pragma unroll 1
   for (int px = 0; px < NA; ++px) {
-    double xr[L * NR], xrb[L * NR];
+    const bool xm = weno_mixed_axis(K, M, px);
+    double xr[L * NR];
 #pragma unroll
     for (int sx = 0; sx < L; ++sx)
 #pragma unroll
@@ -407,10 +413,40 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
 #pragma unroll
         for (int a = 0; a < L; ++a) s = fma(wsub[(sx * NA + px) * L + a], at(row - R, sx - (L - 1) + a), s);
         xr[sx * NR + row] = s;
-        xrb[sx * NR + row] = 0.0;
       }
+    double e[L][L], E[L], Z[L][L], ea[L][L], Ea[L], Za[L][L];
+    double Zb[L][L], Eb[L], Zab[L][L], Eab[L];
+#pragma unroll
+    for (int sy = 0; sy < L; ++sy) {
+      E[sy] = 0.0;
+      Ea[sy] = 0.0;
+      Eb[sy] = 0.0;
+      Eab[sy] = 0.0;
+#pragma unroll
+      for (int sx = 0; sx < L; ++sx) {
+        e[sy][sx] = d1[px * L + sx] * kap[sy * L + sx];
+        E[sy] += e[sy][sx];
+        if (xm) {
+          ea[sy][sx] = fabs(d1[px * L + sx]) * kap[sy * L + sx];
+          Ea[sy] += ea[sy][sx];
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < L; ++b) {
+        double z = 0.0, za = 0.0;
+#pragma unroll
+        for (int sx = 0; sx < L; ++sx) {
+          z = fma(e[sy][sx], xr[sx * NR + sy + b], z);
+          if (xm) za = fma(ea[sy][sx], xr[sx * NR + sy + b], za);
+        }
+        Z[sy][b] = z;
+        Za[sy][b] = za;
+        Zb[sy][b] = 0.0;
+        Zab[sy][b] = 0.0;
+      }
+    }
     const int npy = px < 2 ? M : M + 2;
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < npy; ++k) {
       int py, pt;
       if (px < 2) { py = 2 + k; pt = px * M + k; }
@@ -420,39 +456,93 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
         else if (k == 1) { py = 1; pt = 3 * M + h; }
         else { py = k; pt = 4 * M + (k - 2) * M + h; }
       }
+      const bool ym = weno_mixed_axis(K, M, py);
       const double lb = lam[(size_t)pt * 3 * cells];
-      double pv[S];
-      double ap = 0, dp = 0, am = 0, dm = 0;
+      // forward of the point
+      double T[L], Ta[L];
+      double B = 0.0, D = 0.0, A = 0.0, Cs = 0.0;
 #pragma unroll
-      for (int sy = 0; sy < L; ++sy)
+      for (int sy = 0; sy < L; ++sy) {
+        double t = 0.0, ta = 0.0;
 #pragma unroll
-        for (int sx = 0; sx < L; ++sx) {
-          double s = 0;
-#pragma unroll
-          for (int b = 0; b < L; ++b) s = fma(wsub[(sy * NA + py) * L + b], xr[sx * NR + sy + b], s);
-          const int jj = sy * L + sx;
-          pv[jj] = s;
-          ap = fma(gp[pt * S + jj] * kap[jj], s, ap);
-          dp = fma(gp[pt * S + jj], kap[jj], dp);
-          am = fma(gm[pt * S + jj] * kap[jj], s, am);
-          dm = fma(gm[pt * S + jj], kap[jj], dm);
+        for (int b = 0; b < L; ++b) {
+          t = fma(wsub[(sy * NA + py) * L + b], Z[sy][b], t);
+          if (xm) ta = fma(wsub[(sy * NA + py) * L + b], Za[sy][b], ta);
         }
-      const double sp = tab[C::O.sp + pt], sm = tab[C::O.sm + pt];
-      const double idp = rcp(dp), idm = rcp(dm);
-      const double apb = lb * sp * idp, dpb = -apb * ap * idp;
-      const double amb = -lb * sm * idm, dmb = -amb * am * idm;
-#pragma unroll
-      for (int sy = 0; sy < L; ++sy)
-#pragma unroll
-        for (int sx = 0; sx < L; ++sx) {
-          const int jj = sy * L + sx;
-          const double g1 = gp[pt * S + jj], g2 = gm[pt * S + jj];
-          kapb[jj] += apb * g1 * pv[jj] + dpb * g1 + amb * g2 * pv[jj] + dmb * g2;
-          const double pb = (apb * g1 + amb * g2) * kap[jj];
-#pragma unroll
-          for (int b = 0; b < L; ++b) xrb[sx * NR + sy + b] += pb * wsub[(sy * NA + py) * L + b];
+        T[sy] = t;
+        Ta[sy] = ta;
+        const double dy = d1[py * L + sy];
+        B = fma(dy, t, B);
+        D = fma(dy, E[sy], D);
+        if (xm) {
+          A = fma(fabs(dy), ta, A);
+          Cs = fma(fabs(dy), Ea[sy], Cs);
+        } else if (ym) {
+          A = fma(fabs(dy), t, A);
+          Cs = fma(fabs(dy), E[sy], Cs);
         }
+      }
+      // adjoint of the value: cotangents of B, D, A, C
+      double Bb, Db, Ab = 0.0, Cb = 0.0;
+      if (!xm && !ym) {
+        const double iD = rcp(D);
+        Bb = lb * iD;
+        Db = -Bb * B * iD;
+      } else {
+        const double N1 = fma(th, A, B), D1 = fma(th, Cs, D), N2 = fma(th, A, -B), D2 = fma(th, Cs, -D);
+        const double i1 = rcp(D1), i2 = rcp(D2);
+        const double sp = tab[C::O.sp + pt], sm = tab[C::O.sm + pt];
+        const double N1b = sp * lb * i1, D1b = -N1b * N1 * i1;
+        const double N2b = -sm * lb * i2, D2b = -N2b * N2 * i2;
+        Ab = th * (N1b + N2b);
+        Bb = N1b - N2b;
+        Cb = th * (D1b + D2b);
+        Db = D1b - D2b;
+      }
+      // back to the column sums
+#pragma unroll
+      for (int sy = 0; sy < L; ++sy) {
+        const double dy = d1[py * L + sy];
+        double Tb = dy * Bb;
+        Eb[sy] = fma(dy, Db, Eb[sy]);
+        if (xm) {
+          const double Tab = fabs(dy) * Ab;
+          Eab[sy] = fma(fabs(dy), Cb, Eab[sy]);
+#pragma unroll
+          for (int b = 0; b < L; ++b) Zab[sy][b] = fma(wsub[(sy * NA + py) * L + b], Tab, Zab[sy][b]);
+        } else if (ym) {
+          Tb = fma(fabs(dy), Ab, Tb);
+          Eb[sy] = fma(fabs(dy), Cb, Eb[sy]);
+        }
+#pragma unroll
+        for (int b = 0; b < L; ++b) Zb[sy][b] = fma(wsub[(sy * NA + py) * L + b], Tb, Zb[sy][b]);
+      }
     }
+    // column adjoint: to kappa (through e = d kappa) and to the x-pass
+    double xrb[L * NR];
+#pragma unroll
+    for (int o = 0; o < L * NR; ++o) xrb[o] = 0.0;
+#pragma unroll
+    for (int sy = 0; sy < L; ++sy)
+#pragma unroll
+      for (int sx = 0; sx < L; ++sx) {
+        double eb = Eb[sy];
+#pragma unroll
+        for (int b = 0; b < L; ++b) {
+          eb = fma(Zb[sy][b], xr[sx * NR + sy + b], eb);
+          xrb[sx * NR + sy + b] = fma(e[sy][sx], Zb[sy][b], xrb[sx * NR + sy + b]);
+        }
+        kapb[sy * L + sx] = fma(d1[px * L + sx], eb, kapb[sy * L + sx]);
+        if (xm) {
+          double eab = Eab[sy];
+#pragma unroll
+          for (int b = 0; b < L; ++b) {
+            eab = fma(Zab[sy][b], xr[sx * NR + sy + b], eab);
+            xrb[sx * NR + sy + b] = fma(ea[sy][sx], Zab[sy][b], xrb[sx * NR + sy + b]);
+          }
+          kapb[sy * L + sx] = fma(fabs(d1[px * L + sx]), eab, kapb[sy * L + sx]);
+        }
+      }
     // x-pass adjoint
 #pragma unroll
     for (int sx = 0; sx < L; ++sx)
@@ -460,7 +550,7 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
       for (int row = 0; row < NR; ++row)
 #pragma unroll
         for (int a = 0; a < L; ++a)
-          dq[row * K + (sx + a)] += wsub[(sx * NA + px) * L + a] * xrb[sx * NR + row];
+          dq[row * K + (sx + a)] = fma(wsub[(sx * NA + px) * L + a], xrb[sx * NR + row], dq[row * K + (sx + a)]);
   }
   // kappa_j = 1 + tau/(beta_j + eps)
   double taub = 0, betab[S];
