@@ -6,7 +6,7 @@
 //  k_fill_halo_batch      ghost fill g = G q (appendix (7.12)) of all members:
 //                         one 16-lane group per ghost row of a grid, applied to
 //                         that grid's members while the row's entries sit in
-//                         registers (G is read once per kHaloChunk members)
+//                         registers (G is read once per kHaloChunk = 16 members)
 //  k_edge_traces_batch    panel-edge traces (3.26)-(3.29) of all members; each
 //                         member's range is padded to whole wavefronts
 //  k_stage_batch          the fused stage over a flattened list of work items

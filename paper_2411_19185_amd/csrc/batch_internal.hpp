@@ -53,6 +53,9 @@ int launch_batch_stage(int k, int weno, const BatchMember* members, const int32_
                        const BatchStage& st, void* stream);
 
 // members per ghost-fill pass (the accumulators of one pass live in registers)
-constexpr int kHaloChunk = 8;
+#ifndef HOPE_HALO_CHUNK
+#define HOPE_HALO_CHUNK 16
+#endif
+constexpr int kHaloChunk = HOPE_HALO_CHUNK;
 
 }  // namespace hope
