@@ -129,9 +129,21 @@ __global__ __launch_bounds__(64) void k_vjp_traces(const double* __restrict__ ta
   const double* c0 = q + (size_t)p * P * P + (size_t)(j + C::R) * P + (i + C::R);
   const size_t cells = (size_t)6 * n * n;
   double* out = T + c;
+  // the lane's stencil of one variable, staged in LDS: all its loads are
+  // issued together instead of one by one inside the arithmetic
+  constexpr bool kStage = K * K * 64 * 8 <= 32768;
+  __shared__ double st[kStage ? K * K : 1][64];
+  const int lane = threadIdx.x;
 #pragma unroll 1
   for (int v = 0; v < 3; ++v) {
-    auto at = [&](int dy, int dx) -> double { return c0[v * vs + dy * P + dx]; };
+    if constexpr (kStage) {
+#pragma unroll
+      for (int o = 0; o < K * K; ++o) st[o][lane] = c0[v * vs + (o / K - C::R) * P + (o % K - C::R)];
+    }
+    auto at = [&](int dy, int dx) -> double {
+      if constexpr (kStage) return st[(dy + C::R) * K + dx + C::R][lane];
+      else return c0[v * vs + dy * P + dx];
+    };
     double kap[W ? C::S : 1];
     if constexpr (W) weno_kappa<K, W, M>(tab, gs.eps, at, [&](int jj, double x) { kap[jj] = x; });
     auto kf = [&](int jj) -> double { return kap[jj]; };
@@ -230,7 +242,7 @@ __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ ta
     }
     const int dir = sd < 2 ? 0 : 1;
     const int e = sd == 0 ? i : sd == 1 ? i + 1 : sd == 2 ? j : j + 1;
-#pragma unroll 1
+#pragma unroll
     for (int h = 0; h < M; ++h) {
       double qo[3], qn[3];
 #pragma unroll
@@ -256,9 +268,9 @@ __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ ta
   }
   // sources at the cell Gauss points
   cdp fc = tab + C::O.fcoef + p * 3;
-#pragma unroll 1
+#pragma unroll
   for (int vv = 0; vv < M; ++vv)
-#pragma unroll 1
+#pragma unroll
     for (int h = 0; h < M; ++h) {
       const int pt = 4 * M + vv * M + h;
       const double X = Xg[i * M + h], Y = Xg[j * M + vv];
@@ -346,8 +358,18 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
   const int p = c / (n * n), j = (c / n) % n, i = c % n;
   const size_t vs = (size_t)6 * P * P;
   const double* c0 = q + v * vs + (size_t)p * P * P + (size_t)(j + R) * P + (i + R);
-  auto at = [&](int dy, int dx) -> double { return c0[dy * P + dx]; };
-  const double* lam = Lam + (size_t)v * cells + c;     // point pt at lam[pt * 3 * cells]
+  // the lane's stencil, staged in LDS (see k_vjp_traces)
+  __shared__ double st[K * K][64];
+  __shared__ double sl[NP][64];
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int o = 0; o < K * K; ++o) st[o][lane] = c0[(o / K - R) * P + (o % K - R)];
+  auto at = [&](int dy, int dx) -> double { return st[(dy + R) * K + dx + R][lane]; };
+  {
+    const double* lam = Lam + (size_t)v * cells + c;     // point pt at lam[pt * 3 * cells]
+#pragma unroll
+    for (int pt = 0; pt < NP; ++pt) sl[pt][lane] = lam[(size_t)pt * 3 * cells];
+  }
   cdp V = tab + C::O.V, lamq = tab + C::O.lam, wsub = tab + C::O.wsub;
   double dq[K * K];
 #pragma unroll
@@ -457,7 +479,7 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
         else { py = k; pt = 4 * M + (k - 2) * M + h; }
       }
       const bool ym = weno_mixed_axis(K, M, py);
-      const double lb = lam[(size_t)pt * 3 * cells];
+      const double lb = sl[pt][lane];
       // forward of the point
       double T[L], Ta[L];
       double B = 0.0, D = 0.0, A = 0.0, Cs = 0.0;
