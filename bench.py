@@ -413,7 +413,7 @@ def adjoint(g, n, args, dt):
     g.profile(False)
     pair_ms = ev[0].elapsed_time(ev[1]) / reps
     kern = {}
-    for k in ("vjp_traces", "vjp_points", "vjp_edges", "vjp_weno", "vjp_beta", "vjp_gather", "vjp_ghost_t"):
+    for k in ("vjp_traces", "vjp_points", "vjp_edges", "vjp_weno", "vjp_gather", "vjp_ghost_t"):
         ms, cnt = g.profile_read(k)
         if cnt:
             kern[k] = ms / cnt

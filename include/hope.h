@@ -130,8 +130,8 @@ int hope_tendency(const hope_grid* grid, double* q, double* dqdt, void* stream);
  * ghost-cell cotangents folded back through G^T.  q's ghost rings are scratch.
  * Non-smooth points (|m|, |beta_i - beta_j|) take the subgradient sign(0)=0.
  * ws: caller-owned device workspace of at least layout.vjp_workspace_bytes
- * (8 * (2*3*(4m+m^2) + 3*order^2 + [WENO] 3*((order+1)/2)^2) bytes per cell
- * plus one padded state); gq must not alias w. */
+ * (8 * (2*3*(4m+m^2) + 3*order^2) bytes per cell plus one padded state); gq
+ * must not alias w. */
 int hope_tendency_vjp(const hope_grid* grid, double* q, const double* w, double* gq, double* ws,
                       size_t ws_bytes, void* stream);
 
@@ -167,9 +167,7 @@ int hope_grid_get_launch(const hope_grid* grid, int32_t* strip_w, int32_t* seg_h
  * recorded events and returns the summed elapsed time and launch count of one
  * kernel: 0 ghost fill, 1 panel-edge traces, 2 fused stage, and the kernels
  * of the adjoint: 3 point values, 4 flux and source adjoints, 5 panel-edge
- * adjoints, 6 reconstruction adjoint (WENO: through the point values and
- * weights; TPP: all of it), 7 WENO smoothness-indicator adjoint, 8 gather to
- * the padded cells, 9 G^T fold. */
+ * adjoints, 6 WENO adjoint, 7 gather to the padded cells, 8 G^T fold. */
 int hope_grid_profile(hope_grid* grid, int32_t enable);
 int hope_grid_profile_read(hope_grid* grid, int32_t kernel, double* total_ms, int64_t* launches);
 

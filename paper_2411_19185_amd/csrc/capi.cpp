@@ -303,16 +303,13 @@ void hope_grid_destroy(hope_grid* grid) {
 }
 
 // adjoint scratch: point values T, their cotangents, WENO stencil cotangents, padded cotangent
-static size_t vjp_elems(const HostTables& h, size_t* nT, size_t* nD, size_t* nG, size_t* nK = nullptr) {
+static size_t vjp_elems(const HostTables& h, size_t* nT, size_t* nD, size_t* nG) {
   const size_t cells = 6ULL * h.n * h.n;
   const size_t np = 4 * h.m + h.m * h.m;
   *nT = cells * np * 3;
   *nD = cells * h.k * h.k * 3;
   *nG = 18ULL * h.P * h.P;
-  const size_t l = (h.k + 1) / 2;
-  const size_t k = h.weno ? cells * l * l * 3 : 0;
-  if (nK) *nK = k;
-  return 2 * *nT + *nD + *nG + k;
+  return 2 * *nT + *nD + *nG;
 }
 
 int hope_grid_layout(const hope_grid* G, hope_layout* out) {
@@ -402,7 +399,6 @@ int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq
   a.Lam = ws + nT;
   a.Dl = ws + 2 * nT;
   a.gpad = ws + 2 * nT + nD;
-  a.Kb = ws + 2 * nT + nD + nG;
   a.gt_rows = G->gt_rows;
   a.gt_cell = G->gt_cell;
   a.gt_ptr = G->gt_ptr;

@@ -15,7 +15,6 @@
 //                   (3.26)-(3.29)
 //   k_vjp_weno      WENO: cotangents of the stencil cell values through the
 //                   nonlinear weights, tau, beta and the sub-stencil values
-//   k_vjp_beta      WENO: the smoothness-indicator part of that adjoint
 //   k_vjp_tpp       TPP: the same for the linear reconstruction (separable)
 //   k_vjp_gather    cotangent of every padded cell (interior and ghost)
 //   k_vjp_interior  the interior cotangent
@@ -347,7 +346,7 @@ __global__ __launch_bounds__(64) void k_vjp_edges(const double* __restrict__ tab
 template <int K, bool W, int M>
 __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_, GridScalars gs,
                                                   const double* __restrict__ q, const double* __restrict__ Lam,
-                                                  double* __restrict__ Dl, double* __restrict__ Kb) {
+                                                  double* __restrict__ Dl) {
   using C = Cfg<K, W, M>;
   constexpr int NP = 4 * M + M * M, R = C::R, L = C::L, S = C::S, NR = C::NR, NA = C::NA;
   const cdp tab = (cdp)tab_;
@@ -575,84 +574,6 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
         for (int a = 0; a < L; ++a)
           dq[row * K + (sx + a)] = fma(wsub[(sx * NA + px) * L + a], xrb[sx * NR + row], dq[row * K + (sx + a)]);
   }
-  // the cotangents of kappa go to the smoothness-indicator adjoint (k_vjp_beta)
-#pragma unroll
-  for (int jj = 0; jj < S; ++jj) Kb[((size_t)jj * 3 + v) * cells + c] = kapb[jj];
-  double* out = Dl + (size_t)v * cells + c;
-#pragma unroll
-  for (int o = 0; o < K * K; ++o) out[(size_t)o * 3 * cells] = dq[o];
-}
-
-// ---------------------------------------------------------------------------
-// k_vjp_beta: WENO smoothness-indicator adjoint.  From the cotangents of
-// kappa_j = 1 + tau/(beta_j + eps) (k_vjp_weno), through tau and the
-// indicators beta_j = sum lam c^2, c = (V_sy x V_sx) q, into the stencil
-// cotangents Dl (added to what k_vjp_weno wrote)
-// ---------------------------------------------------------------------------
-template <int K, bool W, int M>
-__global__ __launch_bounds__(64) void k_vjp_beta(const double* __restrict__ tab_, GridScalars gs,
-                                                  const double* __restrict__ q, const double* __restrict__ Kb,
-                                                  double* __restrict__ Dl) {
-  using C = Cfg<K, W, M>;
-  constexpr int R = C::R, L = C::L, S = C::S, NR = C::NR;
-  const cdp tab = (cdp)tab_;
-  const int n = gs.n, P = gs.P;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 18 * n * n) return;
-  const int cells = 6 * n * n;
-  const int v = idx / cells, c = idx % cells;
-  const int p = c / (n * n), j = (c / n) % n, i = c % n;
-  const size_t vs = (size_t)6 * P * P;
-  const double* c0 = q + v * vs + (size_t)p * P * P + (size_t)(j + R) * P + (i + R);
-  __shared__ double st[K * K][64];
-  const int lane = threadIdx.x;
-#pragma unroll
-  for (int o = 0; o < K * K; ++o) st[o][lane] = c0[(o / K - R) * P + (o % K - R)];
-  auto at = [&](int dy, int dx) -> double { return st[(dy + R) * K + dx + R][lane]; };
-  cdp V = tab + C::O.V, lamq = tab + C::O.lam;
-  double kapb[S];
-#pragma unroll
-  for (int jj = 0; jj < S; ++jj) kapb[jj] = Kb[((size_t)jj * 3 + v) * cells + c];
-  double dq[K * K];
-#pragma unroll
-  for (int o = 0; o < K * K; ++o) dq[o] = 0.0;
-  // forward smoothness indicators and tau
-  double beta[S];
-#pragma unroll
-  for (int sx = 0; sx < L; ++sx) {
-    double tr[NR][L];
-#pragma unroll
-    for (int row = 0; row < NR; ++row)
-#pragma unroll
-      for (int al = 0; al < L; ++al) {
-        double s = 0;
-#pragma unroll
-        for (int a = 0; a < L; ++a) s = fma(V[(sx * L + al) * L + a], at(row - R, sx - (L - 1) + a), s);
-        tr[row][al] = s;
-      }
-#pragma unroll
-    for (int sy = 0; sy < L; ++sy) {
-      double b = 0;
-#pragma unroll
-      for (int be = 0; be < L; ++be)
-#pragma unroll
-        for (int al = 0; al < L; ++al) {
-          if (al == 0 && be == 0) continue;
-          double cc = 0;
-#pragma unroll
-          for (int bb = 0; bb < L; ++bb) cc = fma(V[(sy * L + be) * L + bb], tr[sy + bb][al], cc);
-          b = fma(lamq[be * L + al] * cc, cc, b);
-        }
-      beta[sy * L + sx] = b;
-    }
-  }
-  double tau = 0;
-#pragma unroll
-  for (int a = 0; a < S; ++a)
-#pragma unroll
-    for (int b = a + 1; b < S; ++b) tau += fabs(beta[a] - beta[b]);
-  const double ctau = 2.0 / (S * (S + 1));
-  tau *= ctau;
   // kappa_j = 1 + tau/(beta_j + eps)
   double taub = 0, betab[S];
 #pragma unroll
@@ -709,7 +630,7 @@ __global__ __launch_bounds__(64) void k_vjp_beta(const double* __restrict__ tab_
   }
   double* out = Dl + (size_t)v * cells + c;
 #pragma unroll
-  for (int o = 0; o < K * K; ++o) out[(size_t)o * 3 * cells] += dq[o];
+  for (int o = 0; o < K * K; ++o) out[(size_t)o * 3 * cells] = dq[o];
 }
 
 // ---------------------------------------------------------------------------
@@ -872,14 +793,9 @@ static int vjp_t(const VjpArgs& a, int step, void* stream) {
     case kVjpWeno:
       if constexpr (W)
         hipLaunchKernelGGL((k_vjp_weno<K, W, M>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q, a.Lam,
-                           a.Dl, a.Kb);
+                           a.Dl);
       else
         hipLaunchKernelGGL((k_vjp_tpp<K, W, M>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.Lam,
-                           a.Dl);
-      break;
-    case kVjpBeta:
-      if constexpr (W)
-        hipLaunchKernelGGL((k_vjp_beta<K, W, M>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q, a.Kb,
                            a.Dl);
       break;
     case kVjpGather: {

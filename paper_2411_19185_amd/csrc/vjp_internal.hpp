@@ -15,8 +15,7 @@ struct VjpArgs {
   double* gq;
   double* T;       // point values of every cell, [NP][3][6n^2]
   double* Lam;     // their cotangents, same layout
-  double* Dl;      // stencil cotangents, [K^2][3][6n^2]
-  double* Kb;      // WENO: cotangents of the weights kappa, [l^2][3][6n^2]
+  double* Dl;      // WENO: stencil cotangents, [K^2][3][6n^2]
   double* gpad;    // padded cotangent, 3 x 6 x P x P
   // G^T by the interior cells that some ghost row reads (gt_rows of them)
   int32_t gt_rows;
@@ -27,7 +26,7 @@ struct VjpArgs {
   int64_t gt_nnz;
 };
 // the adjoint's kernels in launch order
-enum { kVjpTraces = 0, kVjpPoints, kVjpEdges, kVjpWeno, kVjpBeta, kVjpGather, kVjpGhostT, kVjpSteps };
+enum { kVjpTraces = 0, kVjpPoints, kVjpEdges, kVjpWeno, kVjpGather, kVjpGhostT, kVjpSteps };
 int launch_vjp(int k, int weno, const VjpArgs& a, int step, void* stream);
 
 }  // namespace hope

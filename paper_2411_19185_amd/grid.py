@@ -147,7 +147,7 @@ class Grid:
 
     # ------------------------------------------------------------------
     KERNELS = {"fill_halo": 0, "edge_traces": 1, "stage": 2, "vjp_traces": 3, "vjp_points": 4, "vjp_edges": 5,
-               "vjp_weno": 6, "vjp_beta": 7, "vjp_gather": 8, "vjp_ghost_t": 9}
+               "vjp_weno": 6, "vjp_gather": 7, "vjp_ghost_t": 8}
 
     def profile(self, enable: bool):
         check(lib().hope_grid_profile(self._h, 1 if enable else 0))
