@@ -18,7 +18,7 @@ import statistics
 
 import torch
 
-SEG_CANDIDATES = (2, 3, 4, 6, 8, 12, 16, 24, 32)
+SEG_CANDIDATES = (2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 14, 16, 20, 24, 32)
 
 
 def _cache_path(cache: str | None) -> str:

@@ -94,9 +94,11 @@ static void default_launch(hope_grid* G) {
   int sw, strips;
   balanced_strip(n, &sw, &strips);
   G->strip_w = sw;
-  // enough wavefronts to cover the chip a few times over
-  int h = 8;
-  while (h > 2 && 6L * strips * ((n + h - 1) / h) < 2048) --h;
+  // the tallest segments (fewest re-reconstructed boundary rows) that still
+  // give about 1.4 work items per workgroup slot of the chip (256 CUs x 4
+  // resident workgroups of the order-5 stage)
+  int h = 12;
+  while (h > 2 && 6L * strips * ((n + h - 1) / h) < 1400) --h;
   G->seg_h = h;
 }
 

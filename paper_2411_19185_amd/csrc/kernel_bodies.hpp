@@ -127,13 +127,14 @@ constexpr int kStageThreads = 192;
 
 template <int K, bool W, int M>
 struct StageSmem {
-  static constexpr int R = (K - 1) / 2, NR = 2 * R + 1, CW = 64 + 2 * R, NP = 4 * M + M * M;
+  static constexpr int R = (K - 1) / 2, NR = 2 * R + 1, CW = 64 + 2 * R;
+  // slots of pts: left edge, right edge, bottom edge (M each), then the M x M
+  // cell nodes; a row's top traces stay in the registers of the wavefront
+  // that computed them until they move to ptop
+  static constexpr int PL = 0, PR = M, PB = 2 * M, PI = 3 * M, NP = 3 * M + M * M;
   double sq[3][NR][CW];     // stencil window: NR padded rows (LDS column c = padded column i0-1+c)
-  double pts[3][NP][64];    // the current row's values at every point of every lane's cell
+  double pts[3][NP][64];    // the current row's values at the points of every lane's cell
   double ptop[3][M][64];    // top traces of the row below
-  double fx[3][64];         // Gauss-quadrature flux through each lane's left edge
-  double fy[3][64];         // ... through each lane's bottom edge
-  double src[2][64];        // momentum sources (cell quadrature)
 };
 
 // one work item (panel, strip, segment) of the fused stage; fcb = the 6 x 3
@@ -207,10 +208,19 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     if constexpr (W) weno_kappa<K, W, M>(tab, gs.eps, win(pc), [&](int j, double x) { kap[j] = x; });
   };
   auto pt = [&](int v, int k) -> double& { return sm.pts[v][k][lane]; };
+  using SM = StageSmem<K, W, M>;
+  // results of the flux phase, each written over a point slot that only its
+  // writer read: the x flux through lane L's left edge over the left trace
+  // (wavefront 0), the y flux over the bottom trace (wavefront 1) and the two
+  // momentum sources over the first cell node of variables 0 and 1
+  // (wavefront 2)
+  auto fx = [&](int v, int l) -> double& { return sm.pts[v][SM::PL][l]; };
+  auto fy = [&](int v) -> double& { return sm.pts[v][SM::PB][lane]; };
+  auto src = [&](int c) -> double& { return sm.pts[c][SM::PI][lane]; };
 
   // ---- reconstruction phase: wavefront wv, variable wv ----------------------
   // every point of row pc
-  auto recon_row = [&](int pc) {
+  auto recon_row = [&](int pc, double* top) {
     double kap[W ? S : 1];
     kappa(pc, kap);
     auto kf = [&](int j) -> double { return kap[j]; };
@@ -232,11 +242,11 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
         asm volatile("" ::: "memory");
         xpass<K, W, M>(tab, 2 + h, win(pc), xr);
         wcol<K, W, M>(tab, 2 + h, xr, kf, col);
-        pt(wv, 2 * M + h) = wpoint<K, W, M>(tab, 2 + h, 0, 2 * M + h, col);
-        pt(wv, 3 * M + h) = wpoint<K, W, M>(tab, 2 + h, 1, 3 * M + h, col);
+        pt(wv, SM::PB + h) = wpoint<K, W, M>(tab, 2 + h, 0, 2 * M + h, col);
+        top[h] = wpoint<K, W, M>(tab, 2 + h, 1, 3 * M + h, col);
 #pragma unroll
         for (int w = 0; w < M; ++w)
-          pt(wv, 4 * M + w * M + h) = wpoint<K, W, M>(tab, 2 + h, 2 + w, 4 * M + w * M + h, col);
+          pt(wv, SM::PI + w * M + h) = wpoint<K, W, M>(tab, 2 + h, 2 + w, 4 * M + w * M + h, col);
       }
     } else {
       asm volatile("" ::: "memory");
@@ -251,11 +261,11 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       for (int h = 0; h < M; ++h) {
         asm volatile("" ::: "memory");
         xpass<K, W, M>(tab, 2 + h, win(pc), xr);
-        pt(wv, 2 * M + h) = point<K, W, M>(tab, 0, 2 * M + h, xr, kf);
-        pt(wv, 3 * M + h) = point<K, W, M>(tab, 1, 3 * M + h, xr, kf);
+        pt(wv, SM::PB + h) = point<K, W, M>(tab, 0, 2 * M + h, xr, kf);
+        top[h] = point<K, W, M>(tab, 1, 3 * M + h, xr, kf);
 #pragma unroll
         for (int w = 0; w < M; ++w)
-          pt(wv, 4 * M + w * M + h) = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+          pt(wv, SM::PI + w * M + h) = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
       }
     }
   };
@@ -293,7 +303,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       for (int v = 0; v < 3; ++v) {
         const double dflt = v == 0 ? 1.0 : 0.0;
         qL[v] = real ? sm.ptop[v][h][lane] : dflt;
-        qR[v] = real ? pt(v, 2 * M + h) : dflt;
+        qR[v] = real ? pt(v, SM::PB + h) : dflt;
       }
       double F[3];
       lmars(qL, qR, Xg[ic * M + h], Xe[j], sqg[ic * M + h], sqe[j], 1, ia, F);
@@ -301,7 +311,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       for (int v = 0; v < 3; ++v) gb[v] = fma(gw[h], F[v], gb[v]);
     }
 #pragma unroll
-    for (int v = 0; v < 3; ++v) sm.fy[v][lane] = gb[v];
+    for (int v = 0; v < 3; ++v) fy(v) = gb[v];
   };
   // wavefront 0: flux through the left edge of each lane's column in row j;
   // panel edges take the neighbour's converted trace
@@ -316,13 +326,12 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       double qL[3], qR[3];
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
-        const double bl = btp[(((size_t)0 * n + j) * M + h) * 3 + v];
-        const double br = btp[(((size_t)1 * n + j) * M + h) * 3 + v];
         const double dflt = v == 0 ? 1.0 : 0.0;
-        const double l = sm.pts[v][M + h][ll];
-        const double r = pt(v, h);
-        qL[v] = xdead ? dflt : (i == 0 ? bl : l);
-        qR[v] = xdead ? dflt : (i == n ? br : r);
+        const double l = sm.pts[v][SM::PR + h][ll];
+        const double r = pt(v, SM::PL + h);
+        // only the lanes on a panel edge read the neighbour's trace
+        qL[v] = xdead ? dflt : (i == 0 ? btp[(((size_t)0 * n + j) * M + h) * 3 + v] : l);
+        qR[v] = xdead ? dflt : (i == n ? btp[(((size_t)1 * n + j) * M + h) * 3 + v] : r);
       }
       double F[3];
       lmars(qL, qR, Xei, Xg[j * M + h], sqxe, sqg[j * M + h], 0, ia, F);
@@ -330,7 +339,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       for (int v = 0; v < 3; ++v) fl[v] = fma(gw[h], F[v], fl[v]);
     }
 #pragma unroll
-    for (int v = 0; v < 3; ++v) sm.fx[v][lane] = fl[v];
+    for (int v = 0; v < 3; ++v) fx(v, lane) = fl[v];
   };
   // wavefront 2: metric and Coriolis sources of row j (cell quadrature)
   auto sources_row = [&](int j) {
@@ -344,7 +353,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       for (int w = 0; w < M; ++w) {
         double cq[3];
 #pragma unroll
-        for (int v = 0; v < 3; ++v) cq[v] = real ? pt(v, 4 * M + w * M + h) : (v == 0 ? 1.0 : 0.0);
+        for (int v = 0; v < 3; ++v) cq[v] = real ? pt(v, SM::PI + w * M + h) : (v == 0 ? 1.0 : 0.0);
         const double Y = Xg[j * M + w];
         double a1, a2;
         sources(cq[0], cq[1], cq[2], X, Y, Lx0 + LxX * X + LxY * Y, gs.omega2, a1, a2);
@@ -353,8 +362,8 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
         s2 = fma(g2, a2, s2);
       }
     }
-    sm.src[0][lane] = s1;
-    sm.src[1][lane] = s2;
+    src(0) = s1;
+    src(1) = s2;
   };
 
   // ---- prologue: window and the top traces of row j0-1 ------------------
@@ -373,27 +382,39 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     recon_side(j0 - 1, 1, [&](int h) -> double& { return sm.ptop[wv][h][lane]; });
   }
   double acc = 0.0;                // this wavefront's variable: partial tendency of the previous row
+  double top[M];                   // this wavefront's variable: top traces of the current row
 
   for (int j = j0; j <= j1; ++j) {
     const bool last = (j == j1);
     // the window of step j holds padded rows j .. j+2R; row j+2R was fetched
     // during the previous step and replaces row j-1, no longer read
     const bool have = !(last && j1 == n) && (j + 2 * R) < P;
-    __syncthreads();
+    // the slot of row j+2R held padded row j-1, last read by the previous
+    // step's reconstruction (behind its flux barriers) or, in the first step,
+    // by the prologue's top traces
+    if (j == j0) __syncthreads();
     if (have) store(j + 2 * R, nxt);
     __syncthreads();
     const bool want = (j + 1 < j1 || (j + 1 == j1 && j1 < n)) && (j + 2 * R + 1) < P;
     if (want) fetch(j + 2 * R + 1, nxt);
     if (!last) {
-      recon_row(j);
+      recon_row(j, top);
     } else if (j1 == n) {
       // bottom traces of the panel's top row: the neighbour's converted trace
 #pragma unroll
-      for (int h = 0; h < M; ++h) pt(wv, 2 * M + h) = real ? btp[(((size_t)3 * n + ic) * M + h) * 3 + wv] : 0.0;
+      for (int h = 0; h < M; ++h) pt(wv, SM::PB + h) = real ? btp[(((size_t)3 * n + ic) * M + h) * 3 + wv] : 0.0;
     } else {
-      recon_side(j, 0, [&](int h) -> double& { return pt(wv, 2 * M + h); });
+      recon_side(j, 0, [&](int h) -> double& { return pt(wv, SM::PB + h); });
     }
     __syncthreads();
+    // the cell finished below: q^n is requested before the flux phase so that
+    // its latency is hidden behind it; q_s is padded row jr+R of the window,
+    // read before the next step's store may replace that row
+    const bool fin = j > j0 && owner;
+    const int jr = j - 1;
+    const size_t o_in = wv * vs + p * plane + (size_t)(jr + R) * P + (i + R);
+    const double qn_c = (fin && A.qn) ? A.qn[o_in] : 0.0;
+    const double qs_c = fin ? sm.sq[wv][(jr + R) % NR][lane + R] : 0.0;
     if (wv == 1) yflux(j);
     if (!last) {
       if (wv == 0) xflux(j);
@@ -401,15 +422,13 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     }
     __syncthreads();
     // ---- assembly: wavefront wv, variable wv -----------------------------
-    const double gb = sm.fy[wv][lane];
-    if (j > j0 && owner) {
+    const double gb = fy(wv);
+    if (fin) {
       // finish row j-1: its top flux is row j's bottom flux
-      const int jr = j - 1;
-      const size_t o_in = wv * vs + p * plane + (size_t)(jr + R) * P + (i + R);
       const double dq = fma(-gb, invd, acc);
       double val = A.cc * dq;
-      if (A.cb != 0.0) val = fma(A.cb, A.q[o_in], val);
-      if (A.qn) val = fma(A.ca, A.qn[o_in], val);
+      if (A.cb != 0.0) val = fma(A.cb, qs_c, val);
+      if (A.qn) val = fma(A.ca, qn_c, val);
       if (A.out_padded) {
         A.out[o_in] = val;
       } else {
@@ -417,11 +436,11 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       }
     }
     if (last) break;
-    const double fl = sm.fx[wv][lane];
-    const double fr = sm.fx[wv][min(lane + 1, 63)];
-    acc = wv == 0 ? (fl - fr + gb) * invd : fma(fl - fr + gb, invd, sm.src[wv - 1][lane]);
+    const double fl = fx(wv, lane);
+    const double fr = fx(wv, min(lane + 1, 63));
+    acc = wv == 0 ? (fl - fr + gb) * invd : fma(fl - fr + gb, invd, src(wv - 1));
 #pragma unroll
-    for (int h = 0; h < M; ++h) sm.ptop[wv][h][lane] = pt(wv, 3 * M + h);
+    for (int h = 0; h < M; ++h) sm.ptop[wv][h][lane] = top[h];
   }
 }
 
