@@ -9,14 +9,16 @@
 //              quadrature (3.5)-(3.6) with sources (2.2)-(2.3), the tendency
 //              (3.1) and an optional Runge-Kutta combination
 //
-// stage_tile marches: one wavefront owns a strip of up to 62 interior columns
-// of one panel (lanes 1..62; lanes 0 and 63 are the strip's ring columns) and
-// a segment of rows, walking up the rows.  The 2r+1 stencil rows of the strip
-// sit in an LDS ring buffer (one new row per step, fetched a step ahead).  At
-// each row every lane reconstructs its cell; the flux through the left edge
-// of lane L takes the left state from lane L-1 by a cross-lane shuffle, and
-// the flux through the bottom edge takes the top trace of the row below, kept
-// from the previous step.  No trace goes to HBM.
+// stage_tile marches: a workgroup of three wavefronts owns a strip of up to 62
+// interior columns of one panel (lanes 1..62; lanes 0 and 63 are the strip's
+// ring columns) and a segment of rows, walking up the rows.  The 2r+1 stencil
+// rows of the strip sit in an LDS ring buffer (one new row per step, fetched
+// a step ahead).  At each row wavefront v reconstructs variable v of every
+// lane's cell into LDS; then wavefront 0 evaluates the flux through each
+// lane's left edge (left state: lane L-1's right trace), wavefront 1 the flux
+// through the bottom edge (left state: the top traces of the row below,
+// carried from the previous step) and wavefront 2 the sources.  No trace goes
+// to HBM.
 //
 // The grid's constant tables are one buffer read through the constant address
 // space: with uniform addresses those reads are scalar loads into SGPRs.
