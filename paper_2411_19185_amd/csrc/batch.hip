@@ -4,7 +4,7 @@
 // is bitwise the one its own grid gives.
 //
 //  k_fill_halo_batch      ghost fill g = G q (appendix (7.12)) of all members:
-//                         one 16-lane group per ghost row of a grid, applied to
+//                         one lane group per ghost row of a grid, applied to
 //                         that grid's members while the row's entries sit in
 //                         registers (G is read once per kHaloChunk = 16 members)
 //  k_edge_traces_batch    panel-edge traces (3.26)-(3.29) of all members; each
@@ -23,17 +23,19 @@ __global__ __launch_bounds__(256) void k_fill_halo_batch(const BatchGrid* __rest
                                                          int total_rows, const int32_t* __restrict__ mlist,
                                                          const BatchMember* __restrict__ mem,
                                                          double* __restrict__ base) {
-  const int row = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 4);
-  if (row >= total_rows) return;   // whole 16-lane group leaves together
+  const int row = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kHaloLanes);
+  if (row >= total_rows) return;   // the whole lane group leaves together
   int gi = 0;
   while (gi + 1 < n_grids && grids[gi + 1].row_begin <= row) ++gi;
   const BatchGrid& bg = grids[gi];
   const GhostDev& g = bg.g;
   const int r = row - bg.row_begin;
-  const int lane = threadIdx.x & 15;
+  const int lane = threadIdx.x % kHaloLanes;
   const size_t plane = (size_t)6 * bg.P * bg.P;
   const int b = g.ptr[r], e = g.ptr[r + 1];
   const int d = g.dst[r];
+  const int info = g.info[r];
+  const double* cv = g.cval + (info & 0x0fffffff);
   for (int c0 = 0; c0 < bg.member_count; c0 += kHaloChunk) {
     const int cnt = min(kHaloChunk, bg.member_count - c0);
     double* qm[kHaloChunk];
@@ -42,34 +44,40 @@ __global__ __launch_bounds__(256) void k_fill_halo_batch(const BatchGrid* __rest
     double acc[kHaloChunk][3];
 #pragma unroll
     for (int t = 0; t < kHaloChunk; ++t) acc[t][0] = acc[t][1] = acc[t][2] = 0.0;
-    for (int k = b + lane; k < e; k += 16) {
+    for (int k = b + lane; k < e; k += kHaloLanes) {
       const int c = g.col[k];
-      const double v0 = g.val[k], v1 = g.val[g.nnz + k], v2 = g.val[2 * g.nnz + k];
-      const double v3 = g.val[3 * g.nnz + k], v4 = g.val[4 * g.nnz + k];
+      const int ce = g.ce[k];
+      const int j = ce & 0x1fff, f = ce >> 13;
+      const double v0 = cv[j];
+      double w1, w2, w3, w4;   // the block rows acting on the cell's own frame
+      frame_apply(f, cv[g.cnnz + j], cv[2 * g.cnnz + j], w1, w2);
+      frame_apply(f, cv[3 * g.cnnz + j], cv[4 * g.cnnz + j], w3, w4);
 #pragma unroll
       for (int t = 0; t < kHaloChunk; ++t) {
         if (t < cnt) {
           const double* q = qm[t];
           const double a0 = q[c], a1 = q[plane + c], a2 = q[2 * plane + c];
           acc[t][0] = fma(v0, a0, acc[t][0]);
-          acc[t][1] = fma(v1, a1, fma(v2, a2, acc[t][1]));
-          acc[t][2] = fma(v3, a1, fma(v4, a2, acc[t][2]));
+          acc[t][1] = fma(w1, a1, fma(w2, a2, acc[t][1]));
+          acc[t][2] = fma(w3, a1, fma(w4, a2, acc[t][2]));
         }
       }
     }
 #pragma unroll
     for (int t = 0; t < kHaloChunk; ++t) {
 #pragma unroll
-      for (int off = 8; off > 0; off >>= 1) {
-        acc[t][0] += __shfl_xor(acc[t][0], off, 16);
-        acc[t][1] += __shfl_xor(acc[t][1], off, 16);
-        acc[t][2] += __shfl_xor(acc[t][2], off, 16);
+      for (int off = kHaloLanes / 2; off > 0; off >>= 1) {
+        acc[t][0] += __shfl_xor(acc[t][0], off, kHaloLanes);
+        acc[t][1] += __shfl_xor(acc[t][1], off, kHaloLanes);
+        acc[t][2] += __shfl_xor(acc[t][2], off, kHaloLanes);
       }
       if (lane == 0 && t < cnt) {
         double* q = qm[t];
+        double gu, gv;
+        frame_apply(info >> 28, acc[t][1], acc[t][2], gu, gv);
         q[d] = acc[t][0];
-        q[plane + d] = acc[t][1];
-        q[2 * plane + d] = acc[t][2];
+        q[plane + d] = gu;
+        q[2 * plane + d] = gv;
       }
     }
   }
@@ -134,7 +142,7 @@ int launch_batch_fill_halo(const BatchGrid* grids, int n_grids, int total_rows, 
                            const BatchMember* members, double* base, void* stream) {
   if (total_rows == 0) return 0;
   const int threads = 256;
-  const int blocks = (int)(((size_t)total_rows * 16 + threads - 1) / threads);
+  const int blocks = (int)(((size_t)total_rows * kHaloLanes + threads - 1) / threads);
   hipLaunchKernelGGL(k_fill_halo_batch, dim3(blocks), dim3(threads), 0, (hipStream_t)stream, grids, n_grids,
                      total_rows, members_by_grid, members, base);
   return (int)hipGetLastError();

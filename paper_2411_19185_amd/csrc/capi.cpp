@@ -188,13 +188,16 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
   gsc.r = h.r;
   gsc.m = h.m;
   GhostDev& g = G->g;
-  int e1 = upload(G, h.g_dst, &g.dst);
-  if (!e1) e1 = upload(G, h.g_ptr, &g.ptr);
-  if (!e1) e1 = upload(G, h.g_col, &g.col);
-  if (!e1) e1 = upload(G, h.g_val, &g.val);
+  int e1 = upload(G, h.z_dst, &g.dst);
+  if (!e1) e1 = upload(G, h.z_info, &g.info);
+  if (!e1) e1 = upload(G, h.z_ptr, &g.ptr);
+  if (!e1) e1 = upload(G, h.z_col, &g.col);
+  if (!e1) e1 = upload(G, h.z_ce, &g.ce);
+  if (!e1) e1 = upload(G, h.z_cval, &g.cval);
   if (e1) { free_grid(G); return e1; }
-  g.nnz = (int64_t)h.g_col.size();
-  g.rows = (int)h.g_dst.size();
+  g.nnz = (int64_t)h.z_col.size();
+  g.cnnz = (int64_t)(h.z_cval.size() / 5);
+  g.rows = (int)h.z_dst.size();
   {
     // transpose of G, rows by interior cell (CSR over the cells it reads)
     const int n = h.n, P = h.P, r = h.r;
@@ -245,6 +248,12 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
   std::vector<int32_t>().swap(h.g_ptr);
   std::vector<int32_t>().swap(h.g_col);
   std::vector<double>().swap(h.g_val);
+  std::vector<int32_t>().swap(h.z_dst);
+  std::vector<int32_t>().swap(h.z_info);
+  std::vector<int32_t>().swap(h.z_ptr);
+  std::vector<int32_t>().swap(h.z_col);
+  std::vector<uint16_t>().swap(h.z_ce);
+  std::vector<double>().swap(h.z_cval);
   std::vector<double>().swap(h.bt_conv);
   *out = G;
   return HOPE_OK;

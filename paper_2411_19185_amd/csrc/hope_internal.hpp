@@ -38,6 +38,17 @@ struct HostTables {
   std::vector<int32_t> g_col;          // padded offset of the interior cell
   std::vector<double> g_val;           // 5 x nnz: mass, C11, C12, C21, C22 (SoA)
   int ghost_sweeps = 0;
+  // the same map in the form the ghost-fill kernels read: the cube's 24
+  // rotations carry one quarter of panel 0's ghost ring (the canonical rows)
+  // onto every ghost cell, so the values are stored once per canonical row
+  // and every row keeps only its columns and a 16-bit reference per entry.
+  // Rows are in the order of g_dst.
+  std::vector<int32_t> z_dst;          // padded offset of the row's ghost
+  std::vector<int32_t> z_info;         // start of its canonical row in z_cval | (output frame code << 28)
+  std::vector<int32_t> z_ptr;          // row pointers
+  std::vector<int32_t> z_col;          // padded offset of the interior cell read (ascending in a row)
+  std::vector<uint16_t> z_ce;          // entry within the canonical row | (frame code of the cell's panel << 13)
+  std::vector<double> z_cval;          // 5 x canonical nnz: mass, C11, C12, C21, C22 (SoA)
   // panel-edge traces: for (panel A, side, t, h): the neighbour cell and point
   std::vector<int32_t> bt_cell;        // 6*4*n: padded offset of B's cell centre
   std::vector<int32_t> bt_side;        // 6*4*n: which side of B's cell (0 L,1 R,2 B,3 T)
@@ -114,12 +125,20 @@ struct GridScalars {
   int n, P, r, m;
 };
 
+// Ghost map on the device in its rotation-compressed form (the z_* tables of
+// HostTables).  A frame code f describes a cube rotation on one panel: the
+// image of panel coordinates (X, Y) is (sx * (sw ? Y : X), sy * (sw ? X : Y))
+// with sw = f & 1, sx = -1 if f & 2, sy = -1 if f & 4; contravariant momentum
+// components map the same way.
 struct GhostDev {
   const int32_t* dst;
+  const int32_t* info;
   const int32_t* ptr;
   const int32_t* col;
-  const double* val;     // 5 x nnz
-  int64_t nnz;
+  const uint16_t* ce;
+  const double* cval;    // 5 x cnnz
+  int64_t nnz;           // entries of all rows
+  int64_t cnnz;          // entries of the canonical rows
   int rows;
 };
 

@@ -532,6 +532,249 @@ int build_ghost_map(HostTables& t) {
 }
 
 // ---------------------------------------------------------------------------
+// Rotation compression of the ghost map.  Each of the cube's 24 rotations maps
+// panels onto panels and, on each panel, the gnomonic coordinates (X, Y) by a
+// signed permutation (a frame code, see GhostDev).  The rotations act freely on
+// ghost cells, and the quarter of panel 0's ghost ring below its bottom edge
+// (padded rows 0..r-1, padded columns 0..n+r-1) meets every orbit once, so
+// every ghost row is the image of one such canonical row: the same mass
+// weights at the image cells, and momentum blocks T(f_ghost) C T(f_cell)^T.
+// The map built by the fixed point is checked against its images (they agree
+// to rounding) and then replaced by them, so that the rows the host reports,
+// the adjoint's transpose and the compressed device rows are one map.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct CubeRot {
+  int img[6];    // image panel of each panel
+  int code[6];   // frame code on each panel
+};
+
+// frame code f: (X, Y) -> (sx (sw ? Y : X), sy (sw ? X : Y))
+void frame_apply(int f, ld X, ld Y, ld& X2, ld& Y2) {
+  const bool sw = f & 1;
+  const ld sx = (f & 2) ? -1 : 1, sy = (f & 4) ? -1 : 1;
+  X2 = sx * (sw ? Y : X);
+  Y2 = sy * (sw ? X : Y);
+}
+
+// the same on centred cell indices i in [-r, n+r) (X -> -X is i -> n-1-i)
+void frame_index(int f, int n, int i, int j, int& i2, int& j2) {
+  const bool sw = f & 1;
+  const int a = sw ? j : i, b = sw ? i : j;
+  i2 = (f & 2) ? n - 1 - a : a;
+  j2 = (f & 4) ? n - 1 - b : b;
+}
+
+// 2x2 matrix of a frame code acting on contravariant components
+void frame_matrix(int f, ld T[4]) {
+  const bool sw = f & 1;
+  const ld sx = (f & 2) ? -1 : 1, sy = (f & 4) ? -1 : 1;
+  T[0] = sw ? 0 : sx;
+  T[1] = sw ? sx : 0;
+  T[2] = sw ? sy : 0;
+  T[3] = sw ? 0 : sy;
+}
+
+int cube_rotations(std::vector<CubeRot>& out, std::string& err) {
+  const int perms[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {2, 1, 0}, {1, 0, 2}};
+  const int psign[6] = {1, 1, 1, -1, -1, -1};
+  const ld pts[2][2] = {{0.3L, 0.1L}, {-0.2L, 0.45L}};
+  for (int pi = 0; pi < 6; ++pi)
+    for (int sg = 0; sg < 8; ++sg) {
+      const int sgn[3] = {(sg & 1) ? -1 : 1, (sg & 2) ? -1 : 1, (sg & 4) ? -1 : 1};
+      if (psign[pi] * sgn[0] * sgn[1] * sgn[2] != 1) continue;   // proper rotations only
+      auto rot = [&](const ld u[3], ld u2[3]) {
+        for (int c = 0; c < 3; ++c) u2[c] = sgn[c] * u[perms[pi][c]];
+      };
+      CubeRot R;
+      for (int B = 0; B < 6; ++B) {
+        ld a[3] = {(ld)kAxisDir[B][0], (ld)kAxisDir[B][1], (ld)kAxisDir[B][2]}, a2[3];
+        rot(a, a2);
+        R.img[B] = -1;
+        for (int B2 = 0; B2 < 6; ++B2)
+          if (kAxisDir[B2][0] == (int)a2[0] && kAxisDir[B2][1] == (int)a2[1] && kAxisDir[B2][2] == (int)a2[2])
+            R.img[B] = B2;
+        R.code[B] = -1;
+        for (int f = 0; f < 8 && R.code[B] < 0; ++f) {
+          bool ok = true;
+          for (const auto& pt : pts) {
+            ld u[3], u2[3], X2, Y2, eX, eY;
+            unit_vec(B, pt[0], pt[1], u);
+            rot(u, u2);
+            inverse_map(R.img[B], u2, X2, Y2);
+            frame_apply(f, pt[0], pt[1], eX, eY);
+            ok = ok && std::fabs(X2 - eX) < 1e-12L && std::fabs(Y2 - eY) < 1e-12L;
+          }
+          if (ok) R.code[B] = f;
+        }
+        if (R.img[B] < 0 || R.code[B] < 0) {
+          err = "cube rotation does not map panel coordinates by a signed permutation";
+          return HOPE_ERR_NUMERIC;
+        }
+      }
+      out.push_back(R);
+    }
+  if (out.size() != 24) {
+    err = "cube rotation group incomplete";
+    return HOPE_ERR_NUMERIC;
+  }
+  return 0;
+}
+
+}  // namespace
+
+int compress_ghost_map(HostTables& t) {
+  const int n = t.n, r = t.r, P = t.P;
+  const int PP = P * P;
+  std::vector<CubeRot> rots;
+  if (int st = cube_rotations(rots, t.error)) return st;
+  const int G = (int)t.g_dst.size();
+  std::vector<int32_t> gidx(6 * (size_t)PP, -1);
+  for (int g = 0; g < G; ++g) gidx[t.g_dst[g]] = g;
+  // image of a padded offset under rotation R
+  auto image = [&](const CubeRot& R, int32_t off) {
+    const int B = off / PP, jj = (off / P) % P, ii = off % P;
+    int i2, j2;
+    frame_index(R.code[B], n, ii - r, jj - r, i2, j2);
+    return (int32_t)(R.img[B] * PP + (j2 + r) * P + (i2 + r));
+  };
+  struct E {
+    int32_t col;
+    int canon;    // entry within the canonical row
+    int code;     // frame code on the cell's panel
+    double v[5];
+  };
+  const size_t nnz = t.g_col.size();
+  std::vector<int32_t> hit(G, 0);
+  std::vector<std::vector<E>> rows(G);     // symmetrised rows, by ghost row index
+  std::vector<int> row_canon(G), row_code(G), canon_start;
+  std::vector<int32_t> canon_rows;         // row index of each canonical ghost
+  for (int jj = 0; jj < r; ++jj)
+    for (int ii = 0; ii < n + r; ++ii) canon_rows.push_back(gidx[jj * P + ii]);
+  if ((int)canon_rows.size() * 24 != G) {
+    t.error = "ghost rows are not 24 copies of the canonical rows";
+    return HOPE_ERR_NUMERIC;
+  }
+  std::vector<double> cval[5];
+  double worst = 0;
+  for (size_t c = 0; c < canon_rows.size(); ++c) {
+    const int g0 = canon_rows[c];
+    if (g0 < 0) {
+      t.error = "canonical ghost cell missing";
+      return HOPE_ERR_NUMERIC;
+    }
+    const int32_t b = t.g_ptr[g0], e = t.g_ptr[g0 + 1];
+    canon_start.push_back((int)cval[0].size());
+    for (int32_t k = b; k < e; ++k)
+      for (int comp = 0; comp < 5; ++comp) cval[comp].push_back(t.g_val[comp * nnz + k]);
+    for (int ri = 0; ri < 24; ++ri) {
+      const CubeRot& R = rots[ri];
+      const int32_t d = image(R, t.g_dst[g0]);
+      const int g = gidx[d];
+      if (g < 0 || hit[g]++) {
+        t.error = "rotation images of the ghost ring do not tile it";
+        return HOPE_ERR_NUMERIC;
+      }
+      row_canon[g] = (int)c;
+      const int f0 = R.code[0];
+      row_code[g] = f0;
+      ld T0[4];
+      frame_matrix(f0, T0);
+      std::vector<E>& row = rows[g];
+      row.reserve(e - b);
+      for (int32_t k = b; k < e; ++k) {
+        E x;
+        x.col = image(R, t.g_col[k]);
+        x.canon = k - b;
+        x.code = R.code[t.g_col[k] / PP];
+        ld T[4];
+        frame_matrix(x.code, T);
+        const ld C[4] = {t.g_val[nnz + k], t.g_val[2 * nnz + k], t.g_val[3 * nnz + k], t.g_val[4 * nnz + k]};
+        ld TC[4];   // T0 C
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) TC[i * 2 + j] = T0[i * 2] * C[j] + T0[i * 2 + 1] * C[2 + j];
+        x.v[0] = t.g_val[k];
+        for (int i = 0; i < 2; ++i)       // (T0 C) T^T; exact, T and T0 are signed permutations
+          for (int j = 0; j < 2; ++j) x.v[1 + i * 2 + j] = (double)(TC[i * 2] * T[j * 2] + TC[i * 2 + 1] * T[j * 2 + 1]);
+        row.push_back(x);
+      }
+      std::sort(row.begin(), row.end(), [](const E& a, const E& b2) { return a.col < b2.col; });
+      // agreement with the row the fixed point gave for this ghost
+      double rowmax = 0, diff = 0;
+      const int32_t ob = t.g_ptr[g], oe = t.g_ptr[g + 1];
+      for (int32_t k = ob; k < oe; ++k)
+        for (int comp = 0; comp < 5; ++comp) rowmax = std::max(rowmax, std::fabs(t.g_val[comp * nnz + k]));
+      size_t a = 0;
+      int32_t k = ob;
+      while (a < row.size() || k < oe) {
+        if (k >= oe || (a < row.size() && row[a].col < t.g_col[k])) {
+          for (int comp = 0; comp < 5; ++comp) diff = std::max(diff, std::fabs(row[a].v[comp]));
+          ++a;
+        } else if (a >= row.size() || t.g_col[k] < row[a].col) {
+          for (int comp = 0; comp < 5; ++comp) diff = std::max(diff, std::fabs(t.g_val[comp * nnz + k]));
+          ++k;
+        } else {
+          for (int comp = 0; comp < 5; ++comp)
+            diff = std::max(diff, std::fabs(row[a].v[comp] - t.g_val[comp * nnz + k]));
+          ++a;
+          ++k;
+        }
+      }
+      worst = std::max(worst, diff / (rowmax > 0 ? rowmax : 1));
+      if (e - b >= (1 << 13)) {
+        t.error = "ghost row longer than 8191 entries";
+        return HOPE_ERR_UNSUPPORTED;
+      }
+    }
+  }
+  if (worst > 1e-12) {
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "ghost map not rotation symmetric (max relative difference %.3g)", worst);
+    t.error = buf;
+    return HOPE_ERR_NUMERIC;
+  }
+  // the host rows become the symmetrised ones (same row order)
+  std::vector<int32_t> ptr(G + 1, 0), col;
+  std::vector<double> val[5];
+  for (int g = 0; g < G; ++g) {
+    for (const E& x : rows[g]) {
+      col.push_back(x.col);
+      for (int comp = 0; comp < 5; ++comp) val[comp].push_back(x.v[comp]);
+    }
+    ptr[g + 1] = (int32_t)col.size();
+  }
+  t.g_ptr = ptr;
+  t.g_col = col;
+  t.g_val.resize(5 * col.size());
+  for (int comp = 0; comp < 5; ++comp) std::copy(val[comp].begin(), val[comp].end(), t.g_val.begin() + comp * col.size());
+  // device form, rows in ghost order: neighbouring rows read overlapping
+  // stencils (and, for one rotation, neighbouring canonical rows)
+  const size_t cnnz = cval[0].size();
+  if (cnnz >= (size_t)1 << 28) {
+    t.error = "canonical ghost map too large";
+    return HOPE_ERR_UNSUPPORTED;
+  }
+  t.z_cval.resize(5 * cnnz);
+  for (int comp = 0; comp < 5; ++comp) std::copy(cval[comp].begin(), cval[comp].end(), t.z_cval.begin() + comp * cnnz);
+  t.z_dst.clear();
+  t.z_info.clear();
+  t.z_col.clear();
+  t.z_ce.clear();
+  t.z_ptr.assign(1, 0);
+  for (int g = 0; g < G; ++g) {
+    t.z_dst.push_back(t.g_dst[g]);
+    t.z_info.push_back(canon_start[row_canon[g]] | (row_code[g] << 28));
+    for (const E& x : rows[g]) {
+      t.z_col.push_back(x.col);
+      t.z_ce.push_back((uint16_t)(x.canon | (x.code << 13)));
+    }
+    t.z_ptr.push_back((int32_t)t.z_col.size());
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // Panel-edge trace maps: the neighbour cell and Gauss point at every EQP of
 // every panel side, and the conversion into this panel's variables.
 // ---------------------------------------------------------------------------
@@ -712,6 +955,7 @@ int build_tables(HostTables& t, int n, int k, int weno, double radius, double om
   t.fcoef.resize(18);
   coriolis_coefs(tilt, t.fcoef.data());
   int st = build_ghost_map(t);
+  if (!st) st = compress_ghost_map(t);
   if (st) return st;
   return build_edge_maps(t);
 }

@@ -29,30 +29,57 @@
 
 namespace hope {
 
-// one ghost row of g = G q, reduced over 16 lanes (lane = 0..15 of the group)
+// Frame codes of the rotation-compressed ghost map (GhostDev).  A row of a
+// canonical momentum block, (c1, c2), acts on the canonical frame of the
+// cell read; acting instead on that cell's own frame it is T (c1, c2), T the
+// code's matrix.  A canonical ghost momentum (c1, c2) in the ghost's panel
+// frame is also T (c1, c2).  Signed permutations: exact.
+__device__ __forceinline__ void frame_apply(int f, double c1, double c2, double& g1, double& g2) {
+  const bool sw = f & 1;
+  const double sx = (f & 2) ? -1.0 : 1.0, sy = (f & 4) ? -1.0 : 1.0;
+  g1 = sx * (sw ? c2 : c1);
+  g2 = sy * (sw ? c1 : c2);
+}
+
+// lanes that share one ghost row in the ghost-fill kernels
+#ifndef HOPE_HALO_LANES
+#define HOPE_HALO_LANES 32
+#endif
+constexpr int kHaloLanes = HOPE_HALO_LANES;
+
+// one ghost row of g = G q, reduced over kHaloLanes lanes (lane = 0.. of the
+// group): entries in column order, values from the row's canonical row
 __device__ __forceinline__ void halo_row(const GhostDev& g, double* __restrict__ q, size_t plane, int row, int lane) {
   const int b = g.ptr[row], e = g.ptr[row + 1];
+  const int info = g.info[row];
+  const double* cv = g.cval + (info & 0x0fffffff);
   const double* q1 = q + plane;
   const double* q2 = q + 2 * (size_t)plane;
   double mass = 0, mu = 0, mv = 0;
-  for (int k = b + lane; k < e; k += 16) {
+  for (int k = b + lane; k < e; k += kHaloLanes) {
     const int c = g.col[k];
-    const double a0 = q[c], a1 = q1[c], a2 = q2[c];
-    mass = fma(g.val[k], a0, mass);
-    mu = fma(g.val[g.nnz + k], a1, fma(g.val[2 * g.nnz + k], a2, mu));
-    mv = fma(g.val[3 * g.nnz + k], a1, fma(g.val[4 * g.nnz + k], a2, mv));
+    const int ce = g.ce[k];
+    const int j = ce & 0x1fff, f = ce >> 13;
+    double w1, w2, w3, w4;
+    frame_apply(f, cv[g.cnnz + j], cv[2 * g.cnnz + j], w1, w2);
+    frame_apply(f, cv[3 * g.cnnz + j], cv[4 * g.cnnz + j], w3, w4);
+    mass = fma(cv[j], q[c], mass);
+    mu = fma(w1, q1[c], fma(w2, q2[c], mu));
+    mv = fma(w3, q1[c], fma(w4, q2[c], mv));
   }
 #pragma unroll
-  for (int off = 8; off > 0; off >>= 1) {
-    mass += __shfl_xor(mass, off, 16);
-    mu += __shfl_xor(mu, off, 16);
-    mv += __shfl_xor(mv, off, 16);
+  for (int off = kHaloLanes / 2; off > 0; off >>= 1) {
+    mass += __shfl_xor(mass, off, kHaloLanes);
+    mu += __shfl_xor(mu, off, kHaloLanes);
+    mv += __shfl_xor(mv, off, kHaloLanes);
   }
   if (lane == 0) {
     const int d = g.dst[row];
+    double gu, gv;
+    frame_apply(info >> 28, mu, mv, gu, gv);
     q[d] = mass;
-    q[plane + d] = mu;
-    q[2 * (size_t)plane + d] = mv;
+    q[plane + d] = gu;
+    q[2 * (size_t)plane + d] = gv;
   }
 }
 

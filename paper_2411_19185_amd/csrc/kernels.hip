@@ -1,7 +1,7 @@
 // HIP kernels (gfx950, FP64) of the HOPE right-hand side on one grid; the
 // bodies they run are in kernel_bodies.hpp.
 //
-//  k_fill_halo     ghost cells g = G q (appendix (7.12)); 16 lanes per ghost row
+//  k_fill_halo     ghost cells g = G q (appendix (7.12)); kHaloLanes lanes per ghost row
 //  k_edge_traces   at every panel-edge Gauss point, the neighbour panel's own
 //                  trace, converted into this panel's variables (3.26)-(3.29)
 //  k_stage         fused reconstruction, LMARS, quadrature, sources, tendency
@@ -18,9 +18,9 @@ namespace hope {
 // Ghost fill
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fill_halo(GhostDev g, double* __restrict__ q, int plane) {
-  const int row = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 4);
-  if (row >= g.rows) return;   // whole 16-lane group leaves together
-  halo_row(g, q, plane, row, threadIdx.x & 15);
+  const int row = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kHaloLanes);
+  if (row >= g.rows) return;   // the whole lane group leaves together
+  halo_row(g, q, plane, row, threadIdx.x % kHaloLanes);
 }
 
 // ---------------------------------------------------------------------------
@@ -73,7 +73,7 @@ int launch_combine(size_t len, double* out, const double* x, const double* y, co
 int launch_fill_halo(const GhostDev& g, double* q, int plane, void* stream) {
   if (g.rows == 0) return 0;
   const int threads = 256;
-  const int blocks = (int)(((size_t)g.rows * 16 + threads - 1) / threads);
+  const int blocks = (int)(((size_t)g.rows * kHaloLanes + threads - 1) / threads);
   hipLaunchKernelGGL(k_fill_halo, dim3(blocks), dim3(threads), 0, (hipStream_t)stream, g, q, plane);
   return (int)hipGetLastError();
 }
