@@ -249,6 +249,10 @@ def tpp11(args):
     g = Grid(n, 11, "tpp", axis_tilt=f.alpha)
     qp = g.new_state()
     g.interior(qp).copy_(torch.from_numpy(q))
+    # the stage's work-item shape, tuned on this grid (order 11 fits one
+    # workgroup per CU, so the default shape for order 5 does not carry over)
+    from paper_2411_19185_amd import autotune
+    autotune.tune_grid(g, qp)
     w = torch.from_numpy(hi.normal_array(args.seed + 7, (3, 6, n, n))).cuda()
     dq = torch.empty_like(w)
     gq = torch.empty_like(w)
@@ -275,7 +279,8 @@ def tpp11(args):
     t_step = timed(lambda: g.rk_step(qs, dt, "ssp3", ws))
     t_step_vjp = timed(lambda: g.rk_step_vjp(qp, dt, w, "ssp3", gq, rws))
     cells = 6 * n * n
-    return {"cells": cells, "tendency_ms": t_fwd, "tendency_vjp_ms": t_vjp, "rk_step_ms": t_step,
+    return {"cells": cells, "launch": list(g.get_launch()), "tendency_ms": t_fwd, "tendency_vjp_ms": t_vjp,
+            "rk_step_ms": t_step,
             "rk_step_vjp_ms": t_step_vjp, "fwd_value": cells / (t_fwd / 1e3),
             "fwd_vjp_value": cells / ((t_fwd + t_vjp) / 1e3), "unit": "cell-tendency evals/s"}
 

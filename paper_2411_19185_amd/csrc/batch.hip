@@ -108,8 +108,10 @@ __global__ __launch_bounds__(64) void k_edge_traces_batch(const BatchMember* __r
   edge_trace<K, W, M>((cdp)bm.tab, (cip)bm.itab, bm.gs, in + bm.q_off, bt + bm.bt_off, local);
 }
 
+// orders <= 5 fit 4 workgroups (3 wavefronts per SIMD) by LDS; the register
+// allocation is held to that occupancy
 template <int K, bool W, int M>
-__global__ __launch_bounds__(kStageThreads) void k_stage_batch(const BatchMember* __restrict__ mem,
+__global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu(K <= 5 ? 3 : 1))) void k_stage_batch(const BatchMember* __restrict__ mem,
                                                                       const int32_t* __restrict__ items,
                                                                       int n_items, BatchStage S) {
   __shared__ StageSmem<K, W, M> sm;

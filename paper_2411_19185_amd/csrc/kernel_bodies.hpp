@@ -325,8 +325,15 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
   // j-1 in ptop, qR: bottom trace of row j in pts)
   auto yflux = [&](int j) {
     double gb[3] = {0.0, 0.0, 0.0};
+    // the lane's Gauss-node tables, requested one node ahead
+    double xg_n = Xg[ic * M], sq_n = sqg[ic * M];
 #pragma unroll 1
     for (int h = 0; h < M; ++h) {
+      const double xg = xg_n, sqv = sq_n;
+      if (h + 1 < M) {
+        xg_n = Xg[ic * M + h + 1];
+        sq_n = sqg[ic * M + h + 1];
+      }
       double qL[3], qR[3];
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
@@ -335,7 +342,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
         qR[v] = real ? pt(v, SM::PB + h) : dflt;
       }
       double F[3];
-      lmars(qL, qR, Xg[ic * M + h], Xe[j], sqg[ic * M + h], sqe[j], 1, ia, F);
+      lmars(qL, qR, xg, Xe[j], sqv, sqe[j], 1, ia, F);
 #pragma unroll
       for (int v = 0; v < 3; ++v) gb[v] = fma(gw[h], F[v], gb[v]);
     }
@@ -375,9 +382,11 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     cdp fc = fcb + p * 3;
     const double Lx0 = fc[0], LxX = fc[1], LxY = fc[2];
     double s1 = 0.0, s2 = 0.0;
+    double x_n = Xg[ic * M];
 #pragma unroll 1
     for (int h = 0; h < M; ++h) {
-      const double X = Xg[ic * M + h];
+      const double X = x_n;
+      if (h + 1 < M) x_n = Xg[ic * M + h + 1];
 #pragma unroll
       for (int w = 0; w < M; ++w) {
         double cq[3];
