@@ -74,3 +74,70 @@ def test_batch_create_rejects_bad_arguments():
     assert lib().hope_batch_create(arr, 1, None, ctypes.byref(h)) == -1
     assert lib().hope_batch_create(arr, 0, None, ctypes.byref(h)) == -1
     assert "null" in lib().hope_last_error().decode() or "n_members" in lib().hope_last_error().decode()
+
+
+def _tangent_basis(p, x, y, h=1e-6):
+    """Columns d(point)/dx, d(point)/dy of panel p at angles (x, y) (extended
+    coordinates allowed), by central differences of the oracle's panel map."""
+    from oracle.geometry import panel_xyz
+    ex = (panel_xyz(p, np.tan(x + h), np.tan(y)) - panel_xyz(p, np.tan(x - h), np.tan(y))) / (2 * h)
+    ey = (panel_xyz(p, np.tan(x), np.tan(y + h)) - panel_xyz(p, np.tan(x), np.tan(y - h))) / (2 * h)
+    return np.stack([ex, ey], axis=-1)
+
+
+def _rotation_image(R, p, i, j, n):
+    """Panel, centred cell indices and 2x2 map of contravariant components of
+    the image under the cube rotation R of cell (i, j) of panel p (indices
+    in [-r, n+r): ghost cells in p's extended coordinates)."""
+    from oracle.geometry import PANEL_AXIS, panel_xyz, xyz_to_XY
+    D = np.pi / (2 * n)
+    x, y = (i + 0.5 - n / 2) * D, (j + 0.5 - n / 2) * D
+    v = R @ panel_xyz(p, np.tan(x), np.tan(y))
+    q = int(np.argmin(np.abs(PANEL_AXIS - R @ PANEL_AXIS[p]).sum(axis=1)))
+    X2, Y2 = xyz_to_XY(q, v)
+    x2, y2 = np.arctan(X2), np.arctan(Y2)
+    i2, j2 = x2 / D + n / 2 - 0.5, y2 / D + n / 2 - 0.5
+    assert abs(i2 - round(i2)) < 1e-9 and abs(j2 - round(j2)) < 1e-9
+    E, E2 = _tangent_basis(p, x, y), _tangent_basis(q, x2, y2)
+    Mx = np.linalg.lstsq(E2, R @ E, rcond=None)[0]
+    M = np.round(Mx)
+    assert np.abs(Mx - M).max() < 1e-6      # a signed permutation
+    return q, int(round(i2)), int(round(j2)), M
+
+
+@pytest.mark.parametrize("n,k", [(7, 3), (8, 5)])
+@pytest.mark.parametrize("axis_perm,signs", [((1, 0, 2), (-1, 1, 1)), ((0, 2, 1), (1, -1, 1)), ((2, 0, 1), (1, 1, 1))])
+def test_library_ghost_map_commutes_with_cube_rotations(n, k, axis_perm, signs):
+    """The ghost map is equivariant under the cube's rotations: the ghosts of a
+    rotated field are the rotated ghosts.  Rotations and momentum frames come
+    from the oracle's panel maps (independent of the library's frame codes,
+    which compress the map by this symmetry)."""
+    R = np.zeros((3, 3))
+    for a, (b, s) in enumerate(zip(axis_perm, signs)):
+        R[a, b] = s
+    assert abs(np.linalg.det(R) - 1) < 1e-12
+    r = (k - 1) // 2
+    P = n + 2 * r
+    rng = np.random.default_rng(n * 7 + k)
+    q = rng.uniform(0.5, 1.5, (3, 6, n, n))
+    rot = np.zeros_like(q)
+    for p in range(6):
+        for j in range(n):
+            for i in range(n):
+                p2, i2, j2, M = _rotation_image(R, p, i, j, n)
+                rot[0, p2, j2, i2] = q[0, p, j, i]
+                rot[1:, p2, j2, i2] = M @ q[1:, p, j, i]
+    a, _ = _apply_library_ghost_map(n, k, q)
+    b, _ = _apply_library_ghost_map(n, k, rot)
+    scale = np.abs(a).max()
+    worst = 0.0
+    for p in range(6):
+        for jj in range(P):
+            for ii in range(P):
+                if r <= jj < r + n and r <= ii < r + n:
+                    continue
+                p2, i2, j2, M = _rotation_image(R, p, ii - r, jj - r, n)
+                want = np.concatenate([[a[0, p, jj, ii]], M @ a[1:, p, jj, ii]])
+                got = b[:, p2, j2 + r, i2 + r]
+                worst = max(worst, np.abs(want - got).max() / scale)
+    assert worst < 1e-13, worst
