@@ -56,7 +56,8 @@ enum {
   HOPE_ERR_UNSUPPORTED = -2, /* order/scheme/n combination not built */
   HOPE_ERR_HIP = -3,         /* a HIP runtime call failed */
   HOPE_ERR_NOMEM = -4,       /* device or host allocation failed in create */
-  HOPE_ERR_NUMERIC = -5      /* ghost-map construction did not converge */
+  HOPE_ERR_NUMERIC = -5      /* ghost-map construction did not converge, or its rows
+                                are not images of each other under the cube's rotations */
 };
 
 enum { HOPE_SCHEME_TPP = 0, HOPE_SCHEME_WENO = 1 };
@@ -99,7 +100,11 @@ typedef struct hope_layout {
 /* Build a grid: equiangular metrics, reconstruction and WENO tables, the
  * exact ghost-cell map G of appendix (7.12) (the fixed point of the iterative
  * interpolation of section 3.3.1, with owner-panel conversion (3.26)-(3.29)),
- * and the panel-edge trace maps.  Host work plus device uploads; synchronous.
+ * and the panel-edge trace maps.  G commutes with the cube's 24 rotations;
+ * each row is replaced by the rotation image of one of r*(n+r) canonical rows
+ * (they agree to rounding; the build fails with HOPE_ERR_NUMERIC otherwise),
+ * and the device keeps the values once per canonical row.  Host work plus
+ * device uploads; synchronous.
  * On success *out owns device memory until hope_grid_destroy. */
 int hope_grid_create(const hope_grid_desc* desc, hope_grid** out);
 void hope_grid_destroy(hope_grid* grid);
@@ -177,7 +182,9 @@ int hope_grid_profile_read(hope_grid* grid, int32_t kernel, double* total_ms, in
  * rows (dst), rows+1 (ptr), nnz (col) and 5*nnz (val, struct of arrays:
  * mass, C11, C12, C21, C22) elements.  dst/col are offsets inside one
  * variable plane of the padded layout ((panel*P + jj)*P + ii).  Also returns
- * the number of fixed-point sweeps the construction took in *sweeps. */
+ * the number of fixed-point sweeps the construction took in *sweeps.  These
+ * are the rows the device applies (the rotation images of the canonical
+ * rows), entries in ascending column order. */
 int hope_inspect_ghost_map(const hope_grid_desc* desc, int64_t* rows, int64_t* nnz, int32_t* sweeps,
                            int32_t* dst, int32_t* ptr, int32_t* col, double* val);
 
