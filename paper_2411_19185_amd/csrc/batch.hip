@@ -23,7 +23,8 @@ __global__ __launch_bounds__(256) void k_fill_halo_batch(const BatchGrid* __rest
                                                          int total_rows, const int32_t* __restrict__ mlist,
                                                          const BatchMember* __restrict__ mem,
                                                          double* __restrict__ base) {
-  const int row = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kHaloLanes);
+  const int lb = xcd_block(blockIdx.x, gridDim.x);   // contiguous rows per L2 domain
+  const int row = (int)((lb * (size_t)blockDim.x + threadIdx.x) / kHaloLanes);
   if (row >= total_rows) return;   // the whole lane group leaves together
   int gi = 0;
   while (gi + 1 < n_grids && grids[gi + 1].row_begin <= row) ++gi;
@@ -144,7 +145,8 @@ int launch_batch_fill_halo(const BatchGrid* grids, int n_grids, int total_rows, 
                            const BatchMember* members, double* base, void* stream) {
   if (total_rows == 0) return 0;
   const int threads = 256;
-  const int blocks = (int)(((size_t)total_rows * kHaloLanes + threads - 1) / threads);
+  int blocks = (int)(((size_t)total_rows * kHaloLanes + threads - 1) / threads);
+  blocks = (blocks + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL(k_fill_halo_batch, dim3(blocks), dim3(threads), 0, (hipStream_t)stream, grids, n_grids,
                      total_rows, members_by_grid, members, base);
   return (int)hipGetLastError();

@@ -42,7 +42,7 @@ struct HostTables {
   // rotations carry one quarter of panel 0's ghost ring (the canonical rows)
   // onto every ghost cell, so the values are stored once per canonical row
   // and every row keeps only its columns and a 16-bit reference per entry.
-  // Rows are in the order of g_dst.
+  // Rows are ordered for the L2 domains of the chip (see compress_ghost_map).
   std::vector<int32_t> z_dst;          // padded offset of the row's ghost
   std::vector<int32_t> z_info;         // start of its canonical row in z_cval | (output frame code << 28)
   std::vector<int32_t> z_ptr;          // row pointers

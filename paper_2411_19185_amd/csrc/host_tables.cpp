@@ -648,7 +648,7 @@ int compress_ghost_map(HostTables& t) {
   const size_t nnz = t.g_col.size();
   std::vector<int32_t> hit(G, 0);
   std::vector<std::vector<E>> rows(G);     // symmetrised rows, by ghost row index
-  std::vector<int> row_canon(G), row_code(G), canon_start;
+  std::vector<int> row_canon(G), row_code(G), row_rot(G), canon_start;
   std::vector<int32_t> canon_rows;         // row index of each canonical ghost
   for (int jj = 0; jj < r; ++jj)
     for (int ii = 0; ii < n + r; ++ii) canon_rows.push_back(gidx[jj * P + ii]);
@@ -677,6 +677,7 @@ int compress_ghost_map(HostTables& t) {
         return HOPE_ERR_NUMERIC;
       }
       row_canon[g] = (int)c;
+      row_rot[g] = ri;
       const int f0 = R.code[0];
       row_code[g] = f0;
       ld T0[4];
@@ -748,8 +749,12 @@ int compress_ghost_map(HostTables& t) {
   t.g_col = col;
   t.g_val.resize(5 * col.size());
   for (int comp = 0; comp < 5; ++comp) std::copy(val[comp].begin(), val[comp].end(), t.g_val.begin() + comp * col.size());
-  // device form, rows in ghost order: neighbouring rows read overlapping
-  // stencils (and, for one rotation, neighbouring canonical rows)
+  // device form.  Row order: the canonical strip (r deep, n+r long) is cut
+  // along its length into kXcdChunks spans; rows go by span, then rotation,
+  // then position along the edge and depth.  Neighbouring rows read
+  // overlapping stencils, and the ghost-fill kernels give each of the chip's
+  // 8 L2 domains one contiguous range of rows, so each touches about one
+  // span's canonical values and ghost stencils rather than all of them.
   const size_t cnnz = cval[0].size();
   if (cnnz >= (size_t)1 << 28) {
     t.error = "canonical ghost map too large";
@@ -762,7 +767,16 @@ int compress_ghost_map(HostTables& t) {
   t.z_col.clear();
   t.z_ce.clear();
   t.z_ptr.assign(1, 0);
+  const int L = n + r, kXcdChunks = 8;
+  std::vector<int> order(G);
+  std::vector<int64_t> key(G);
   for (int g = 0; g < G; ++g) {
+    const int ii = row_canon[g] % L, jj = row_canon[g] / L;
+    key[g] = (((int64_t)(ii * kXcdChunks / L) * 24 + row_rot[g]) * L + ii) * r + jj;
+    order[g] = g;
+  }
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+  for (int g : order) {
     t.z_dst.push_back(t.g_dst[g]);
     t.z_info.push_back(canon_start[row_canon[g]] | (row_code[g] << 28));
     for (const E& x : rows[g]) {

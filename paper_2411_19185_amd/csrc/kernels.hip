@@ -18,7 +18,9 @@ namespace hope {
 // Ghost fill
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fill_halo(GhostDev g, double* __restrict__ q, int plane) {
-  const int row = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kHaloLanes);
+  // each L2 domain takes a contiguous range of rows (the rows are ordered for it)
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int row = (int)((lb * (size_t)blockDim.x + threadIdx.x) / kHaloLanes);
   if (row >= g.rows) return;   // the whole lane group leaves together
   halo_row(g, q, plane, row, threadIdx.x % kHaloLanes);
 }
@@ -73,7 +75,8 @@ int launch_combine(size_t len, double* out, const double* x, const double* y, co
 int launch_fill_halo(const GhostDev& g, double* q, int plane, void* stream) {
   if (g.rows == 0) return 0;
   const int threads = 256;
-  const int blocks = (int)(((size_t)g.rows * kHaloLanes + threads - 1) / threads);
+  int blocks = (int)(((size_t)g.rows * kHaloLanes + threads - 1) / threads);
+  blocks = (blocks + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL(k_fill_halo, dim3(blocks), dim3(threads), 0, (hipStream_t)stream, g, q, plane);
   return (int)hipGetLastError();
 }
