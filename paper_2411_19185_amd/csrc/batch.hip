@@ -8,7 +8,8 @@
 //                         that grid's members while the row's entries sit in
 //                         registers (G is read once per kHaloChunk = 16 members)
 //  k_edge_traces_batch    panel-edge traces (3.26)-(3.29) of all members; each
-//                         member's range is padded to whole wavefronts
+//                         member's range is padded to 64 sides (whole
+//                         wavefronts of lane groups)
 //  k_stage_batch          the fused stage over a flattened list of work items
 //                         (member, panel, strip, segment); with blocks < items
 //                         it is persistent, each workgroup striding the list
@@ -84,29 +85,21 @@ __global__ __launch_bounds__(256) void k_fill_halo_batch(const BatchGrid* __rest
   }
 }
 
-// member whose flattened range [edge_begin, next edge_begin) holds idx
-__device__ __forceinline__ int member_of_edge(const BatchMember* __restrict__ mem, int n_members, int idx) {
-  int lo = 0, hi = n_members - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (mem[mid].edge_begin <= idx) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 template <int K, bool W, int M>
-__global__ __launch_bounds__(64) void k_edge_traces_batch(const BatchMember* __restrict__ mem, int n_members,
+__global__ __launch_bounds__(64) void k_edge_traces_batch(const BatchMember* __restrict__ mem,
+                                                           const int32_t* __restrict__ edge_member,
                                                            int total_edges, const double* __restrict__ in,
                                                            double* __restrict__ bt) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = t / kEdgeLanes;   // one lane group per side
   if (idx >= total_edges) return;
-  // every member's range starts on a wavefront boundary, so the member is uniform
-  const int mi = __builtin_amdgcn_readfirstlane(member_of_edge(mem, n_members, idx));
+  // every member's range starts on a multiple of 64 sides, so the member is
+  // uniform over each wavefront
+  const int mi = __builtin_amdgcn_readfirstlane(edge_member[idx / 64]);
   const BatchMember& bm = mem[mi];
   const int local = idx - bm.edge_begin;
-  if (local >= 24 * bm.gs.n) return;
-  edge_trace<K, W, M>((cdp)bm.tab, (cip)bm.itab, bm.gs, in + bm.q_off, bt + bm.bt_off, local);
+  if (local >= 24 * bm.gs.n) return;   // the whole lane group leaves together
+  edge_trace<K, W, M>((cdp)bm.tab, (cip)bm.itab, bm.gs, in + bm.q_off, bt + bm.bt_off, local, t % kEdgeLanes);
 }
 
 // orders <= 5 fit 4 workgroups (3 wavefronts per SIMD) by LDS; the register
@@ -153,10 +146,10 @@ int launch_batch_fill_halo(const BatchGrid* grids, int n_grids, int total_rows, 
 }
 
 template <int K, bool W, int M>
-static int batch_edges_t(const BatchMember* members, int n_members, int total_edges, const double* in, double* bt,
-                         void* stream) {
-  hipLaunchKernelGGL((k_edge_traces_batch<K, W, M>), dim3((total_edges + 63) / 64), dim3(64), 0,
-                     (hipStream_t)stream, members, n_members, total_edges, in, bt);
+static int batch_edges_t(const BatchMember* members, const int32_t* edge_member, int total_edges, const double* in,
+                         double* bt, void* stream) {
+  hipLaunchKernelGGL((k_edge_traces_batch<K, W, M>), dim3((total_edges * kEdgeLanes + 63) / 64), dim3(64), 0,
+                     (hipStream_t)stream, members, edge_member, total_edges, in, bt);
   return (int)hipGetLastError();
 }
 
@@ -189,10 +182,10 @@ static int batch_stage_t(const BatchMember* members, const int32_t* items, int n
     return (int)hipErrorInvalidValue;                 \
   } while (0)
 
-int launch_batch_edge_traces(int k, int weno, const BatchMember* members, int n_members, int total_edges,
-                             const double* in, double* bt, void* stream) {
+int launch_batch_edge_traces(int k, int weno, const BatchMember* members, const int32_t* edge_member,
+                             int total_edges, const double* in, double* bt, void* stream) {
   if (total_edges == 0) return 0;
-  HOPE_BATCH_DISPATCH(batch_edges_t, members, n_members, total_edges, in, bt, stream);
+  HOPE_BATCH_DISPATCH(batch_edges_t, members, edge_member, total_edges, in, bt, stream);
 }
 
 int launch_batch_stage(int k, int weno, const BatchMember* members, const int32_t* items, int n_items, int blocks,

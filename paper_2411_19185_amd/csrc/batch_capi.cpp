@@ -24,6 +24,7 @@ struct hope_batch {
   BatchMember* mem = nullptr;
   BatchGrid* dgrids = nullptr;
   int32_t* mlist = nullptr;
+  int32_t* edge_member = nullptr;              // member of each block of 64 panel-edge sides
   int32_t* items = nullptr;
   double* fcoef = nullptr;
   double* bt = nullptr;
@@ -92,7 +93,7 @@ int batch_stage(const hope_batch* B, double* in, const double* qn, double* out, 
                 double cb, double cs, const double* dt, void* stream) {
   int e = launch_batch_fill_halo(B->dgrids, B->n_grids, B->total_rows, B->mlist, B->mem, in, stream);
   if (e) return hip_fail((hipError_t)e, "batch fill_halo launch");
-  e = launch_batch_edge_traces(B->k, B->weno, B->mem, B->n_members, B->total_edges, in, B->bt, stream);
+  e = launch_batch_edge_traces(B->k, B->weno, B->mem, B->edge_member, B->total_edges, in, B->bt, stream);
   if (e) return hip_fail((hipError_t)e, "batch edge_traces launch");
   BatchStage st;
   st.in = in;
@@ -135,6 +136,7 @@ int hope_batch_create(const hope_grid* const* grids, int32_t n_members, const do
   std::vector<double> fco(18 * (size_t)n_members);
   int64_t qo = 0, fo = 0, bo = 0;
   int eb = 0;
+  std::vector<int32_t> em;   // member of each block of 64 panel-edge sides
   B->hmem.resize(n_members);
   for (int i = 0; i < n_members; ++i) {
     const hope_grid* G = grids[i];
@@ -161,6 +163,7 @@ int hope_batch_create(const hope_grid* const* grids, int32_t n_members, const do
     fo += 18LL * n * n;
     bo += 24LL * n * B->m * 3;
     eb += ((24 * n + 63) / 64) * 64;
+    em.resize(eb / 64, i);
     if (axis_tilt) coriolis_coefs(axis_tilt[i], &fco[18 * (size_t)i]);
     else std::copy(G->h.fcoef.begin(), G->h.fcoef.end(), fco.begin() + 18 * (size_t)i);
   }
@@ -189,6 +192,7 @@ int hope_batch_create(const hope_grid* const* grids, int32_t n_members, const do
   int st = upload_vec(B, fco, &B->fcoef);
   if (!st) st = upload_vec(B, bgs, &B->dgrids);
   if (!st) st = upload_vec(B, ml, &B->mlist);
+  if (!st) st = upload_vec(B, em, &B->edge_member);
   if (!st) {
     for (int i = 0; i < n_members; ++i) B->hmem[i].fcoef = B->fcoef + 18 * (size_t)i;
     st = upload_vec(B, B->hmem, &B->mem);

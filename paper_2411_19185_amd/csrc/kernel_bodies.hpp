@@ -89,21 +89,26 @@ __device__ __forceinline__ void halo_row(const GhostDev& g, double* __restrict__
   }
 }
 
-// the converted neighbour trace at the panel-edge side idx (0 <= idx < 24 n)
+// the converted neighbour trace at the panel-edge side idx (0 <= idx < 24 n),
+// computed by a group of 4 consecutive lanes: lane g of the group
+// reconstructs variable min(g, 2) (lane 3 repeats variable 2, so the group
+// takes no divergent path), the group exchanges its values, and lane g < 3
+// writes component g of the converted trace (3.26)-(3.29)
+constexpr int kEdgeLanes = 4;
 template <int K, bool W, int M>
 __device__ __forceinline__ void edge_trace(cdp tab, cip itab, const GridScalars& gs, const double* __restrict__ q,
-                                           double* __restrict__ bt, int idx) {
+                                           double* __restrict__ bt, int idx, int g) {
   using C = Cfg<K, W, M>;
   const int n = gs.n, P = gs.P;
   const TabOffsets O = tab_offsets(K, W, M, n);
   const size_t vs = (size_t)6 * P * P;
-  const double* c0 = q + itab[O.i_cell + idx];
+  const int v = min(g, 2);
+  const double* c0 = q + itab[O.i_cell + idx] + v * vs;
   const int sd = itab[O.i_side + idx];
   const int rev = itab[O.i_rev + idx];
-  double vals[3][M];
-#pragma unroll
-  for (int v = 0; v < 3; ++v) {
-    auto at = [&](int dy, int dx) -> double { return c0[v * vs + dy * P + dx]; };
+  double vals[M];
+  {
+    auto at = [&](int dy, int dx) -> double { return c0[dy * P + dx]; };
     double kap[W ? C::S : 1];
     if constexpr (W) weno_kappa<K, W, M>(tab, gs.eps, at, [&](int j, double x) { kap[j] = x; });
     auto kf = [&](int j) -> double { return kap[j]; };
@@ -114,10 +119,10 @@ __device__ __forceinline__ void edge_trace(cdp tab, cip itab, const GridScalars&
         WCol<K, M> col;
         wcol<K, W, M>(tab, sd, xr, kf, col);
 #pragma unroll
-        for (int h = 0; h < M; ++h) vals[v][h] = wpoint<K, W, M>(tab, sd, 2 + h, sd * M + h, col);
+        for (int h = 0; h < M; ++h) vals[h] = wpoint<K, W, M>(tab, sd, 2 + h, sd * M + h, col);
       } else {
 #pragma unroll
-        for (int h = 0; h < M; ++h) vals[v][h] = point<K, W, M>(tab, 2 + h, sd * M + h, xr, kf);
+        for (int h = 0; h < M; ++h) vals[h] = point<K, W, M>(tab, 2 + h, sd * M + h, xr, kf);
       }
     } else {
 #pragma unroll
@@ -126,21 +131,22 @@ __device__ __forceinline__ void edge_trace(cdp tab, cip itab, const GridScalars&
         if constexpr (W) {
           WCol<K, M> col;
           wcol<K, W, M>(tab, 2 + h, xr, kf, col);
-          vals[v][h] = wpoint<K, W, M>(tab, 2 + h, sd - 2, (sd == 2 ? 2 * M : 3 * M) + h, col);
+          vals[h] = wpoint<K, W, M>(tab, 2 + h, sd - 2, (sd == 2 ? 2 * M : 3 * M) + h, col);
         } else {
-          vals[v][h] = point<K, W, M>(tab, sd - 2, (sd == 2 ? 2 * M : 3 * M) + h, xr, kf);
+          vals[h] = point<K, W, M>(tab, sd - 2, (sd == 2 ? 2 * M : 3 * M) + h, xr, kf);
         }
       }
     }
   }
 #pragma unroll
   for (int h = 0; h < M; ++h) {
-    const int hb = rev ? M - 1 - h : h;
+    const double mine = rev ? vals[M - 1 - h] : vals[h];
+    const double a0 = __shfl(mine, 0, kEdgeLanes), a1 = __shfl(mine, 1, kEdgeLanes), a2 = __shfl(mine, 2, kEdgeLanes);
     cdp cv = tab + O.bt_conv + ((size_t)idx * M + h) * 5;
     double* o = bt + ((size_t)idx * M + h) * 3;
-    o[0] = cv[0] * vals[0][hb];
-    o[1] = cv[1] * vals[1][hb] + cv[2] * vals[2][hb];
-    o[2] = cv[3] * vals[1][hb] + cv[4] * vals[2][hb];
+    if (g == 0) o[0] = cv[0] * a0;
+    if (g == 1) o[1] = cv[1] * a1 + cv[2] * a2;
+    if (g == 2) o[2] = cv[3] * a1 + cv[4] * a2;
   }
 }
 

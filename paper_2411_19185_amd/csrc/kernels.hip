@@ -3,7 +3,8 @@
 //
 //  k_fill_halo     ghost cells g = G q (appendix (7.12)); kHaloLanes lanes per ghost row
 //  k_edge_traces   at every panel-edge Gauss point, the neighbour panel's own
-//                  trace, converted into this panel's variables (3.26)-(3.29)
+//                  trace, converted into this panel's variables (3.26)-(3.29);
+//                  one group of kEdgeLanes lanes per panel-edge cell side
 //  k_stage         fused reconstruction, LMARS, quadrature, sources, tendency
 //                  and Runge-Kutta combination; one marching work item per
 //                  workgroup
@@ -32,9 +33,10 @@ template <int K, bool W, int M>
 __global__ __launch_bounds__(64) void k_edge_traces(const double* __restrict__ tab_, const int32_t* __restrict__ itab_,
                                                      GridScalars gs, const double* __restrict__ q,
                                                      double* __restrict__ bt) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 24 * gs.n) return;
-  edge_trace<K, W, M>((cdp)tab_, (cip)itab_, gs, q, bt, idx);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = t / kEdgeLanes;
+  if (idx >= 24 * gs.n) return;   // the whole lane group leaves together
+  edge_trace<K, W, M>((cdp)tab_, (cip)itab_, gs, q, bt, idx, t % kEdgeLanes);
 }
 
 // ---------------------------------------------------------------------------
@@ -85,7 +87,7 @@ template <int K, bool W, int M>
 static int edge_traces_t(const double* tab, const int32_t* itab, const GridScalars& gs, const double* q, double* bt,
                          void* stream) {
   const int total = 24 * gs.n;
-  hipLaunchKernelGGL((k_edge_traces<K, W, M>), dim3((total + 63) / 64), dim3(64), 0, (hipStream_t)stream, tab,
+  hipLaunchKernelGGL((k_edge_traces<K, W, M>), dim3((total * kEdgeLanes + 63) / 64), dim3(64), 0, (hipStream_t)stream, tab,
                      itab, gs, q, bt);
   return (int)hipGetLastError();
 }
