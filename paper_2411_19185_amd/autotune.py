@@ -42,15 +42,20 @@ def _store(path: str, data: dict):
     os.replace(tmp, path)
 
 
+HALF_STRIP = 30   # strips this narrow run two per workgroup (32 lanes each)
+
+
 def strip_candidates(n: int) -> list[int]:
-    """Strip widths <= 62 that split n into 1..4 more strips than needed,
-    each balanced over the panel."""
-    need = (n + 61) // 62
+    """Strip widths, each balanced over the panel: those <= 62 that split n
+    into 1..4 more strips than needed, and those <= 30 (two strips per
+    workgroup) that split it into 1..3 more than needed at that width."""
     out = []
-    for strips in range(need, need + 4):
-        w = (n + strips - 1) // strips
-        if 1 <= w <= 62 and w not in out:
-            out.append(w)
+    for cap, extra in ((62, 4), (HALF_STRIP, 3)):
+        need = (n + cap - 1) // cap
+        for strips in range(need, need + extra):
+            w = (n + strips - 1) // strips
+            if 1 <= w <= 62 and w not in out:
+                out.append(w)
     return out
 
 

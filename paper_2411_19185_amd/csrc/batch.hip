@@ -126,6 +126,7 @@ __global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu(K
     A.seg_h = bm.seg_h;
     A.n_strips = bm.n_strips;
     A.n_segs = bm.n_segs;
+    A.half = bm.half;
     if (it != (int)blockIdx.x) __syncthreads();   // the previous item's LDS reads are done
     stage_tile<K, W, M>(bm.tab, (cdp)bm.fcoef, bm.gs, A, local, sm);
   }

@@ -61,9 +61,9 @@ int build_items(hope_batch* B) {
   std::vector<It> its;
   for (int i = 0; i < B->n_members; ++i) {
     const BatchMember& bm = B->hmem[i];
-    const int per = 6 * bm.n_strips * bm.n_segs;
+    const int per = stage_items(bm.strip_w, bm.n_strips, bm.n_segs);
     if (per > (1 << 20)) return fail(HOPE_ERR_INVALID, "too many work items in one member");
-    const int64_t cost = (int64_t)(bm.seg_h + 1) * (bm.strip_w + 2);
+    const int64_t cost = (int64_t)(bm.seg_h + 1) * (bm.half ? 64 : bm.strip_w + 2);
     for (int l = 0; l < per; ++l) its.push_back({cost, (int32_t)((i << 20) | l)});
   }
   std::stable_sort(its.begin(), its.end(), [](const It& a, const It& b) { return a.cost > b.cost; });
@@ -157,6 +157,7 @@ int hope_batch_create(const hope_grid* const* grids, int32_t n_members, const do
     bm.n_strips = strips;
     bm.seg_h = std::min(8, n);
     bm.n_segs = (n + bm.seg_h - 1) / bm.seg_h;
+    bm.half = bm.strip_w <= kHalfStrip;
     B->q_off.push_back(qo);
     B->f_off.push_back(fo);
     qo += 18LL * P * P;
@@ -250,6 +251,7 @@ int hope_batch_set_launch(hope_batch* B, const int32_t* strip_w, const int32_t* 
     if (seg_h) bm.seg_h = seg_h[i];
     bm.n_strips = (n + bm.strip_w - 1) / bm.strip_w;
     bm.n_segs = (n + bm.seg_h - 1) / bm.seg_h;
+    bm.half = bm.strip_w <= kHalfStrip;
   }
   B->blocks = blocks;
   int st = upload_members(B);

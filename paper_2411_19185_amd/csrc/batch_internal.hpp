@@ -20,6 +20,7 @@ struct BatchMember {
   int64_t bt_off;           // panel-edge traces [24 n m][3]
   int32_t edge_begin;       // first flattened panel-edge side (multiple of 64)
   int32_t strip_w, seg_h, n_strips, n_segs;
+  int32_t half;             // strip_w <= kHalfStrip: two strips per work item
 };
 
 // The members of one grid, for the ghost fill: rows of that grid's G are

@@ -142,6 +142,16 @@ struct GhostDev {
   int rows;
 };
 
+// Strips of the fused stage of up to 30 columns (32 lanes with the two ring
+// lanes) run two per workgroup, one in each half of its lanes, side by side
+// over the same rows; wider strips take all 64 lanes.  Work items of a stage
+// launch: (pair of strip columns, or strip column) x segment.
+constexpr int kHalfStrip = 30;
+inline int stage_items(int strip_w, int n_strips, int n_segs) {
+  const int cols = 6 * n_strips;
+  return (strip_w <= kHalfStrip ? (cols + 1) / 2 : cols) * n_segs;
+}
+
 // Launchers implemented in kernels.hip.  All enqueue on `stream` and return a
 // hipError_t value (0 on success).
 int launch_fill_halo(const GhostDev& g, double* q, int plane, void* stream);

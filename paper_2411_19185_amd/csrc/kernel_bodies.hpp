@@ -158,7 +158,9 @@ struct StageArgs {
   double ca, cb, cc;
   int out_padded;
   int strip_w, seg_h, n_strips, n_segs;
+  int half;                 // strips of <= kHalfStrip columns: two per workgroup, 32 lanes each
 };
+
 
 // The fused stage runs three wavefronts per work item: in the reconstruction
 // phase wavefront v reconstructs variable v, so that each keeps only one
@@ -168,12 +170,14 @@ constexpr int kStageThreads = 192;
 
 template <int K, bool W, int M>
 struct StageSmem {
-  static constexpr int R = (K - 1) / 2, NR = 2 * R + 1, CW = 64 + 2 * R;
+  // window columns: one strip of up to 64 lanes plus 2R, or two half strips
+  // of 32 lanes plus 2R each
+  static constexpr int R = (K - 1) / 2, NR = 2 * R + 1, CW = 64 + 4 * R;
   // slots of pts: left edge, right edge, bottom edge (M each), then the M x M
   // cell nodes; a row's top traces stay in the registers of the wavefront
   // that computed them until they move to ptop
   static constexpr int PL = 0, PR = M, PB = 2 * M, PI = 3 * M, NP = 3 * M + M * M;
-  double sq[3][NR][CW];     // stencil window: NR padded rows (LDS column c = padded column i0-1+c)
+  double sq[3][NR][CW];     // stencil window: NR padded rows (column c of a strip's part = padded column i0-1+c)
   double pts[3][NP][64];    // the current row's values at the points of every lane's cell
   double ptop[3][M][64];    // top traces of the row below
 };
@@ -193,30 +197,39 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
                                            const StageArgs& A, int item, StageSmem<K, W, M>& sm) {
   using C = Cfg<K, W, M>;
   constexpr int R = C::R, S = C::S, NR = C::NR, XR = C::XR;
-  constexpr int CW = 64 + 2 * R;
-  const cdp tab = (cdp)tab_;
+  constexpr int CW = StageSmem<K, W, M>::CW;       // window columns allocated
+  constexpr int HW = 32 + 2 * R;                   // window columns of a half strip
+  cdp tab = (cdp)tab_;
   const int n = gs.n, P = gs.P;
   const TabOffsets O = tab_offsets(K, W, M, n);
   const size_t plane = (size_t)P * P;
   const size_t vs = 6 * plane;
+  const bool half = A.half != 0;
   const int seg = item % A.n_segs;
-  item /= A.n_segs;
-  const int strip = item % A.n_strips;
-  const int p = item / A.n_strips;
+  const int colpos = item / A.n_segs;              // strip column, or pair of strip columns
+  const int ncols = 6 * A.n_strips;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // this wavefront's variable / role
+  const int grp = half ? lane >> 5 : 0;            // which half strip (0 in full mode)
+  const int gl = half ? lane & 31 : lane;          // lane within the strip
+  // strip column of half g (clamped; the second half of the last pair may be empty)
+  auto col_of = [&](int g) { return min(half ? 2 * colpos + g : colpos, ncols - 1); };
+  const bool live = !half || 2 * colpos + grp < ncols;
+  const int scol = col_of(grp);
+  const int strip = scol % A.n_strips;
+  const int p = scol / A.n_strips;
   const int i0 = strip * A.strip_w;
-  const int i1 = min(n, i0 + A.strip_w);          // owned columns [i0, i1)
-  const int i = i0 - 1 + lane;                     // this lane's column
-  const bool in_strip = (i >= i0 - 1) && (i <= i1);
+  const int i1 = live ? min(n, i0 + A.strip_w) : i0;   // owned columns [i0, i1)
+  const int i = i0 - 1 + gl;                       // this lane's column
+  const bool in_strip = live && (i >= i0 - 1) && (i <= i1);
   const bool real = in_strip && i >= 0 && i < n;   // a cell this lane can reconstruct
   const bool owner = i >= i0 && i < i1;            // a cell whose result this lane writes
+  const int wc = (half ? grp * HW : 0) + gl + R;   // window column of this lane's cell
   const int j0 = seg * A.seg_h;
   const int j1 = min(n, j0 + A.seg_h);
   const double invd = gs.inv_delta;
   const double ia = 1.0 / gs.radius;
-  const double* qp = A.q + p * plane;
   const double* btp = A.bt + (size_t)p * 4 * n * M * 3;
   const int ic = max(0, min(n - 1, i));            // clamped column for table reads
   cdp Xg = tab + O.Xg, sqg = tab + O.sqg, Xe = tab + O.Xe, sqe = tab + O.sqe, gw = tab + C::O.gw;
@@ -228,8 +241,13 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     for (int k = 0; k < PER; ++k) {
       const int idx = tid + kStageThreads * k;
       const int v = idx / CW, c = idx % CW;
-      const int gc = i0 - 1 + c;
-      buf[k] = (idx < 3 * CW && pr >= 0 && pr < P && gc >= 0 && gc < P) ? qp[v * vs + (size_t)pr * P + gc] : 0.0;
+      const int g = half ? c / HW : 0, cc = half ? c % HW : c;
+      const int sc = col_of(g);
+      const int gc = (sc % A.n_strips) * A.strip_w - 1 + cc;
+      const bool used = half ? g < 2 : c < 64 + 2 * R;
+      buf[k] = (idx < 3 * CW && used && pr >= 0 && pr < P && gc >= 0 && gc < P)
+                   ? A.q[(sc / A.n_strips) * plane + v * vs + (size_t)pr * P + gc]
+                   : 0.0;
     }
   };
   auto store = [&](int pr, const double* buf) {
@@ -242,7 +260,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
   };
   // stencil of this wavefront's variable at offset (dy, dx) of the lane's cell in interior row pc
   auto win = [&](int pc) {
-    return [&, pc](int dy, int dx) -> double { return sm.sq[wv][(pc + R + dy) % NR][lane + R + dx]; };
+    return [&, pc](int dy, int dx) -> double { return sm.sq[wv][(pc + R + dy) % NR][wc + dx]; };
   };
   // WENO weights kappa_j of this wavefront's variable in row pc
   auto kappa = [&](int pc, double* kap) {
@@ -366,7 +384,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
   auto xflux = [&](int j) {
     const int ie = max(0, min(n, i));
     const double Xei = tab[O.Xe + ie], sqxe = tab[O.sqe + ie];
-    const bool xdead = !(in_strip && i >= 0 && i <= n && lane >= 1);
+    const bool xdead = !(in_strip && i >= 0 && i <= n && gl >= 1);
     const int ll = max(lane - 1, 0);
     double fl[3] = {0.0, 0.0, 0.0};
 #pragma unroll 1
@@ -464,7 +482,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     const int jr = j - 1;
     const size_t o_in = wv * vs + p * plane + (size_t)(jr + R) * P + (i + R);
     const double qn_c = (fin && A.qn) ? A.qn[o_in] : 0.0;
-    const double qs_c = fin ? sm.sq[wv][(jr + R) % NR][lane + R] : 0.0;
+    const double qs_c = fin ? sm.sq[wv][(jr + R) % NR][wc] : 0.0;
     if (wv == 1) yflux(j);
     if (!last) {
       if (wv == 0) xflux(j);

@@ -7,7 +7,7 @@
 //                  one group of kEdgeLanes lanes per panel-edge cell side
 //  k_stage         fused reconstruction, LMARS, quadrature, sources, tendency
 //                  and Runge-Kutta combination; one marching work item per
-//                  workgroup
+//                  workgroup (a strip, or two strips of <= 30 columns)
 //  k_combine       out = a x + b y + c z (the Runge-Kutta adjoint)
 #include <hip/hip_runtime.h>
 
@@ -94,7 +94,7 @@ static int edge_traces_t(const double* tab, const int32_t* itab, const GridScala
 
 template <int K, bool W, int M>
 static int stage_t(const double* tab, const GridScalars& gs, const StageArgs& a, void* stream) {
-  const int items = 6 * a.n_strips * a.n_segs;
+  const int items = stage_items(a.strip_w, a.n_strips, a.n_segs);
   hipLaunchKernelGGL((k_stage<K, W, M>), dim3(items), dim3(kStageThreads), 0, (hipStream_t)stream, tab, gs, a);
   return (int)hipGetLastError();
 }
@@ -141,6 +141,7 @@ int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const 
   a.seg_h = seg_h;
   a.n_strips = (gs.n + strip_w - 1) / strip_w;
   a.n_segs = (gs.n + seg_h - 1) / seg_h;
+  a.half = strip_w <= kHalfStrip;
   HOPE_DISPATCH(stage_t, tab, gs, a, stream);
 }
 
