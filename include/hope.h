@@ -158,10 +158,12 @@ int hope_rk_step_vjp(const hope_grid* grid, double* q, double dt, int32_t scheme
 /* Message for the last error on this thread ("" if none). */
 const char* hope_last_error(void);
 
-/* Launch shape of the fused stage kernel: each wavefront owns a strip of
- * strip_w <= 62 interior columns of one panel and marches over seg_h rows.
- * Any values in range give identical results; they only change speed (the
- * autotuner picks them per grid).  Returns HOPE_ERR_INVALID out of range. */
+/* Launch shape of the fused stage kernel: each workgroup (three wavefronts,
+ * one per variable) owns a strip of strip_w <= 62 interior columns of one
+ * panel and marches over seg_h rows; strips of strip_w <= 30 columns run two
+ * per workgroup, one in each half of its lanes.  Any values in range give
+ * bitwise identical results; they only change speed (the autotuner picks
+ * them per grid).  Returns HOPE_ERR_INVALID out of range. */
 int hope_grid_set_launch(hope_grid* grid, int32_t strip_w, int32_t seg_h);
 int hope_grid_get_launch(const hope_grid* grid, int32_t* strip_w, int32_t* seg_h);
 
