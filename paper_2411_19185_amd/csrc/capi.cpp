@@ -93,12 +93,19 @@ static void default_launch(hope_grid* G) {
   const int n = G->h.n;
   int sw, strips;
   balanced_strip(n, &sw, &strips);
+  // half strips (<= kHalfStrip columns, 32 lanes each) when they leave fewer
+  // lanes idle than full strips (64 lanes each)
+  const int hs = (n + kHalfStrip - 1) / kHalfStrip, hw = (n + hs - 1) / hs;
+  if (sw > kHalfStrip && 32L * hs < 64L * strips) {
+    sw = hw;
+    strips = hs;
+  }
   G->strip_w = sw;
   // the tallest segments (fewest re-reconstructed boundary rows) that still
   // give about 1.4 work items per workgroup slot of the chip (256 CUs x 4
   // resident workgroups of the order-5 stage)
   int h = 12;
-  while (h > 2 && 6L * strips * ((n + h - 1) / h) < 1400) --h;
+  while (h > 2 && stage_items(sw, strips, (n + h - 1) / h) < 1400) --h;
   G->seg_h = h;
 }
 
