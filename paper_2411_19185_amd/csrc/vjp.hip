@@ -4,11 +4,11 @@
 // forward evaluation:
 //   k_vjp_traces    recompute every cell's values at its edge and cell Gauss
 //                   points (the forward reconstruction) into scratch T
-//   k_vjp_points    per cell, the cotangent of each of its point values: the
-//                   adjoint of the LMARS flux (3.30)-(3.38) through each edge
-//                   point it feeds (flux cotangent from the tendency (3.1)
-//                   and the quadrature (3.5)), and of the sources (2.2)-(2.3)
-//                   at its cell points (3.6)
+//   k_vjp_points    the cotangent of every point value: per cell edge, the
+//                   adjoint of the LMARS flux (3.30)-(3.38) at its Gauss
+//                   points (flux cotangent from the tendency (3.1) and the
+//                   quadrature (3.5)) for the traces on both sides; per cell,
+//                   that of the sources (2.2)-(2.3) at its nodes (3.6)
 //   k_vjp_edges     adds, at every panel-edge point, the adjoint of the
 //                   neighbour panel's own flux with respect to the converted
 //                   trace, taken back through the transposed conversion
@@ -201,72 +201,82 @@ __device__ __forceinline__ void outside_state(cdp tab, cip itab, const TabOffset
 }
 
 // ---------------------------------------------------------------------------
-// k_vjp_points: Lam[(pt*3 + v)*cells + c] = dL/d(point value)
+// k_vjp_points: Lam[(pt*3 + v)*cells + c] = dL/d(point value).  Lanes
+// [0, 12 n (n+1)) take one cell edge each (panel p, direction, position):
+// the flux adjoint at its m Gauss points gives the cotangents of both
+// traces, written to the edge points of the cells on either side (a panel
+// edge's outside trace belongs to the neighbour panel and is handled by
+// k_vjp_edges).  Each point slot has exactly one writer.  The remaining
+// 6 n^2 lanes take one cell each: the source adjoint at its m^2 nodes.
 // ---------------------------------------------------------------------------
 template <int K, bool W, int M>
 __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ tab_, const int32_t* __restrict__ itab_,
                                                     GridScalars gs, const double* __restrict__ T,
                                                     const double* __restrict__ w, double* __restrict__ Lam) {
   using C = Cfg<K, W, M>;
-  constexpr int NP = 4 * M + M * M;
   const cdp tab = (cdp)tab_;
   const cip itab = (cip)itab_;
   const int n = gs.n, P = gs.P;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= 6 * n * n) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int edges = 12 * n * (n + 1);
+  if (t >= edges + 6 * n * n) return;
   const TabOffsets O = tab_offsets(K, W, M, n);
-  const int p = c / (n * n), j = (c / n) % n, i = c % n;
   const double invd = gs.inv_delta, ia = 1.0 / gs.radius;
   const size_t nn = (size_t)n * n;
-  auto wv = [&](int v, int cc) -> double { return w[(size_t)v * 6 * nn + cc]; };
   const size_t cells = (size_t)6 * n * n;
-  auto own = [&](int pt, int v) -> double { return T[((size_t)pt * 3 + v) * cells + c]; };
-  auto lam = [&](int pt, int v) -> double& { return Lam[((size_t)pt * 3 + v) * cells + c]; };
+  auto wv = [&](int v, int cc) -> double { return w[(size_t)v * 6 * nn + cc]; };
+  auto tr = [&](int pt, int v, int cc) -> double { return T[((size_t)pt * 3 + v) * cells + cc]; };
+  auto lam = [&](int pt, int v, int cc) -> double& { return Lam[((size_t)pt * 3 + v) * cells + cc]; };
   cdp Xg = tab + O.Xg, sqg = tab + O.sqg, Xe = tab + O.Xe, sqe = tab + O.sqe, gw = tab + C::O.gw;
-#pragma unroll 1
-  for (int sd = 0; sd < 4; ++sd) {
-    // neighbour inside the panel, flux cotangent factor
-    const int ni = i + (sd == 0 ? -1 : sd == 1 ? 1 : 0);
-    const int nj = j + (sd == 2 ? -1 : sd == 3 ? 1 : 0);
-    const bool inside = ni >= 0 && ni < n && nj >= 0 && nj < n;
-    const int nc = (p * n + nj) * n + ni;
-    const int osd = sd ^ 1;                    // facing side of the neighbour
-    const bool own_is_right = (sd == 0 || sd == 2);
+  if (t < edges) {
+    const int per = (n + 1) * n;
+    const int pd = t / per, loc = t % per;
+    const int p = pd >> 1, dir = pd & 1;
+    // x edge e between cells (e-1, a) and (e, a); y edge e between (a, e-1) and (a, e)
+    const int e = dir == 0 ? loc % (n + 1) : loc / n;
+    const int a = dir == 0 ? loc / (n + 1) : loc % n;
+    const bool inL = e > 0, inR = e < n;
+    const int cL = dir == 0 ? (p * n + a) * n + (e - 1) : (p * n + (e - 1)) * n + a;
+    const int cR = dir == 0 ? (p * n + a) * n + e : (p * n + e) * n + a;
+    const int sdL = dir == 0 ? 1 : 3, sdR = dir == 0 ? 0 : 2;   // the edge's side in each cell
+    // the flux through the edge adds +F/D to the right (top) cell and -F/D to the other
     double dF[3];
 #pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      const double wc = wv(v, c);
-      const double wn = inside ? wv(v, nc) : 0.0;
-      // flux through this edge adds +F/D to the cell on its right/top and -F/D to the other
-      dF[v] = own_is_right ? (wc - wn) * invd : (wn - wc) * invd;
-    }
-    const int dir = sd < 2 ? 0 : 1;
-    const int e = sd == 0 ? i : sd == 1 ? i + 1 : sd == 2 ? j : j + 1;
+    for (int v = 0; v < 3; ++v) dF[v] = ((inR ? wv(v, cR) : 0.0) - (inL ? wv(v, cL) : 0.0)) * invd;
 #pragma unroll
     for (int h = 0; h < M; ++h) {
-      double qo[3], qn[3];
+      double qL[3], qR[3];
+      cdp cv;
+      int bc, bp;
+      if (inL) {
 #pragma unroll
-      for (int v = 0; v < 3; ++v) qo[v] = own(sd * M + h, v);
-      if (inside) {
-#pragma unroll
-        for (int v = 0; v < 3; ++v) qn[v] = T[((size_t)(osd * M + h) * 3 + v) * cells + nc];
+        for (int v = 0; v < 3; ++v) qL[v] = tr(sdL * M + h, v, cL);
       } else {
-        cdp cv;
-        int bc, bp;
-        outside_state<M>(tab, itab, O, n, P, gs.r, T, p, sd, dir == 0 ? j : i, h, qn, &cv, &bc, &bp);
+        outside_state<M>(tab, itab, O, n, P, gs.r, T, p, sdR, a, h, qL, &cv, &bc, &bp);
+      }
+      if (inR) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) qR[v] = tr(sdR * M + h, v, cR);
+      } else {
+        outside_state<M>(tab, itab, O, n, P, gs.r, T, p, sdL, a, h, qR, &cv, &bc, &bp);
       }
       double X, Y, sx, sy;
-      if (dir == 0) { X = Xe[e]; sx = sqe[e]; Y = Xg[j * M + h]; sy = sqg[j * M + h]; }
-      else { X = Xg[i * M + h]; sx = sqg[i * M + h]; Y = Xe[e]; sy = sqe[e]; }
+      if (dir == 0) { X = Xe[e]; sx = sqe[e]; Y = Xg[a * M + h]; sy = sqg[a * M + h]; }
+      else { X = Xg[a * M + h]; sx = sqg[a * M + h]; Y = Xe[e]; sy = sqe[e]; }
       double mu[3] = {gw[h] * dF[0], gw[h] * dF[1], gw[h] * dF[2]};
       double bL[3] = {0, 0, 0}, bR[3] = {0, 0, 0};
-      if (own_is_right) lmars_adj(qn, qo, X, Y, sx, sy, dir, ia, mu, bL, bR);
-      else lmars_adj(qo, qn, X, Y, sx, sy, dir, ia, mu, bL, bR);
+      lmars_adj(qL, qR, X, Y, sx, sy, dir, ia, mu, bL, bR);
 #pragma unroll
-      for (int v = 0; v < 3; ++v) lam(sd * M + h, v) = own_is_right ? bR[v] : bL[v];
+      for (int v = 0; v < 3; ++v) {
+        if (inL) lam(sdL * M + h, v, cL) = bL[v];
+        if (inR) lam(sdR * M + h, v, cR) = bR[v];
+      }
     }
+    return;
   }
   // sources at the cell Gauss points
+  const int c = t - edges;
+  const int p = c / (n * n), j = (c / n) % n, i = c % n;
   cdp fc = tab + C::O.fcoef + p * 3;
 #pragma unroll
   for (int vv = 0; vv < M; ++vv)
@@ -276,10 +286,10 @@ __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ ta
       const double X = Xg[i * M + h], Y = Xg[j * M + vv];
       const double g2 = gw[h] * gw[vv];
       double Qb[3] = {0, 0, 0};
-      sources_adj(own(pt, 0), own(pt, 1), own(pt, 2), X, Y, fc[0] + fc[1] * X + fc[2] * Y,
+      sources_adj(tr(pt, 0, c), tr(pt, 1, c), tr(pt, 2, c), X, Y, fc[0] + fc[1] * X + fc[2] * Y,
                   gs.omega2, g2 * wv(1, c), g2 * wv(2, c), Qb);
 #pragma unroll
-      for (int v = 0; v < 3; ++v) lam(pt, v) = Qb[v];
+      for (int v = 0; v < 3; ++v) lam(pt, v, c) = Qb[v];
     }
 }
 
@@ -781,8 +791,8 @@ static int vjp_t(const VjpArgs& a, int step, void* stream) {
       hipLaunchKernelGGL((k_vjp_traces<K, W, M>), dim3((cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q, a.T);
       break;
     case kVjpPoints:
-      hipLaunchKernelGGL((k_vjp_points<K, W, M>), dim3((cells + 63) / 64), dim3(64), 0, s, a.tab, a.itab, gs, a.T,
-                         a.w, a.Lam);
+      hipLaunchKernelGGL((k_vjp_points<K, W, M>), dim3((12 * n * (n + 1) + cells + 63) / 64), dim3(64), 0, s, a.tab,
+                         a.itab, gs, a.T, a.w, a.Lam);
       break;
     case kVjpEdges: {
       const int ept = 24 * n * M;
