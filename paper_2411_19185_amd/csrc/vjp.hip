@@ -112,7 +112,7 @@ template <int M>
 __device__ __forceinline__ int side_pt(int sd, int h) { return sd * M + h; }
 
 // ---------------------------------------------------------------------------
-// k_vjp_traces: T[(pt*3 + v)*cells + c] (struct of arrays: lanes of
+// k_vjp_traces: T[(pt*3 + v)*cells + c], one lane per (variable, cell) (struct of arrays: lanes of
 // neighbouring cells touch neighbouring addresses)
 // ---------------------------------------------------------------------------
 template <int K, bool W, int M>
@@ -122,20 +122,21 @@ __global__ __launch_bounds__(64) void k_vjp_traces(const double* __restrict__ ta
   constexpr int NP = 4 * M + M * M;
   const cdp tab = (cdp)tab_;
   const int n = gs.n, P = gs.P;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= 6 * n * n) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 18 * n * n) return;
+  const int cells_i = 6 * n * n;
+  const int v = idx / cells_i, c = idx % cells_i;   // one lane per (variable, cell)
   const int p = c / (n * n), j = (c / n) % n, i = c % n;
   const size_t vs = (size_t)6 * P * P;
   const double* c0 = q + (size_t)p * P * P + (size_t)(j + C::R) * P + (i + C::R);
-  const size_t cells = (size_t)6 * n * n;
+  const size_t cells = (size_t)cells_i;
   double* out = T + c;
   // the lane's stencil of one variable, staged in LDS: all its loads are
   // issued together instead of one by one inside the arithmetic
   constexpr bool kStage = K * K * 64 * 8 <= 32768;
   __shared__ double st[kStage ? K * K : 1][64];
   const int lane = threadIdx.x;
-#pragma unroll 1
-  for (int v = 0; v < 3; ++v) {
+  {
     if constexpr (kStage) {
 #pragma unroll
       for (int o = 0; o < K * K; ++o) st[o][lane] = c0[v * vs + (o / K - C::R) * P + (o % K - C::R)];
@@ -788,7 +789,7 @@ static int vjp_t(const VjpArgs& a, int step, void* stream) {
   const int cells = 6 * n * n;
   switch (step) {
     case kVjpTraces:
-      hipLaunchKernelGGL((k_vjp_traces<K, W, M>), dim3((cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q, a.T);
+      hipLaunchKernelGGL((k_vjp_traces<K, W, M>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q, a.T);
       break;
     case kVjpPoints:
       hipLaunchKernelGGL((k_vjp_points<K, W, M>), dim3((12 * n * (n + 1) + cells + 63) / 64), dim3(64), 0, s, a.tab,
