@@ -362,10 +362,9 @@ def ensemble(args):
             ens.member_grid(i)
         torch.cuda.synchronize()
         ev[0].record(stream)
-        for i in range(len(ns)):
-            gr = ens.member_loss_gradient(i, q0s[i], dts[i], vjp_steps, checkpoint_every=5)
-            grads_finite = grads_finite and bool(torch.isfinite(gr).all())
+        grads = ens.member_loss_gradients(q0s, dts, vjp_steps, checkpoint_every=5, streams=args.vjp_streams)
         ev[1].record(stream)
+        grads_finite = all(bool(torch.isfinite(gr).all()) for gr in grads)
         torch.cuda.synchronize()
         vjp_ms = ev[0].elapsed_time(ev[1])
     return {"value": cells * 3 / (batch_ms / 1e3), "unit": "cell-tendency evals/s",
@@ -378,7 +377,8 @@ def ensemble(args):
                            "value": (cells * 3 * vjp_steps / (vjp_ms / 1e3)) if vjp_ms else None,
                            "unit": "cell-tendency evals/s (fwd+VJP)", "grads_finite": grads_finite,
                            "loss": "0.5 ||q_T||^2 per member; each member's checkpointed rollout and step "
-                                   "adjoints on its own derived grid, members looped"},
+                                   "adjoints on its own derived grid, members spread over "
+                                   f"{args.vjp_streams} HIP streams"},
             "launches_per_step": 9,
             "note": "batched: one captured graph per step (9 kernel launches over all members); looped: "
                     "hope_rk_step per member on its resolution's grid (timing only)"}
@@ -501,6 +501,7 @@ def main():
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--ensemble-steps", type=int, default=50)
     ap.add_argument("--no-ensemble-vjp", dest="ensemble_vjp", action="store_false")
+    ap.add_argument("--vjp-streams", type=int, default=8, help="HIP streams for the per-member adjoints")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy (counter scale)")
     ap.add_argument("--vjp-reps", type=int, default=10)
     ap.add_argument("--rollout-steps", type=int, default=20)

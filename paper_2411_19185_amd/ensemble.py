@@ -33,6 +33,7 @@ class Ensemble:
         self.grids = list(grids)       # the grids must outlive the batch
         self.axis_tilt = list(axis_tilt) if axis_tilt is not None else None
         self._member_grids: dict[int, Grid] = {}
+        self._private_grids: dict[int, Grid] = {}
         arr = (ctypes.c_void_p * n)(*[g._h.value for g in grids])
         tilt = (ctypes.c_double * n)(*axis_tilt) if axis_tilt is not None else None
         h = ctypes.c_void_p()
@@ -145,6 +146,44 @@ class Ensemble:
         qT = rollout(self.member_grid(i), q, dt, steps, checkpoint_every, scheme)
         (0.5 * (qT * qT).sum()).backward()
         return q.grad
+
+    def member_loss_gradients(self, q0s: list[torch.Tensor], dts: list[float], steps: int,
+                              checkpoint_every: int = 5, scheme: str = "ssp3",
+                              streams: int = 4) -> list[torch.Tensor]:
+        """member_loss_gradient for every member, with the members spread over
+        ``streams`` HIP streams (default priority) so that the launches of
+        small members overlap on the GPU.  Each member runs on a grid handle of
+        its own (its panel-edge trace scratch is private), and each stream on
+        its own workspaces; results equal the one-by-one ones bitwise."""
+        from .autograd import rollout
+        n = self.n_members
+        if len(q0s) != n or len(dts) != n:
+            raise ValueError("one initial state and one time step per member")
+        handles = []
+        for i in range(n):
+            if self.axis_tilt is not None:
+                handles.append(self.member_grid(i))
+            else:
+                if i not in self._private_grids:
+                    self._private_grids[i] = self.grids[i].derive(self.grids[i].desc.axis_tilt)
+                handles.append(self._private_grids[i])
+        main = torch.cuda.current_stream()
+        pool = [torch.cuda.Stream() for _ in range(max(1, int(streams)))]
+        for st in pool:
+            st.wait_stream(main)
+        grads = []
+        for i in range(n):
+            st = pool[i % len(pool)]
+            with torch.cuda.stream(st):
+                q = q0s[i].detach().clone().requires_grad_(True)
+                qT = rollout(handles[i], q, dts[i], steps, checkpoint_every, scheme)
+                (0.5 * (qT * qT).sum()).backward()
+                grads.append(q.grad)
+        for st in pool:
+            main.wait_stream(st)
+        for gr in grads:
+            gr.record_stream(main)
+        return grads
 
     # ------------------------------------------------------------------
     def set_launch(self, strip_w: list[int] | None = None, seg_h: list[int] | None = None, blocks: int = 0):

@@ -194,3 +194,29 @@ def test_derived_member_grid_equals_a_fresh_grid_and_member_gradient():
     err = rel_err(grad, qq.grad)
     print("member gradient rel err", err, flush=True)
     assert max(err) < TOL, err
+
+
+@pytest.mark.parametrize("tilted", [True, False])
+def test_member_gradients_on_streams_equal_one_by_one(tilted):
+    """Per-member loss gradients computed concurrently on several HIP streams
+    equal bitwise those computed one member after another (members with and
+    without their own axis tilt, two sharing one grid)."""
+    from paper_2411_19185_amd.ensemble import Ensemble
+    ns = [10, 12, 10]
+    print("case member gradients on streams", tilted, flush=True)
+    shared = {n: _grid(n, 5, "weno") for n in sorted(set(ns))}
+    tilts, states = [], []
+    for i, n in enumerate(ns):
+        alpha, q = STATES["perturbed_member"](n, 700 + i, nq=2)
+        tilts.append(alpha)
+        states.append(q)
+    ens = Ensemble([shared[n] for n in ns], axis_tilt=tilts if tilted else None)
+    q0s = [q.cuda() for q in states]
+    dts = [cfl_dt(q) for q in states]
+    conc = ens.member_loss_gradients(q0s, dts, 2, checkpoint_every=1, streams=3)
+    torch.cuda.synchronize()
+    for i in range(len(ns)):
+        one = ens.member_loss_gradient(i, q0s[i], dts[i], 2, checkpoint_every=1)
+        torch.cuda.synchronize()
+        same = torch.equal(conc[i], one)
+        assert same, (i, rel_err(conc[i], one))
