@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_fill_halo_batch(const BatchGrid* __rest
   const int b = g.ptr[r], e = g.ptr[r + 1];
   const int d = g.dst[r];
   const int info = g.info[r];
-  const double* cv = g.cval + (info & 0x0fffffff);
+  const GhostVal* cv = g.cval + (info & 0x0fffffff);
   for (int c0 = 0; c0 < bg.member_count; c0 += kHaloChunk) {
     const int cnt = min(kHaloChunk, bg.member_count - c0);
     double* qm[kHaloChunk];
@@ -47,13 +47,14 @@ __global__ __launch_bounds__(256) void k_fill_halo_batch(const BatchGrid* __rest
 #pragma unroll
     for (int t = 0; t < kHaloChunk; ++t) acc[t][0] = acc[t][1] = acc[t][2] = 0.0;
     for (int k = b + lane; k < e; k += kHaloLanes) {
-      const int c = g.col[k];
-      const int ce = g.ce[k];
-      const int j = ce & 0x1fff, f = ce >> 13;
-      const double v0 = cv[j];
+      const GhostEnt en = g.ent[k];
+      const int c = en.col;
+      const int j = en.ce & 0x1fff, f = en.ce >> 13;
+      const GhostVal cj = cv[j];
+      const double v0 = cj.v[0];
       double w1, w2, w3, w4;   // the block rows acting on the cell's own frame
-      frame_apply(f, cv[g.cnnz + j], cv[2 * g.cnnz + j], w1, w2);
-      frame_apply(f, cv[3 * g.cnnz + j], cv[4 * g.cnnz + j], w3, w4);
+      frame_apply(f, cj.v[1], cj.v[2], w1, w2);
+      frame_apply(f, cj.v[3], cj.v[4], w3, w4);
 #pragma unroll
       for (int t = 0; t < kHaloChunk; ++t) {
         if (t < cnt) {

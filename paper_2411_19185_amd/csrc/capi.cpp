@@ -198,12 +198,15 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
   int e1 = upload(G, h.z_dst, &g.dst);
   if (!e1) e1 = upload(G, h.z_info, &g.info);
   if (!e1) e1 = upload(G, h.z_ptr, &g.ptr);
-  if (!e1) e1 = upload(G, h.z_col, &g.col);
-  if (!e1) e1 = upload(G, h.z_ce, &g.ce);
-  if (!e1) e1 = upload(G, h.z_cval, &g.cval);
+  const int32_t* ent = nullptr;
+  const double* cval = nullptr;
+  if (!e1) e1 = upload(G, h.z_ent, &ent);
+  if (!e1) e1 = upload(G, h.z_cval, &cval);
+  g.ent = reinterpret_cast<const GhostEnt*>(ent);       // device allocations are 256-byte aligned
+  g.cval = reinterpret_cast<const GhostVal*>(cval);
   if (e1) { free_grid(G); return e1; }
-  g.nnz = (int64_t)h.z_col.size();
-  g.cnnz = (int64_t)(h.z_cval.size() / 5);
+  g.nnz = (int64_t)(h.z_ent.size() / 2);
+  g.cnnz = (int64_t)(h.z_cval.size() / 6);
   g.rows = (int)h.z_dst.size();
   {
     // transpose of G, rows by interior cell (CSR over the cells it reads)
@@ -258,8 +261,7 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
   std::vector<int32_t>().swap(h.z_dst);
   std::vector<int32_t>().swap(h.z_info);
   std::vector<int32_t>().swap(h.z_ptr);
-  std::vector<int32_t>().swap(h.z_col);
-  std::vector<uint16_t>().swap(h.z_ce);
+  std::vector<int32_t>().swap(h.z_ent);
   std::vector<double>().swap(h.z_cval);
   std::vector<double>().swap(h.bt_conv);
   *out = G;

@@ -46,9 +46,10 @@ struct HostTables {
   std::vector<int32_t> z_dst;          // padded offset of the row's ghost
   std::vector<int32_t> z_info;         // start of its canonical row in z_cval | (output frame code << 28)
   std::vector<int32_t> z_ptr;          // row pointers
-  std::vector<int32_t> z_col;          // padded offset of the interior cell read (ascending in a row)
-  std::vector<uint16_t> z_ce;          // entry within the canonical row | (frame code of the cell's panel << 13)
-  std::vector<double> z_cval;          // 5 x canonical nnz: mass, C11, C12, C21, C22 (SoA)
+  std::vector<int32_t> z_ent;          // per entry: padded offset of the interior cell read (ascending in a
+                                       // row), then entry within the canonical row | (frame code of the
+                                       // cell's panel << 13)
+  std::vector<double> z_cval;          // per canonical entry: mass, C11, C12, C21, C22, 0 (48 bytes)
   // panel-edge traces: for (panel A, side, t, h): the neighbour cell and point
   std::vector<int32_t> bt_cell;        // 6*4*n: padded offset of B's cell centre
   std::vector<int32_t> bt_side;        // 6*4*n: which side of B's cell (0 L,1 R,2 B,3 T)
@@ -130,13 +131,19 @@ struct GridScalars {
 // image of panel coordinates (X, Y) is (sx * (sw ? Y : X), sy * (sw ? X : Y))
 // with sw = f & 1, sx = -1 if f & 2, sy = -1 if f & 4; contravariant momentum
 // components map the same way.
+struct alignas(8) GhostEnt {
+  int32_t col;           // padded offset of the interior cell read
+  int32_t ce;            // entry within the canonical row | (frame code << 13)
+};
+struct alignas(16) GhostVal {
+  double v[6];           // mass, C11, C12, C21, C22, padding
+};
 struct GhostDev {
   const int32_t* dst;
   const int32_t* info;
   const int32_t* ptr;
-  const int32_t* col;
-  const uint16_t* ce;
-  const double* cval;    // 5 x cnnz
+  const GhostEnt* ent;
+  const GhostVal* cval;
   int64_t nnz;           // entries of all rows
   int64_t cnnz;          // entries of the canonical rows
   int rows;

@@ -760,12 +760,12 @@ int compress_ghost_map(HostTables& t) {
     t.error = "canonical ghost map too large";
     return HOPE_ERR_UNSUPPORTED;
   }
-  t.z_cval.resize(5 * cnnz);
-  for (int comp = 0; comp < 5; ++comp) std::copy(cval[comp].begin(), cval[comp].end(), t.z_cval.begin() + comp * cnnz);
+  t.z_cval.assign(6 * cnnz, 0.0);
+  for (size_t e = 0; e < cnnz; ++e)
+    for (int comp = 0; comp < 5; ++comp) t.z_cval[6 * e + comp] = cval[comp][e];
   t.z_dst.clear();
   t.z_info.clear();
-  t.z_col.clear();
-  t.z_ce.clear();
+  t.z_ent.clear();
   t.z_ptr.assign(1, 0);
   const int L = n + r, kXcdChunks = 8;
   std::vector<int> order(G);
@@ -780,10 +780,10 @@ int compress_ghost_map(HostTables& t) {
     t.z_dst.push_back(t.g_dst[g]);
     t.z_info.push_back(canon_start[row_canon[g]] | (row_code[g] << 28));
     for (const E& x : rows[g]) {
-      t.z_col.push_back(x.col);
-      t.z_ce.push_back((uint16_t)(x.canon | (x.code << 13)));
+      t.z_ent.push_back(x.col);
+      t.z_ent.push_back(x.canon | (x.code << 13));
     }
-    t.z_ptr.push_back((int32_t)t.z_col.size());
+    t.z_ptr.push_back((int32_t)(t.z_ent.size() / 2));
   }
   return 0;
 }

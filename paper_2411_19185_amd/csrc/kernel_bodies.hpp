@@ -58,18 +58,19 @@ constexpr int kHaloLanes = HOPE_HALO_LANES;
 __device__ __forceinline__ void halo_row(const GhostDev& g, double* __restrict__ q, size_t plane, int row, int lane) {
   const int b = g.ptr[row], e = g.ptr[row + 1];
   const int info = g.info[row];
-  const double* cv = g.cval + (info & 0x0fffffff);
+  const GhostVal* cv = g.cval + (info & 0x0fffffff);
   const double* q1 = q + plane;
   const double* q2 = q + 2 * (size_t)plane;
   double mass = 0, mu = 0, mv = 0;
   for (int k = b + lane; k < e; k += kHaloLanes) {
-    const int c = g.col[k];
-    const int ce = g.ce[k];
-    const int j = ce & 0x1fff, f = ce >> 13;
+    const GhostEnt en = g.ent[k];
+    const int c = en.col;
+    const int j = en.ce & 0x1fff, f = en.ce >> 13;
+    const GhostVal cj = cv[j];
     double w1, w2, w3, w4;
-    frame_apply(f, cv[g.cnnz + j], cv[2 * g.cnnz + j], w1, w2);
-    frame_apply(f, cv[3 * g.cnnz + j], cv[4 * g.cnnz + j], w3, w4);
-    mass = fma(cv[j], q[c], mass);
+    frame_apply(f, cj.v[1], cj.v[2], w1, w2);
+    frame_apply(f, cj.v[3], cj.v[4], w3, w4);
+    mass = fma(cj.v[0], q[c], mass);
     mu = fma(w1, q1[c], fma(w2, q2[c], mu));
     mv = fma(w3, q1[c], fma(w4, q2[c], mv));
   }
