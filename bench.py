@@ -360,6 +360,8 @@ def ensemble(args):
         q0s = [torch.from_numpy(q).cuda() for q in states]
         for i in range(len(ns)):          # derived member grids, made before timing
             ens.member_grid(i)
+        # untimed warm-up (one step): the streams' workspaces are allocated here
+        ens.member_loss_gradients(q0s, dts, 1, checkpoint_every=5, streams=args.vjp_streams)
         torch.cuda.synchronize()
         ev[0].record(stream)
         grads = ens.member_loss_gradients(q0s, dts, vjp_steps, checkpoint_every=5, streams=args.vjp_streams)
@@ -437,6 +439,11 @@ def adjoint(g, n, args, dt):
         g.rk_step(qt, dt, "ssp3", rws)
     h_target = (g.interior(qt)[0] * hscale).contiguous()
     del qt, rws, qp, ws, dq, gq
+    # untimed warm-up: one checkpoint segment forward and backward, so that the
+    # timed run does not include the first device allocation of its workspaces
+    qw = q0.clone().requires_grad_(True)
+    (0.5 * (autograd.rollout(g, qw, dt, min(steps, every), checkpoint_every=every) ** 2).sum()).backward()
+    del qw
     torch.cuda.synchronize()
     torch.cuda.reset_peak_memory_stats()
     base_mem = torch.cuda.memory_allocated()

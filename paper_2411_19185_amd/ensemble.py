@@ -34,6 +34,7 @@ class Ensemble:
         self.axis_tilt = list(axis_tilt) if axis_tilt is not None else None
         self._member_grids: dict[int, Grid] = {}
         self._private_grids: dict[int, Grid] = {}
+        self._streams: list = []
         arr = (ctypes.c_void_p * n)(*[g._h.value for g in grids])
         tilt = (ctypes.c_double * n)(*axis_tilt) if axis_tilt is not None else None
         h = ctypes.c_void_p()
@@ -168,7 +169,11 @@ class Ensemble:
                     self._private_grids[i] = self.grids[i].derive(self.grids[i].desc.axis_tilt)
                 handles.append(self._private_grids[i])
         main = torch.cuda.current_stream()
-        pool = [torch.cuda.Stream() for _ in range(max(1, int(streams)))]
+        # the pool persists across calls, so that the caching allocator's
+        # per-stream blocks are reused
+        while len(self._streams) < max(1, int(streams)):
+            self._streams.append(torch.cuda.Stream())
+        pool = self._streams[:max(1, int(streams))]
         for st in pool:
             st.wait_stream(main)
         grads = []
