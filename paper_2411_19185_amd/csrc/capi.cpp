@@ -220,15 +220,29 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
     for (int32_t col : h.g_col) cnt[cell_of(col) + 1]++;
     for (int c = 0; c < cells; ++c) cnt[c + 1] += cnt[c];
     const size_t nnz = h.g_col.size();
-    std::vector<int32_t> rows(nnz), fill(cnt.begin(), cnt.end() - 1);
-    std::vector<double> vals(5 * nnz);
-    for (size_t gr = 0; gr + 1 < h.g_ptr.size(); ++gr)
+    std::vector<int32_t> rows(nnz), refs(nnz), fill(cnt.begin(), cnt.end() - 1);
+    // each entry refers to the canonical value record of its G entry and
+    // carries the two frame codes (the device rows hold the same entries in
+    // the same column order)
+    std::vector<int32_t> zrow(6 * (size_t)P * P, -1);
+    for (size_t zr = 0; zr < h.z_dst.size(); ++zr) zrow[h.z_dst[zr]] = (int32_t)zr;
+    for (size_t gr = 0; gr + 1 < h.g_ptr.size(); ++gr) {
+      const int zr = zrow[h.g_dst[gr]];
+      const int32_t info = h.z_info[zr], zb = h.z_ptr[zr];
       for (int32_t k = h.g_ptr[gr]; k < h.g_ptr[gr + 1]; ++k) {
-        const int c = cell_of(h.g_col[k]);
+        const int32_t col = h.z_ent[2 * (zb + (k - h.g_ptr[gr]))];
+        const int32_t ce = h.z_ent[2 * (zb + (k - h.g_ptr[gr])) + 1];
+        const int32_t rec = (info & 0x0fffffff) + (ce & 0x1fff);
+        if (col != h.g_col[k] || rec >= (1 << 24)) {
+          free_grid(G);
+          return fail(HOPE_ERR_NUMERIC, "ghost map transpose: inconsistent rows");
+        }
+        const int c = cell_of(col);
         const int32_t pos = fill[c]++;
         rows[pos] = h.g_dst[gr];
-        for (int comp = 0; comp < 5; ++comp) vals[comp * nnz + pos] = h.g_val[comp * nnz + k];
+        refs[pos] = rec | ((ce >> 13) << 24) | ((info >> 28) << 27);
       }
+    }
     // keep only the cells some ghost row reads
     std::vector<int32_t> cptr(1, 0), ccell;
     for (int c = 0; c < cells; ++c)
@@ -240,7 +254,7 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
     int e2 = upload(G, cptr, &G->gt_ptr);
     if (!e2) e2 = upload(G, ccell, &G->gt_cell);
     if (!e2) e2 = upload(G, rows, &G->gt_row);
-    if (!e2) e2 = upload(G, vals, &G->gt_val);
+    if (!e2) e2 = upload(G, refs, &G->gt_ref);
     if (e2) { free_grid(G); return e2; }
     G->gt_nnz = (int64_t)nnz;
   }
@@ -289,7 +303,7 @@ int hope_grid_derive(const hope_grid* base, double axis_tilt, hope_grid** out) {
   G->gt_cell = base->gt_cell;
   G->gt_ptr = base->gt_ptr;
   G->gt_row = base->gt_row;
-  G->gt_val = base->gt_val;
+  G->gt_ref = base->gt_ref;
   G->gt_nnz = base->gt_nnz;
   G->strip_w = base->strip_w;
   G->seg_h = base->seg_h;
@@ -423,7 +437,8 @@ int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq
   a.gt_cell = G->gt_cell;
   a.gt_ptr = G->gt_ptr;
   a.gt_row = G->gt_row;
-  a.gt_val = G->gt_val;
+  a.gt_ref = G->gt_ref;
+  a.gcval = G->g.cval;
   a.gt_nnz = G->gt_nnz;
   for (int step = 0; step < kVjpSteps; ++step) {
     Timed tm(G, 3 + step, stream);

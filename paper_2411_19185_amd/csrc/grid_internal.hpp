@@ -24,7 +24,7 @@ struct hope_grid {
   const int32_t* gt_cell = nullptr;
   const int32_t* gt_ptr = nullptr;
   const int32_t* gt_row = nullptr;
-  const double* gt_val = nullptr;
+  const int32_t* gt_ref = nullptr;   // canonical value record and frame codes of each entry
   int64_t gt_nnz = 0;
   // optional per-kernel timing with HIP events on the launch stream
   bool timing = false;

@@ -745,11 +745,22 @@ __global__ __launch_bounds__(256) void k_vjp_interior(int n, int P, int r, const
 // ---------------------------------------------------------------------------
 // k_vjp_ghost_t: gq += G^T (ghost cotangents), 16 lanes per interior cell
 // that some ghost row reads (the only rows of G^T with entries)
+// (c1, c2) -> T (c1, c2) for a frame code of the compressed ghost map: the
+// image of panel coordinates (X, Y) is (sx (sw ? Y : X), sy (sw ? X : Y)),
+// sw = f & 1, sx = -1 if f & 2, sy = -1 if f & 4
+__device__ __forceinline__ void frame_apply_t(int f, double c1, double c2, double& g1, double& g2) {
+  const bool sw = f & 1;
+  const double sx = (f & 2) ? -1.0 : 1.0, sy = (f & 4) ? -1.0 : 1.0;
+  g1 = sx * (sw ? c2 : c1);
+  g2 = sy * (sw ? c1 : c2);
+}
+
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_vjp_ghost_t(int rows, int n, int P, const int32_t* __restrict__ gt_cell,
                                                      const int32_t* __restrict__ gt_ptr,
                                                      const int32_t* __restrict__ gt_row,
-                                                     const double* __restrict__ gt_val, int64_t gnnz,
+                                                     const int32_t* __restrict__ gt_ref,
+                                                     const GhostVal* __restrict__ gcval,
                                                      const double* __restrict__ gpad, double* __restrict__ gq) {
   const int row = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 4);
   if (row >= rows) return;   // whole 16-lane group leaves together
@@ -759,9 +770,19 @@ __global__ __launch_bounds__(256) void k_vjp_ghost_t(int rows, int n, int P, con
   for (int k = gt_ptr[row] + lane; k < gt_ptr[row + 1]; k += 16) {
     const int d = gt_row[k];
     const double a0 = gpad[d], a1 = gpad[plane + d], a2 = gpad[2 * plane + d];
-    g0 = fma(gt_val[k], a0, g0);
-    g1 = fma(gt_val[gnnz + k], a1, fma(gt_val[3 * gnnz + k], a2, g1));
-    g2 = fma(gt_val[2 * gnnz + k], a1, fma(gt_val[4 * gnnz + k], a2, g2));
+    // the G entry's momentum block T(f0) C T(f)^T from its canonical record
+    // (signed permutations: exact, the values G applied in the forward fill)
+    const int ref = gt_ref[k];
+    const GhostVal cj = gcval[ref & 0xffffff];
+    const int f = (ref >> 24) & 7, f0 = (ref >> 27) & 7;
+    double m11, m12, m21, m22, b11, b12, b21, b22;
+    frame_apply_t(f, cj.v[1], cj.v[2], m11, m12);
+    frame_apply_t(f, cj.v[3], cj.v[4], m21, m22);
+    frame_apply_t(f0, m11, m21, b11, b21);
+    frame_apply_t(f0, m12, m22, b12, b22);
+    g0 = fma(cj.v[0], a0, g0);
+    g1 = fma(b11, a1, fma(b21, a2, g1));
+    g2 = fma(b12, a1, fma(b22, a2, g2));
   }
 #pragma unroll
   for (int off = 8; off > 0; off >>= 1) {
@@ -819,7 +840,7 @@ static int vjp_t(const VjpArgs& a, int step, void* stream) {
       hipLaunchKernelGGL(k_vjp_interior, dim3((cells + 255) / 256), dim3(256), 0, s, n, P, gs.r, a.gpad, a.gq);
       if (a.gt_rows > 0)
         hipLaunchKernelGGL(k_vjp_ghost_t, dim3((unsigned)(((size_t)a.gt_rows * 16 + 255) / 256)), dim3(256), 0, s,
-                           a.gt_rows, n, P, a.gt_cell, a.gt_ptr, a.gt_row, a.gt_val, a.gt_nnz, a.gpad, a.gq);
+                           a.gt_rows, n, P, a.gt_cell, a.gt_ptr, a.gt_row, a.gt_ref, a.gcval, a.gpad, a.gq);
       break;
     default:
       return (int)hipErrorInvalidValue;

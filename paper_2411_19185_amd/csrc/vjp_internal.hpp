@@ -22,7 +22,9 @@ struct VjpArgs {
   const int32_t* gt_cell;  // the interior cell of each row
   const int32_t* gt_ptr;   // rows + 1
   const int32_t* gt_row;   // padded offset (in one variable plane) of the ghost cell
-  const double* gt_val;    // 5 x nnz, same component order as G
+  const int32_t* gt_ref;   // per entry: canonical value record | (frame code of the cell << 24)
+                           // | (frame code of the ghost << 27), see GhostDev
+  const GhostVal* gcval;   // canonical value records of the ghost map
   int64_t gt_nnz;
 };
 // the adjoint's kernels in launch order
