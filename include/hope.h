@@ -73,7 +73,10 @@ typedef struct hope_grid_desc {
                             TPP (3.7)-(3.15): 3,5,7,9,11,13; WENO (3.16)-(3.25): 3,5 */
   int32_t scheme;        /* HOPE_SCHEME_TPP or HOPE_SCHEME_WENO */
   int32_t n_gauss;       /* Gauss points per edge (3.5); 0 or (order+1)/2 */
-  int32_t reserved0;
+  int32_t ghost_iters;   /* ghost map (7.12): 0 = the exact fixed point of the
+                            ghost interpolation (section 3.3.1); N in 1..300 =
+                            the map of N Jacobi sweeps from g = 0 (the paper
+                            uses 10) */
   double radius;         /* sphere radius a in m (default 6.371e6) */
   double gravity;        /* g in m/s^2 (default 9.80616), informational */
   double omega;          /* rotation rate Omega in 1/s (default 7.292e-5) */

@@ -34,7 +34,7 @@ class GridDesc(ctypes.Structure):
         ("order", ctypes.c_int32),
         ("scheme", ctypes.c_int32),
         ("n_gauss", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("ghost_iters", ctypes.c_int32),
         ("radius", ctypes.c_double),
         ("gravity", ctypes.c_double),
         ("omega", ctypes.c_double),
@@ -136,7 +136,7 @@ def check(code: int):
 
 
 def make_desc(n, order, scheme="tpp", radius=6.371e6, omega=7.292e-5, axis_tilt=0.0, weno_eps=1e-12,
-              split_theta=3.0, gravity=9.80616) -> GridDesc:
+              split_theta=3.0, gravity=9.80616, ghost_iters=0) -> GridDesc:
     d = GridDesc()
     d.struct_size = ctypes.sizeof(GridDesc)
     d.n = n
@@ -149,13 +149,15 @@ def make_desc(n, order, scheme="tpp", radius=6.371e6, omega=7.292e-5, axis_tilt=
     d.axis_tilt = axis_tilt
     d.weno_eps = weno_eps
     d.split_theta = split_theta
+    d.ghost_iters = ghost_iters
     return d
 
 
-def inspect_ghost_map(n, order, scheme="tpp", radius=6.371e6):
-    """The ghost map the library builds, as numpy arrays (host only)."""
+def inspect_ghost_map(n, order, scheme="tpp", radius=6.371e6, ghost_iters=0):
+    """The ghost map the library builds, as numpy arrays (host only);
+    ghost_iters = 0 gives the fixed point, N > 0 the map of N Jacobi sweeps."""
     import numpy as np
-    d = make_desc(n, order, scheme, radius)
+    d = make_desc(n, order, scheme, radius, ghost_iters=ghost_iters)
     rows, nnz, sweeps = ctypes.c_int64(), ctypes.c_int64(), _I32()
     check(lib().hope_inspect_ghost_map(ctypes.byref(d), ctypes.byref(rows), ctypes.byref(nnz),
                                        ctypes.byref(sweeps), None, None, None, None))

@@ -125,6 +125,8 @@ static int validate(const hope_grid_desc* desc) {
   if (n < k || n > 4096) return fail(HOPE_ERR_UNSUPPORTED, "n must satisfy order <= n <= 4096");
   if (!(desc->radius >= 0) || !std::isfinite(desc->axis_tilt) || !(desc->weno_eps >= 0))
     return fail(HOPE_ERR_INVALID, "bad physical parameter");
+  if (desc->ghost_iters < 0 || desc->ghost_iters > 300)
+    return fail(HOPE_ERR_INVALID, "ghost_iters must be 0 (fixed point) or 1..300 sweeps");
   return HOPE_OK;
 }
 
@@ -142,7 +144,7 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
   if (!G) return fail(HOPE_ERR_NOMEM, "host allocation");
   int st = 0;
   try {
-    st = build_tables(G->h, n, k, weno, radius, omega, desc->axis_tilt, eps, theta);
+    st = build_tables(G->h, n, k, weno, radius, omega, desc->axis_tilt, eps, theta, desc->ghost_iters);
   } catch (const std::bad_alloc&) {
     free_grid(G);
     return fail(HOPE_ERR_NOMEM, "host allocation while building tables");
@@ -578,7 +580,7 @@ int hope_inspect_ghost_map(const hope_grid_desc* desc, int64_t* rows, int64_t* n
   const int k = desc->order, n = desc->n;
   HostTables h;
   const double radius = desc->radius > 0 ? desc->radius : 6.371e6;
-  int st = build_tables(h, n, k, desc->scheme, radius, 7.292e-5, 0.0, 1e-12, 3.0);
+  int st = build_tables(h, n, k, desc->scheme, radius, 7.292e-5, 0.0, 1e-12, 3.0, desc->ghost_iters);
   if (st) return fail(st, h.error);
   *rows = (int64_t)h.g_dst.size();
   *nnz = (int64_t)h.g_col.size();

@@ -62,8 +62,9 @@ struct HostTables {
 void coriolis_coefs(double tilt, double* out);
 
 // Builds every table; returns 0 on success, else a HOPE_ERR code with error set.
+// ghost_iters: 0 for the fixed-point ghost map, N > 0 for N Jacobi sweeps from 0.
 int build_tables(HostTables& t, int n, int k, int weno, double radius, double omega, double tilt,
-                 double eps, double theta);
+                 double eps, double theta, int ghost_iters = 0);
 
 // ---------------------------------------------------------------------------
 // All constant tables of a grid live in one FP64 buffer (and one int32

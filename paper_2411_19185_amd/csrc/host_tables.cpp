@@ -349,7 +349,11 @@ struct Entry {
   double v[5];
 };
 
-int build_ghost_map(HostTables& t) {
+// iters = 0: the fixed point G = Lq + Lg G of the ghost interpolation, by
+// Gauss-Seidel sweeps over sparse rows until converged; iters = N > 0: the
+// map of exactly N Jacobi sweeps from g = 0 (G_1 = Lq, G_{s+1} = Lq + Lg G_s),
+// the truncated map the paper builds with its 10 sweeps
+int build_ghost_map(HostTables& t, int iters) {
   const int n = t.n, k = t.k, r = t.r, P = t.P, m = t.m;
   const ld D = kPi / (2 * (ld)n);
   std::vector<ld> gx, gwt;
@@ -435,7 +439,14 @@ int build_ghost_map(HostTables& t) {
   std::vector<int32_t> touched;
   std::vector<char> mark(plane, 0);
   int sweeps = 0, settle = -1;
+  const bool jacobi = iters > 0;
+  std::vector<std::vector<Entry>> prev;   // the previous sweep's rows (Jacobi)
   for (; sweeps < 300; ++sweeps) {
+    if (jacobi) {
+      if (sweeps + 1 >= iters) break;     // G_1 = Lq is the first sweep
+      prev = Gm;
+    }
+    const std::vector<std::vector<Entry>>& src = jacobi ? prev : Gm;
     double maxrel = 0;
     for (int g = 0; g < G; ++g) {
       touched.clear();
@@ -446,7 +457,7 @@ int build_ghost_map(HostTables& t) {
       for (const Entry& e : Lq[g]) add(e.col, e.v);
       for (const Entry& ref : Lg[g]) {
         const double* c = ref.v;
-        for (const Entry& e : Gm[ref.col]) {
+        for (const Entry& e : src[ref.col]) {
           double v[5];
           v[0] = c[0] * e.v[0];
           v[1] = c[1] * e.v[1] + c[2] * e.v[3];
@@ -494,17 +505,18 @@ int build_ghost_map(HostTables& t) {
       maxrel = std::max(maxrel, diff / (rowmax > 0 ? rowmax : 1));
       Gm[g].swap(row);
     }
+    if (jacobi) continue;
     if (settle < 0 && maxrel < 1e-15) settle = 2;
     if (settle >= 0) {
       if (settle == 0) { ++sweeps; break; }
       --settle;
     }
   }
-  if (settle != 0 && sweeps >= 300) {
+  if (!jacobi && settle != 0 && sweeps >= 300) {
     t.error = "ghost map fixed point did not converge";
     return HOPE_ERR_NUMERIC;
   }
-  t.ghost_sweeps = sweeps;
+  t.ghost_sweeps = jacobi ? iters : sweeps;
   // final drop: entries below 1e-16 of the row's largest entry
   t.g_dst.assign(dst.begin(), dst.end());
   t.g_ptr.assign(G + 1, 0);
@@ -858,7 +870,7 @@ int build_edge_maps(HostTables& t) {
 }  // namespace
 
 int build_tables(HostTables& t, int n, int k, int weno, double radius, double omega, double tilt,
-                 double eps, double theta) {
+                 double eps, double theta, int ghost_iters) {
   t.n = n;
   t.k = k;
   t.r = (k - 1) / 2;
@@ -968,7 +980,7 @@ int build_tables(HostTables& t, int n, int k, int weno, double radius, double om
     }
   t.fcoef.resize(18);
   coriolis_coefs(tilt, t.fcoef.data());
-  int st = build_ghost_map(t);
+  int st = build_ghost_map(t, ghost_iters);
   if (!st) st = compress_ghost_map(t);
   if (st) return st;
   return build_edge_maps(t);

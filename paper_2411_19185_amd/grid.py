@@ -23,8 +23,9 @@ class Grid:
 
     def __init__(self, n: int, order: int, scheme: str = "tpp", radius: float = 6.371e6,
                  omega: float = 7.292e-5, axis_tilt: float = 0.0, weno_eps: float = 1e-12,
-                 split_theta: float = 3.0):
-        self.desc = make_desc(n, order, scheme, radius, omega, axis_tilt, weno_eps, split_theta)
+                 split_theta: float = 3.0, ghost_iters: int = 0):
+        self.desc = make_desc(n, order, scheme, radius, omega, axis_tilt, weno_eps, split_theta,
+                              ghost_iters=ghost_iters)
         h = ctypes.c_void_p()
         check(lib().hope_grid_create(ctypes.byref(self.desc), ctypes.byref(h)))
         self._h = h
@@ -43,7 +44,7 @@ class Grid:
         check(lib().hope_grid_derive(self._h, float(axis_tilt), ctypes.byref(h)))
         g = Grid.__new__(Grid)
         g.desc = make_desc(self.n, self.order, self.scheme, self.desc.radius, self.desc.omega, axis_tilt,
-                           self.desc.weno_eps, self.desc.split_theta)
+                           self.desc.weno_eps, self.desc.split_theta, ghost_iters=self.desc.ghost_iters)
         g._h = h
         g._base = self
         lay = Layout()

@@ -61,6 +61,26 @@ def test_halo_matches_oracle_fixed_point(n, order, scheme, state, seed):
     assert max(rel_err(qp, ref)) < 1e-13
 
 
+@pytest.mark.parametrize("n,order,scheme,state,seed,iters", [(30, 3, "tpp", "member", 14, 10),
+                                                             (16, 5, "weno", "dam_break", 15, 10),
+                                                             (12, 5, "tpp", "member", 16, 2)])
+def test_tendency_with_fixed_ghost_sweeps_matches_oracle(n, order, scheme, state, seed, iters):
+    """A grid built with ghost_iters = N fills its ghosts with the map of N
+    Jacobi sweeps from zero; its tendency equals the oracle's with the same
+    fixed sweep count."""
+    from paper_2411_19185_amd import Grid
+    print(f"case n={n} order={order} {scheme} {state} sweeps={iters}", flush=True)
+    alpha, q = STATES[state](n, seed)
+    og = oracle_grid(n, order, scheme, alpha)
+    ref = og.tendency(q, ghost_sweeps=iters)
+    g = Grid(n, order, scheme, axis_tilt=alpha, ghost_iters=iters)
+    out = g.tendency(to_padded(q, g.r))
+    torch.cuda.synchronize()
+    err = rel_err(out, ref)
+    print("rel err", err, flush=True)
+    assert max(err) < TOL, err
+
+
 @pytest.mark.parametrize("sw,sh", [(5, 3), (62, 30), (17, 1), (30, 7)])
 def test_launch_shape_does_not_change_results(sw, sh):
     n, order, scheme = 30, 5, "weno"

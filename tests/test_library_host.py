@@ -39,8 +39,8 @@ def test_create_rejects_bad_struct_size():
     assert lib().hope_grid_create(None, ctypes.byref(h)) == -1
 
 
-def _apply_library_ghost_map(n, k, q):
-    dst, ptr, col, val, sweeps = inspect_ghost_map(n, k)
+def _apply_library_ghost_map(n, k, q, ghost_iters=0):
+    dst, ptr, col, val, sweeps = inspect_ghost_map(n, k, ghost_iters=ghost_iters)
     r = (k - 1) // 2
     P = n + 2 * r
     qp = np.zeros((3, 6 * P * P))
@@ -65,6 +65,31 @@ def test_library_ghost_map_equals_oracle_fixed_point(n, k):
     for v in range(3):
         assert np.abs(a[v] - b[v]).max() / np.abs(b[v]).max() < 1e-14
     assert sweeps < 40
+
+
+@pytest.mark.parametrize("n,k,iters", [(8, 5, 1), (8, 5, 2), (13, 5, 10), (10, 7, 10), (9, 3, 4)])
+def test_library_ghost_map_of_fixed_sweeps_equals_oracle(n, k, iters):
+    """With ghost_iters = N the library's map is that of exactly N Jacobi
+    sweeps from g = 0 (the fixed sweep count of section 3.3.1's iteration):
+    it reproduces the oracle's N-sweep fill, and for small N it differs
+    measurably from the fixed point, so the count is really honoured."""
+    q = np.random.default_rng(n * 37 + k + iters).uniform(0.5, 1.5, (3, 6, n, n))
+    a, sweeps = _apply_library_ghost_map(n, k, q, ghost_iters=iters)
+    assert sweeps == iters
+    b = GhostMap(n, k, 6.371e6).fill(torch.tensor(q), sweeps=iters).numpy()
+    for v in range(3):
+        assert np.abs(a[v] - b[v]).max() / np.abs(b[v]).max() < 1e-14
+    if iters <= 2:
+        c = GhostMap(n, k, 6.371e6).fill(torch.tensor(q)).numpy()
+        assert np.abs(a - c).max() > 1e-8
+
+
+@pytest.mark.parametrize("iters", [-1, 301])
+def test_create_rejects_bad_ghost_iters(iters):
+    d = make_desc(12, 5, ghost_iters=iters)
+    h = ctypes.c_void_p()
+    assert lib().hope_grid_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert "ghost_iters" in lib().hope_last_error().decode()
 
 
 def test_batch_create_rejects_bad_arguments():
