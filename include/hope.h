@@ -36,7 +36,8 @@
  * status; a thread-local message is available from hope_last_error().
  * Argument and launch errors are reported synchronously; faults inside a
  * kernel surface at the caller's next synchronisation of the stream.  No call
- * except hope_grid_create / hope_grid_destroy synchronises the device.
+ * except hope_grid_create / hope_grid_destroy synchronises the device, and
+ * hope_check_state, which waits for its stream.
  *
  * Streams are passed as void* holding a hipStream_t (NULL = null stream).
  */
@@ -56,7 +57,8 @@ enum {
   HOPE_ERR_UNSUPPORTED = -2, /* order/scheme/n combination not built */
   HOPE_ERR_HIP = -3,         /* a HIP runtime call failed */
   HOPE_ERR_NOMEM = -4,       /* device or host allocation failed in create */
-  HOPE_ERR_NUMERIC = -5      /* ghost-map construction did not converge, or its rows
+  HOPE_ERR_NUMERIC = -5      /* hope_check_state found a bad cell; or the
+                                ghost-map construction did not converge, or its rows
                                 are not images of each other under the cube's rotations */
 };
 
@@ -124,6 +126,17 @@ int hope_grid_layout(const hope_grid* grid, hope_layout* out);
  * momentum rows are 2x2 blocks (the conversion (3.29) at each ghost Gauss
  * point).  Interior cells are read only. */
 int hope_fill_halo(const hope_grid* grid, double* q, void* stream);
+
+/* State check for a run that may have left the shallow-water system's
+ * domain: counts the interior cells of the padded state q whose layer
+ * thickness sqrtG*phi (variable 0, section 2) is not a positive finite
+ * number, or whose momentum (variables 1, 2) is not finite.  Ghost rings are
+ * not read.  The count goes to *n_bad (host memory, may be NULL).  Waits for
+ * the work queued on the stream before it, so call it between steps, not
+ * inside a captured graph.  It uses a counter in the grid's scratch, like
+ * the forward calls.  Returns HOPE_ERR_NUMERIC when the count is not zero,
+ * else HOPE_OK. */
+int hope_check_state(const hope_grid* grid, const double* q, int64_t* n_bad, void* stream);
 
 /* Tendency dq/dt of (3.1): fills the ghost rings of q (they are scratch),
  * then for every interior cell reconstructs to the edge and cell Gauss

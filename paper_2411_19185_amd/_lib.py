@@ -17,6 +17,7 @@ LIB_PATH = os.environ.get("HOPE_LIB") or os.path.join(HERE, "libhope.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "hope.h")
 
 HOPE_OK = 0
+HOPE_ERR_NUMERIC = -5
 HOPE_SCHEME_TPP, HOPE_SCHEME_WENO = 0, 1
 HOPE_RK_SSP3, HOPE_RK_WS3 = 0, 1
 
@@ -84,6 +85,7 @@ _SIGS = {
     "hope_grid_derive": (_I32, [_P, ctypes.c_double, ctypes.POINTER(_P)]),
     "hope_grid_layout": (_I32, [_P, ctypes.POINTER(Layout)]),
     "hope_fill_halo": (_I32, [_P, _P, _P]),
+    "hope_check_state": (_I32, [_P, _P, ctypes.POINTER(ctypes.c_int64), _P]),
     "hope_tendency": (_I32, [_P, _P, _P, _P]),
     "hope_tendency_vjp": (_I32, [_P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "hope_rk_step": (_I32, [_P, _P, ctypes.c_double, _I32, _P, ctypes.c_size_t, _P]),

@@ -53,15 +53,19 @@ class _RkStep(torch.autograd.Function):
 
 class _Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, q0, grid, dt, steps, every, scheme):
+    def forward(ctx, q0, grid, dt, steps, every, scheme, check_state):
         ctx.grid, ctx.dt, ctx.steps, ctx.every, ctx.scheme = grid, dt, steps, every, scheme
         qp = _padded(grid, q0)
         ws = grid.workspace()
         checkpoints = []
         for s in range(steps):
             if s % every == 0:
+                if check_state and s > 0:
+                    _raise_if_bad(grid, qp, s)
                 checkpoints.append(grid.interior(qp).clone())
             grid.rk_step(qp, dt, scheme, ws)
+        if check_state:
+            _raise_if_bad(grid, qp, steps)
         ctx.checkpoints = checkpoints
         return grid.interior(qp).contiguous()
 
@@ -87,7 +91,14 @@ class _Rollout(torch.autograd.Function):
                 cot, nxt = nxt, cot
             del states
         ctx.checkpoints = None
-        return cot, None, None, None, None, None
+        return cot, None, None, None, None, None, None
+
+
+def _raise_if_bad(grid: Grid, qp: torch.Tensor, step: int):
+    bad = grid.bad_cells(qp)
+    if bad:
+        raise FloatingPointError(f"after step {step}: {bad} cells with a thickness that is not positive "
+                                 "or a variable that is not finite")
 
 
 def tendency(grid: Grid, q: torch.Tensor) -> torch.Tensor:
@@ -101,9 +112,12 @@ def rk_step(grid: Grid, q: torch.Tensor, dt: float, scheme: str = "ssp3") -> tor
 
 
 def rollout(grid: Grid, q0: torch.Tensor, dt: float, steps: int, checkpoint_every: int = 5,
-            scheme: str = "ssp3") -> torch.Tensor:
+            scheme: str = "ssp3", check_state: bool = False) -> torch.Tensor:
     """The state after ``steps`` Runge-Kutta steps from q0, differentiable with
-    checkpoints every ``checkpoint_every`` steps."""
+    checkpoints every ``checkpoint_every`` steps.  With ``check_state`` the
+    state is checked at every checkpoint and at the end, and a thickness that
+    is not positive or a variable that is not finite raises
+    FloatingPointError naming the step (each check waits for the stream)."""
     if steps < 1 or checkpoint_every < 1:
         raise ValueError("steps and checkpoint_every must be positive")
-    return _Rollout.apply(q0, grid, float(dt), int(steps), int(checkpoint_every), scheme)
+    return _Rollout.apply(q0, grid, float(dt), int(steps), int(checkpoint_every), scheme, bool(check_state))

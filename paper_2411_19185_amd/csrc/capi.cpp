@@ -62,6 +62,21 @@ struct Timed {
 };
 }  // namespace
 
+// The grid's scratch: panel-edge traces (24 n m x 3 doubles), then the
+// counter of hope_check_state.
+static int alloc_scratch(hope_grid* G) {
+  const size_t traces = 24 * (size_t)G->h.n * G->h.m * 3;
+  const size_t bytes = sizeof(double) * traces + 256;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc (grid scratch)");
+  G->allocs.push_back(p);
+  G->device_bytes += bytes;
+  G->bt = static_cast<double*>(p);
+  G->bad = reinterpret_cast<unsigned long long*>(G->bt + traces);
+  return 0;
+}
+
 template <typename T>
 static int upload(hope_grid* G, const std::vector<T>& v, const T** out) {
   *out = nullptr;
@@ -260,13 +275,10 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
     if (e2) { free_grid(G); return e2; }
     G->gt_nnz = (int64_t)nnz;
   }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, sizeof(double) * 24 * (size_t)n * h.m * 3);
-  if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipMalloc (edge traces)"); }
-  G->allocs.push_back(p);
-  G->device_bytes += sizeof(double) * 24 * (size_t)n * h.m * 3;
-  G->bt = static_cast<double*>(p);
+  int e3 = alloc_scratch(G);
+  if (e3) { free_grid(G); return e3; }
   default_launch(G);
+  hipError_t e;
   e = hipDeviceSynchronize();
   if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipDeviceSynchronize"); }
   // the device holds the ghost map and edge maps now; drop the host copies
@@ -320,12 +332,7 @@ int hope_grid_derive(const hope_grid* base, double axis_tilt, hope_grid** out) {
     e = hipMemcpy(static_cast<double*>(p) + O.fcoef, h.fcoef.data(), 18 * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipMemcpy (derived tables)"); }
   G->tab = static_cast<const double*>(p);
-  p = nullptr;
-  e = hipMalloc(&p, sizeof(double) * 24 * (size_t)h.n * h.m * 3);
-  if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipMalloc (edge traces)"); }
-  G->allocs.push_back(p);
-  G->device_bytes += sizeof(double) * 24 * (size_t)h.n * h.m * 3;
-  G->bt = static_cast<double*>(p);
+  if (int e3 = alloc_scratch(G)) { free_grid(G); return e3; }
   e = hipDeviceSynchronize();
   if (e != hipSuccess) { free_grid(G); return hip_fail(e, "hipDeviceSynchronize"); }
   *out = G;
@@ -376,6 +383,25 @@ int hope_fill_halo(const hope_grid* G, double* q, void* stream) {
   Timed tm(G, 0, stream);
   int e = launch_fill_halo(G->g, q, 6 * G->h.P * G->h.P, stream);
   if (e) return hip_fail((hipError_t)e, "fill_halo launch");
+  return HOPE_OK;
+}
+
+int hope_check_state(const hope_grid* G, const double* q, int64_t* n_bad, void* stream) {
+  if (n_bad) *n_bad = 0;
+  if (!G || !q) return fail(HOPE_ERR_INVALID, "null argument");
+  if (reinterpret_cast<uintptr_t>(q) % 8) return fail(HOPE_ERR_INVALID, "misaligned state");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemsetAsync(G->bad, 0, sizeof(unsigned long long), s);
+  if (e != hipSuccess) return hip_fail(e, "check_state clear");
+  int le = launch_check_state(q, G->h.n, G->h.r, G->bad, stream);
+  if (le) return hip_fail((hipError_t)le, "check_state launch");
+  unsigned long long count = 0;
+  e = hipMemcpyAsync(&count, G->bad, sizeof(count), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "check_state read");
+  if (n_bad) *n_bad = (int64_t)count;
+  if (count) return fail(HOPE_ERR_NUMERIC, std::to_string(count) + " cells with a thickness that is not positive "
+                                            "or a variable that is not finite");
   return HOPE_OK;
 }
 

@@ -163,6 +163,9 @@ inline int stage_items(int strip_w, int n_strips, int n_segs) {
 // Launchers implemented in kernels.hip.  All enqueue on `stream` and return a
 // hipError_t value (0 on success).
 int launch_fill_halo(const GhostDev& g, double* q, int plane, void* stream);
+// bad[0] += number of interior cells of the padded state q with variable 0 not
+// positive and finite, or variables 1, 2 not finite; bad must be zeroed before
+int launch_check_state(const double* q, int n, int r, unsigned long long* bad, void* stream);
 int launch_combine(size_t len, double* out, const double* x, const double* y, const double* z, double a, double b,
                    double c, void* stream);
 int launch_edge_traces(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs,

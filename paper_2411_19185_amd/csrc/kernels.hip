@@ -9,7 +9,12 @@
 //                  and Runge-Kutta combination; one marching work item per
 //                  workgroup (a strip, or two strips of <= 30 columns)
 //  k_combine       out = a x + b y + c z (the Runge-Kutta adjoint)
+//  k_check_state   count of interior cells with a thickness that is not positive
+//                  or a variable that is not finite
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
 
 #include "kernel_bodies.hpp"
 
@@ -72,8 +77,34 @@ int launch_combine(size_t len, double* out, const double* x, const double* y, co
 }
 
 // ---------------------------------------------------------------------------
+// Count of interior cells outside the system's domain (see launch_check_state)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_check_state(const double* __restrict__ q, int n, int r,
+                                                      unsigned long long* __restrict__ bad) {
+  const int P = n + 2 * r;
+  const size_t nn = (size_t)n * n, cells = 6 * nn, plane = 6 * (size_t)P * P;
+  unsigned long long cnt = 0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (size_t)gridDim.x * blockDim.x) {
+    const size_t f = c / nn, rem = c - f * nn;
+    const size_t j = rem / n, i = rem - j * n;
+    const size_t o = (f * P + j + r) * P + i + r;
+    const double h = q[o], mu = q[o + plane], mv = q[o + 2 * plane];
+    const bool ok = h > 0.0 && h <= DBL_MAX && fabs(mu) <= DBL_MAX && fabs(mv) <= DBL_MAX;
+    cnt += ok ? 0 : 1;
+  }
+  if (cnt) atomicAdd(bad, cnt);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+int launch_check_state(const double* q, int n, int r, unsigned long long* bad, void* stream) {
+  const size_t cells = 6 * (size_t)n * n;
+  const int blocks = (int)std::min<size_t>((cells + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_check_state, dim3(blocks), dim3(256), 0, (hipStream_t)stream, q, n, r, bad);
+  return (int)hipGetLastError();
+}
+
 int launch_fill_halo(const GhostDev& g, double* q, int plane, void* stream) {
   if (g.rows == 0) return 0;
   const int threads = 256;

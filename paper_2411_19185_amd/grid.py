@@ -6,7 +6,7 @@ import ctypes
 
 import torch
 
-from ._lib import (HOPE_RK_SSP3, HOPE_RK_WS3, Layout, check, lib, make_desc)
+from ._lib import (HOPE_ERR_NUMERIC, HOPE_OK, HOPE_RK_SSP3, HOPE_RK_WS3, Layout, check, lib, make_desc)
 
 
 def _stream() -> ctypes.c_void_p:
@@ -68,7 +68,7 @@ class Grid:
         r, n = self.r, self.n
         return q[:, :, r:r + n, r:r + n]
 
-    def _check_state(self, q):
+    def _check_padded(self, q):
         if not (q.is_cuda and q.dtype == torch.float64 and q.is_contiguous()
                 and tuple(q.shape) == (3, 6, self.P, self.P)):
             raise ValueError(f"state must be a contiguous cuda float64 tensor of shape (3, 6, {self.P}, {self.P})")
@@ -79,13 +79,24 @@ class Grid:
             raise ValueError(f"field must be a contiguous cuda float64 tensor of shape (3, 6, {self.n}, {self.n})")
 
     # ------------------------------------------------------------------
+    def bad_cells(self, q: torch.Tensor) -> int:
+        """Number of interior cells of the padded state q whose thickness is
+        not positive or whose variables are not finite (waits for the
+        current stream)."""
+        self._check_padded(q)
+        n_bad = ctypes.c_int64()
+        code = lib().hope_check_state(self._h, _ptr(q), ctypes.byref(n_bad), _stream())
+        if code not in (HOPE_OK, HOPE_ERR_NUMERIC):
+            check(code)
+        return n_bad.value
+
     def fill_halo(self, q: torch.Tensor) -> torch.Tensor:
-        self._check_state(q)
+        self._check_padded(q)
         check(lib().hope_fill_halo(self._h, _ptr(q), _stream()))
         return q
 
     def tendency(self, q: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        self._check_state(q)
+        self._check_padded(q)
         if out is None:
             out = torch.empty(3, 6, self.n, self.n, dtype=torch.float64, device=q.device)
         self._check_field(out)
@@ -96,7 +107,7 @@ class Grid:
                      ws: torch.Tensor | None = None) -> torch.Tensor:
         """dL/dq (interior) of the tendency at the padded state q, given
         w = dL/d(dq/dt)."""
-        self._check_state(q)
+        self._check_padded(q)
         self._check_field(w)
         if out is None:
             out = torch.empty(3, 6, self.n, self.n, dtype=torch.float64, device=q.device)
@@ -116,7 +127,7 @@ class Grid:
         return torch.empty(self.layout.rk_vjp_workspace_bytes // 8, dtype=torch.float64, device="cuda")
 
     def rk_step(self, q: torch.Tensor, dt: float, scheme: str = "ssp3", ws: torch.Tensor | None = None):
-        self._check_state(q)
+        self._check_padded(q)
         if ws is None:
             ws = self.workspace()
         code = {"ssp3": HOPE_RK_SSP3, "ws3": HOPE_RK_WS3}[scheme]
@@ -126,7 +137,7 @@ class Grid:
     def rk_step_vjp(self, q: torch.Tensor, dt: float, gout: torch.Tensor, scheme: str = "ssp3",
                     out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
         """dL/dq^n of one RK step from q^n (padded) and gout = dL/dq^{n+1}."""
-        self._check_state(q)
+        self._check_padded(q)
         self._check_field(gout)
         if out is None:
             out = torch.empty(3, 6, self.n, self.n, dtype=torch.float64, device=q.device)
