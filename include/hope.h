@@ -87,6 +87,16 @@ typedef struct hope_grid_desc {
                             unit position (x, y, z); 0 gives f = 2 Omega sin(theta) */
   double weno_eps;       /* epsilon of (3.23) (default 1e-12) */
   double split_theta;    /* theta of the weight split (3.20) (default 3) */
+  const char* cache_dir; /* NULL, or an existing directory for cached host
+                            tables: hope_grid_create reads the tables of the
+                            same (n, order, scheme, radius, weno_eps,
+                            split_theta, ghost_iters) and library build from
+                            a file there instead of building them, and
+                            otherwise builds them and writes the file (about
+                            40 MB at C360).  A file that does not match or
+                            fails its checksum or range checks is rebuilt; a
+                            directory that cannot be written only costs the
+                            build. */
 } hope_grid_desc;
 
 /* Sizes a caller needs to allocate buffers (all counts are elements). */
@@ -100,6 +110,8 @@ typedef struct hope_layout {
   int64_t ghost_cells;      /* ghost cells per variable, all panels */
   int64_t ghost_nnz;        /* stored entries of the ghost map */
   int64_t device_bytes;     /* device memory owned by the grid (tables, maps, scratch) */
+  int32_t ghost_sweeps;     /* sweeps of the ghost-map build (ghost_iters if set) */
+  int32_t tables_cached;    /* 1 if the host tables were read from cache_dir */
 } hope_layout;
 
 /* Build a grid: equiangular metrics, reconstruction and WENO tables, the

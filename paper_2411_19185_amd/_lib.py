@@ -42,6 +42,7 @@ class GridDesc(ctypes.Structure):
         ("axis_tilt", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
         ("split_theta", ctypes.c_double),
+        ("cache_dir", ctypes.c_char_p),
     ]
 
 
@@ -59,6 +60,8 @@ class Layout(ctypes.Structure):
         ("ghost_cells", ctypes.c_int64),
         ("ghost_nnz", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64),
+        ("ghost_sweeps", ctypes.c_int32),
+        ("tables_cached", ctypes.c_int32),
     ]
 
 
@@ -138,7 +141,7 @@ def check(code: int):
 
 
 def make_desc(n, order, scheme="tpp", radius=6.371e6, omega=7.292e-5, axis_tilt=0.0, weno_eps=1e-12,
-              split_theta=3.0, gravity=9.80616, ghost_iters=0) -> GridDesc:
+              split_theta=3.0, gravity=9.80616, ghost_iters=0, cache_dir=None) -> GridDesc:
     d = GridDesc()
     d.struct_size = ctypes.sizeof(GridDesc)
     d.n = n
@@ -152,6 +155,7 @@ def make_desc(n, order, scheme="tpp", radius=6.371e6, omega=7.292e-5, axis_tilt=
     d.weno_eps = weno_eps
     d.split_theta = split_theta
     d.ghost_iters = ghost_iters
+    d.cache_dir = None if cache_dir is None else os.fsencode(cache_dir)
     return d
 
 

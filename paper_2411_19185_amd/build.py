@@ -13,7 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhope.so")
 
-SOURCES = ["capi.cpp", "batch_capi.cpp", "host_tables.cpp", "kernels.hip", "vjp.hip", "batch.hip"]
+SOURCES = ["capi.cpp", "batch_capi.cpp", "host_tables.cpp", "grid_cache.cpp", "kernels.hip", "vjp.hip",
+           "batch.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

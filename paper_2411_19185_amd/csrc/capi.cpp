@@ -159,7 +159,10 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
   if (!G) return fail(HOPE_ERR_NOMEM, "host allocation");
   int st = 0;
   try {
-    st = build_tables(G->h, n, k, weno, radius, omega, desc->axis_tilt, eps, theta, desc->ghost_iters);
+    bool cached = false;
+    st = build_tables_cached(G->h, desc->cache_dir, &cached, n, k, weno, radius, omega, desc->axis_tilt, eps, theta,
+                             desc->ghost_iters);
+    G->tables_cached = cached;
   } catch (const std::bad_alloc&) {
     free_grid(G);
     return fail(HOPE_ERR_NOMEM, "host allocation while building tables");
@@ -374,6 +377,8 @@ int hope_grid_layout(const hope_grid* G, hope_layout* out) {
   out->ghost_cells = G->g.rows;
   out->ghost_nnz = G->g.nnz;
   out->device_bytes = (int64_t)G->device_bytes;
+  out->ghost_sweeps = h.ghost_sweeps;
+  out->tables_cached = G->tables_cached ? 1 : 0;
   return HOPE_OK;
 }
 

@@ -20,6 +20,7 @@ struct hope_grid {
   double* bt = nullptr;      // panel-edge trace scratch, 24*n*m*3
   unsigned long long* bad = nullptr;   // hope_check_state's counter, after bt
   int strip_w = 62, seg_h = 8;
+  bool tables_cached = false;   // host tables read from a cache file
   // G^T by the interior cells some ghost row reads (adjoint of the ghost fill)
   int32_t gt_rows = 0;
   const int32_t* gt_cell = nullptr;

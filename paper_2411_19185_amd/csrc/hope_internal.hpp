@@ -65,6 +65,12 @@ void coriolis_coefs(double tilt, double* out);
 // ghost_iters: 0 for the fixed-point ghost map, N > 0 for N Jacobi sweeps from 0.
 int build_tables(HostTables& t, int n, int k, int weno, double radius, double omega, double tilt,
                  double eps, double theta, int ghost_iters = 0);
+// Identifies the build of the table code (cache files of other builds are ignored).
+const char* tables_build_stamp();
+// build_tables through an on-disk cache in dir (null or empty: no cache);
+// *loaded tells whether the tables came from a cache file.
+int build_tables_cached(HostTables& t, const char* dir, bool* loaded, int n, int k, int weno, double radius,
+                        double omega, double tilt, double eps, double theta, int ghost_iters);
 
 // ---------------------------------------------------------------------------
 // All constant tables of a grid live in one FP64 buffer (and one int32

@@ -987,6 +987,8 @@ int build_tables(HostTables& t, int n, int k, int weno, double radius, double om
 }
 
 // Coriolis parameter on panel p: f = 2 Omega (Omega_hat . p_hat) with the axis
+const char* tables_build_stamp() { return "host tables " __DATE__ " " __TIME__; }
+
 // tilted by alpha towards -x, Omega_hat = (-sin alpha, 0, cos alpha).  With the
 // unnormalised panel point v = (c0 + X cX + Y cY per component), Omega_hat . v =
 // L0 + LX X + LY Y; out[3p..3p+2] = (L0, LX, LY).

@@ -3,6 +3,7 @@ passes tensor pointers and torch's current stream to the library."""
 from __future__ import annotations
 
 import ctypes
+import os
 
 import torch
 
@@ -23,9 +24,11 @@ class Grid:
 
     def __init__(self, n: int, order: int, scheme: str = "tpp", radius: float = 6.371e6,
                  omega: float = 7.292e-5, axis_tilt: float = 0.0, weno_eps: float = 1e-12,
-                 split_theta: float = 3.0, ghost_iters: int = 0):
+                 split_theta: float = 3.0, ghost_iters: int = 0, cache_dir: str | None = None):
+        if cache_dir is not None:
+            os.makedirs(cache_dir, exist_ok=True)
         self.desc = make_desc(n, order, scheme, radius, omega, axis_tilt, weno_eps, split_theta,
-                              ghost_iters=ghost_iters)
+                              ghost_iters=ghost_iters, cache_dir=cache_dir)
         h = ctypes.c_void_p()
         check(lib().hope_grid_create(ctypes.byref(self.desc), ctypes.byref(h)))
         self._h = h
