@@ -23,6 +23,8 @@
 // Scratch arrays are structs of arrays over cells, so that neighbouring lanes
 // (neighbouring cells) read and write neighbouring addresses.
 // Non-smooth points take the subgradient sign(0) = 0.
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "vjp_internal.hpp"
 
@@ -434,9 +436,10 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
   // |d_sx| versions Za, Ea for the centre node); per point B, D (and A, C)
   cdp d1 = tab + C::O.d1;
   const double th = tab[C::O.theta];
-#pragma unroll 1
-  for (int px = 0; px < NA; ++px) {
-    const bool xm = weno_mixed_axis(K, M, px);
+  // one x axis point; the mixed-sign centre node (xm) keeps the abs(d)
+  // column sums as well, the other nodes are compiled without them
+  auto column_pass = [&](auto mixed, int px) {
+    constexpr bool xm = decltype(mixed)::value;
     double xr[L * NR];
 #pragma unroll
     for (int sx = 0; sx < L; ++sx)
@@ -584,6 +587,11 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
 #pragma unroll
         for (int a = 0; a < L; ++a)
           dq[row * K + (sx + a)] = fma(wsub[(sx * NA + px) * L + a], xrb[sx * NR + row], dq[row * K + (sx + a)]);
+  };
+#pragma unroll 1
+  for (int px = 0; px < NA; ++px) {
+    if (weno_mixed_axis(K, M, px)) column_pass(std::true_type{}, px);
+    else column_pass(std::false_type{}, px);
   }
   // kappa_j = 1 + tau/(beta_j + eps)
   double taub = 0, betab[S];
