@@ -21,7 +21,8 @@ def test_library_exports_every_header_function():
 
 
 @pytest.mark.parametrize("n,order,scheme,code", [(12, 4, "tpp", -2), (12, 15, "tpp", -2), (12, 7, "weno", -2),
-                                                 (4, 5, "tpp", -2)])
+                                                 (4, 5, "tpp", -2), (4097, 5, "weno", -2), (0, 3, "tpp", -2),
+                                                 (-5, 3, "tpp", -2), (12, 1, "tpp", -2)])
 def test_inspect_rejects_unsupported(n, order, scheme, code):
     d = make_desc(n, order, scheme)
     rows, nnz = ctypes.c_int64(), ctypes.c_int64()
