@@ -1,11 +1,14 @@
 """The paper's accuracy experiment (section 5.1, Table 5.1) on the GPU path:
 the steady-state geostrophic flow integrated for 12 days with the paper's
-three-stage Runge-Kutta scheme and time steps, TPP3 and TPP5 at C30, C45 and
-C90.  The normalised geopotential errors must equal the printed values to
-the five significant digits the paper prints, and so the printed rates (the
-paper ran in quadruple precision; at these resolutions the errors are far
-above FP64 rounding).  This pins the readings the path shares with the
-oracle end to end, including the second stage of (3.40) taken from q^n."""
+three-stage Runge-Kutta scheme and time steps, with TPP3 to TPP11 at C30 to
+C360.  The normalised geopotential errors must equal the printed values to
+the five significant digits the paper prints, and so the printed rates.  The
+paper ran in quadruple precision; FP64 rounding, accumulated over up to 2e4
+steps of relative error 1.1e-16 each, adds at most about 1e-14 to a
+normalised error, so the cases kept are those whose printed errors lie well
+above that floor (all of TPP3 and TPP5, TPP7 to C90, TPP9 and TPP11 to C45).
+This pins the readings the path shares with the oracle end to end, including
+the second stage of (3.40) taken from q^n, and the high-order kernels."""
 import math
 
 import numpy as np
@@ -13,7 +16,7 @@ import pytest
 import torch
 
 import hope_inputs as hi
-from golden.table51 import DT, RESOLUTIONS, load
+from golden.table51 import DT, load
 from oracle.ic import cell_average, cell_sqrt_g
 from oracle.norms import error_norms
 
@@ -37,25 +40,32 @@ def _run(order, n):
     sg = cell_sqrt_g(n, a)[None, :, :]
     phi = g.interior(qp)[0].cpu().numpy() / sg
     ref = q0[0].numpy() / sg
-    l1, _, linf = error_norms(phi, ref, np.broadcast_to(sg, phi.shape))
-    return {"L1": l1, "Linf": linf}
+    l1, l2, linf = error_norms(phi, ref, np.broadcast_to(sg, phi.shape))
+    return {"L1": l1, "L2": l2, "Linf": linf}
 
 
-@pytest.mark.parametrize("order", [3, 5])
+# resolutions per order whose printed errors lie above the FP64 floor
+CASES = {3: (30, 45, 90, 180, 360), 5: (30, 45, 90, 180, 360), 7: (30, 45, 90), 9: (30, 45), 11: (30, 45)}
+FP64_FLOOR = 1e-14
+
+
+@pytest.mark.parametrize("order", sorted(CASES))
 def test_table_5_1_rates_and_errors(order):
     errors, rates = load()
     key = f"tpp{order}"
+    res = CASES[order]
     got = {}
-    for n in RESOLUTIONS:
+    for n in res:
         print(f"case TPP{order} C{n}, 12 days", flush=True)
         got[n] = _run(order, n)
-        print("  ", got[n], "paper", {nm: errors[(key, nm)][n] for nm in ("L1", "Linf")}, flush=True)
-    for norm in ("L1", "Linf"):
-        for n in RESOLUTIONS:
+        print("  ", got[n], "paper", {nm: errors[(key, nm)][n] for nm in ("L1", "L2", "Linf")}, flush=True)
+    for norm in ("L1", "L2", "Linf"):
+        for n in res:
             printed = errors[(key, norm)][n]
             # printed with 5 significant digits: half a unit of the last digit is <= 5e-5 relative
-            assert abs(got[n][norm] - printed) <= 5.1e-5 * printed, (norm, n, got[n][norm], printed)
-        for (a, b), printed in zip(zip(RESOLUTIONS, RESOLUTIONS[1:]), rates[(key, norm)]):
+            assert abs(got[n][norm] - printed) <= 5.1e-5 * printed + FP64_FLOOR, (norm, n, got[n][norm], printed)
+        for a, b in zip(res, res[1:]):
+            printed = rates[(key, norm)][b]
             rate = math.log(got[a][norm] / got[b][norm]) / math.log(b / a)
             print(f"  rate {norm} C{a}->C{b}: {rate:.4f} (paper {printed})", flush=True)
             assert abs(rate - printed) < 2e-3, (norm, a, b, rate, printed)
