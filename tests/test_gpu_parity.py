@@ -30,6 +30,14 @@ CASES = [
     (26, 13, "tpp", "perturbed_balanced", 8),
     (70, 5, "tpp", "member", 9),             # two strips per panel
     (64, 3, "tpp", "member", 10),
+    # the smallest grid of each order (n = order): ghost stencils reach across
+    # a whole panel
+    (3, 3, "tpp", "member", 23),
+    (3, 3, "weno", "member", 24),
+    (5, 5, "tpp", "member", 25),
+    (5, 5, "weno", "dam_break", 26),
+    (9, 9, "tpp", "perturbed_balanced", 27),
+    (11, 11, "tpp", "member", 28),
 ]
 
 

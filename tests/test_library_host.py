@@ -55,7 +55,7 @@ def _apply_library_ghost_map(n, k, q, ghost_iters=0):
     return qp.reshape(3, 6, P, P), sweeps
 
 
-@pytest.mark.parametrize("n,k", [(6, 3), (8, 5), (13, 5), (10, 7), (12, 11)])
+@pytest.mark.parametrize("n,k", [(6, 3), (8, 5), (13, 5), (10, 7), (12, 11), (3, 3), (5, 5), (9, 9)])
 def test_library_ghost_map_equals_oracle_fixed_point(n, k):
     """The library builds G with its own geometry (3D basis vectors), weights
     (primitive-function Lagrange form) and Gauss-Seidel iteration; applied to
