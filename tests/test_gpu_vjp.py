@@ -37,6 +37,10 @@ VJP_CASES = [
     (8, 7, "tpp", "perturbed_member", 36),
     (20, 9, "tpp", "perturbed_member", 37),
     (26, 13, "tpp", "perturbed_balanced", 38),
+    # the smallest grid of each scheme (n = order)
+    (3, 3, "weno", "perturbed_member", 39),
+    (5, 5, "weno", "perturbed_member", 40),
+    (7, 7, "tpp", "perturbed_member", 41),
 ]
 
 
@@ -73,7 +77,8 @@ def test_tendency_vjp_is_repeatable_and_ignores_stale_ghosts():
 @pytest.mark.parametrize("n,order,scheme,state,rk,seed", [(12, 3, "tpp", "perturbed_member", "ssp3", 42),
                                                          (10, 5, "weno", "perturbed_member", "ssp3", 43),
                                                          (12, 11, "tpp", "perturbed_balanced", "ssp3", 44),
-                                                         (9, 5, "tpp", "perturbed_member", "ws3", 45)])
+                                                         (9, 5, "tpp", "perturbed_member", "ws3", 45),
+                                                         (5, 5, "weno", "perturbed_member", "ssp3", 46)])
 def test_rk_step_vjp_matches_oracle_autograd(n, order, scheme, state, rk, seed):
     print(f"case n={n} order={order} {scheme} {rk}", flush=True)
     alpha, q = STATES[state](n, seed)
