@@ -56,6 +56,25 @@ def test_batch_tendency_equals_each_member_grid_bitwise():
     assert max(err) < TOL, err
 
 
+@pytest.mark.parametrize("order,scheme,ns", [(3, "tpp", [3, 8, 3, 31]), (3, "weno", [3, 5, 9]),
+                                             (11, "tpp", [11, 14, 11]), (5, "tpp", [5, 64, 6])])
+def test_batch_of_other_orders_and_smallest_members_equals_member_grids(order, scheme, ns):
+    """Other orders and schemes, with members as small as the order allows."""
+    print("case batch", order, scheme, ns, flush=True)
+    ens, q_all, tilts, states, _ = _setup(ns, order=order, scheme=scheme, seed=200 + order)
+    out = ens.tendency(q_all)
+    for i, n in enumerate(ns):
+        g = _grid(n, order, scheme, tilts[i])
+        ref = g.tendency(to_padded(states[i], g.r))
+        got = ens.member_field(out, i)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), (i, n, rel_err(got, ref))
+    og = oracle_grid(ns[0], order, scheme, tilts[0])
+    err = rel_err(ens.member_field(out, 0), og.tendency(states[0]))
+    print("oracle rel err", err, flush=True)
+    assert max(err) < TOL, err
+
+
 @pytest.mark.parametrize("scheme", ["ssp3", "ws3"])
 def test_batch_rk_steps_equal_each_member_grid_bitwise(scheme):
     ns = [12, 9, 12, 15]
