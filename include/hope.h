@@ -115,9 +115,10 @@ typedef struct hope_layout {
 } hope_layout;
 
 /* Build a grid: equiangular metrics, reconstruction and WENO tables, the
- * exact ghost-cell map G of appendix (7.12) (the fixed point of the iterative
- * interpolation of section 3.3.1, with owner-panel conversion (3.26)-(3.29)),
- * and the panel-edge trace maps.  G commutes with the cube's 24 rotations;
+ * ghost-cell map G of appendix (7.12) (the exact fixed point of the iterative
+ * interpolation of section 3.3.1, with owner-panel conversion (3.26)-(3.29),
+ * or with ghost_iters set the map of that many sweeps), and the panel-edge
+ * trace maps; with cache_dir set, the host tables may come from a file.  G commutes with the cube's 24 rotations;
  * each row is replaced by the rotation image of one of r*(n+r) canonical rows
  * (they agree to rounding; the build fails with HOPE_ERR_NUMERIC otherwise),
  * and the device keeps the values once per canonical row.  Host work plus
