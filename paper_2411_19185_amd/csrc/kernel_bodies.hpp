@@ -174,10 +174,17 @@ struct StageSmem {
   // window columns: one strip of up to 64 lanes plus 2R, or two half strips
   // of 32 lanes plus 2R each
   static constexpr int R = (K - 1) / 2, NR = 2 * R + 1, CW = 64 + 4 * R;
-  // slots of pts: left edge, right edge, bottom edge (M each), then the M x M
-  // cell nodes; a row's top traces stay in the registers of the wavefront
-  // that computed them until they move to ptop
-  static constexpr int PL = 0, PR = M, PB = 2 * M, PI = 3 * M, NP = 3 * M + M * M;
+  // TPP orders 11 and 13 take the cell nodes in chunks of HC node columns
+  // (the sources of a chunk are added before the next chunk is
+  // reconstructed), so that two workgroups fit in a CU's LDS instead of one;
+  // the lower orders keep all M x M, which measured faster for them.
+  static constexpr bool kChunk = !W && K >= 11;
+  static constexpr int HC = kChunk ? (K >= 13 ? 1 : 2) : M;
+  static constexpr int NCH = (M + HC - 1) / HC;
+  // slots of pts: left edge, right edge, bottom edge (M each), then the cell
+  // nodes of one chunk (M x HC); a row's top traces stay in the registers of
+  // the wavefront that computed them until they move to ptop
+  static constexpr int PL = 0, PR = M, PB = 2 * M, PI = 3 * M, NP = 3 * M + M * HC;
   double sq[3][NR][CW];     // stencil window: NR padded rows (column c of a strip's part = padded column i0-1+c)
   double pts[3][NP][64];    // the current row's values at the points of every lane's cell
   double ptop[3][M][64];    // top traces of the row below
@@ -408,6 +415,64 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
 #pragma unroll
     for (int v = 0; v < 3; ++v) fx(v, lane) = fl[v];
   };
+  // wavefront 2: sources of the node columns [h0, h1) of row j, whose values
+  // are in the chunk slots (chunked mode), accumulated into s1, s2 in the
+  // order of sources_row
+  auto sources_chunk = [&](int j, int h0, int h1, double& s1, double& s2) {
+    cdp fc = fcb + p * 3;
+    const double Lx0 = fc[0], LxX = fc[1], LxY = fc[2];
+#pragma unroll 1
+    for (int h = h0; h < h1; ++h) {
+      const double X = Xg[ic * M + h];
+#pragma unroll
+      for (int w = 0; w < M; ++w) {
+        double cq[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) cq[v] = real ? pt(v, SM::PI + w * SM::HC + (h - h0)) : (v == 0 ? 1.0 : 0.0);
+        const double Y = Xg[j * M + w];
+        double a1, a2;
+        sources(cq[0], cq[1], cq[2], X, Y, Lx0 + LxX * X + LxY * Y, gs.omega2, a1, a2);
+        const double g2 = gw[h] * gw[w];
+        s1 = fma(g2, a1, s1);
+        s2 = fma(g2, a2, s2);
+      }
+    }
+  };
+  // chunked TPP: every point of row pc, the cell nodes chunk by chunk, with
+  // wavefront 2 adding each chunk's sources between two barriers (all
+  // threads pass the same barriers)
+  auto recon_row_chunked = [&](int pc, double* top, double& s1, double& s2) {
+    double kap[1];
+    auto kf = [&](int jj) -> double { return kap[jj]; };
+    double xr[XR];
+    asm volatile("" ::: "memory");
+    xpass<K, W, M>(tab, 0, win(pc), xr);
+#pragma unroll
+    for (int h = 0; h < M; ++h) pt(wv, h) = point<K, W, M>(tab, 2 + h, h, xr, kf);
+    asm volatile("" ::: "memory");
+    xpass<K, W, M>(tab, 1, win(pc), xr);
+#pragma unroll
+    for (int h = 0; h < M; ++h) pt(wv, M + h) = point<K, W, M>(tab, 2 + h, M + h, xr, kf);
+    s1 = 0.0;
+    s2 = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < SM::NCH; ++c) {
+      const int h0 = c * SM::HC, h1 = min(M, h0 + SM::HC);
+#pragma unroll 1
+      for (int h = h0; h < h1; ++h) {
+        asm volatile("" ::: "memory");
+        xpass<K, W, M>(tab, 2 + h, win(pc), xr);
+        pt(wv, SM::PB + h) = point<K, W, M>(tab, 0, 2 * M + h, xr, kf);
+        top[h] = point<K, W, M>(tab, 1, 3 * M + h, xr, kf);
+#pragma unroll
+        for (int w = 0; w < M; ++w)
+          pt(wv, SM::PI + w * SM::HC + (h - h0)) = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+      }
+      __syncthreads();
+      if (wv == 2) sources_chunk(pc, h0, h1, s1, s2);
+      if (c + 1 < SM::NCH) __syncthreads();
+    }
+  };
   // wavefront 2: metric and Coriolis sources of row j (cell quadrature)
   auto sources_row = [&](int j) {
     cdp fc = fcb + p * 3;
@@ -466,8 +531,10 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     __syncthreads();
     const bool want = (j + 1 < j1 || (j + 1 == j1 && j1 < n)) && (j + 2 * R + 1) < P;
     if (want) fetch(j + 2 * R + 1, nxt);
+    double s1c = 0.0, s2c = 0.0;     // chunked mode: this row's sources (wavefront 2)
     if (!last) {
-      recon_row(j, top);
+      if constexpr (SM::kChunk) recon_row_chunked(j, top, s1c, s2c);
+      else recon_row(j, top);
     } else if (j1 == n) {
       // bottom traces of the panel's top row: the neighbour's converted trace
 #pragma unroll
@@ -487,7 +554,14 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     if (wv == 1) yflux(j);
     if (!last) {
       if (wv == 0) xflux(j);
-      if (wv == 2) sources_row(j);
+      if (wv == 2) {
+        if constexpr (SM::kChunk) {
+          src(0) = s1c;
+          src(1) = s2c;
+        } else {
+          sources_row(j);
+        }
+      }
     }
     __syncthreads();
     // ---- assembly: wavefront wv, variable wv -----------------------------
