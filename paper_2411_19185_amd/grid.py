@@ -26,6 +26,7 @@ class Grid:
                  omega: float = 7.292e-5, axis_tilt: float = 0.0, weno_eps: float = 1e-12,
                  split_theta: float = 3.0, ghost_iters: int = 0, cache_dir: str | None = None):
         if cache_dir is not None:
+            cache_dir = os.path.expanduser(cache_dir)
             os.makedirs(cache_dir, exist_ok=True)
         self.desc = make_desc(n, order, scheme, radius, omega, axis_tilt, weno_eps, split_theta,
                               ghost_iters=ghost_iters, cache_dir=cache_dir)
