@@ -199,11 +199,15 @@ int hope_grid_get_launch(const hope_grid* grid, int32_t* strip_w, int32_t* seg_h
 /* Per-kernel timing.  While enabled, the library brackets each kernel it
  * launches with HIP events recorded on the launch stream (events are created
  * on first use and kept by the grid).  hope_grid_profile(g, 1) clears the
- * record and starts, (g, 0) stops.  hope_grid_profile_read waits for the
+ * record and starts timing every kernel; (g, HOPE_PROFILE_SELECT | bits)
+ * does the same for the kernels whose bit (1 << index, indices below) is
+ * set, so that the other launches carry no events (each event costs the
+ * stream a few microseconds); (g, 0) stops.  hope_grid_profile_read waits for the
  * recorded events and returns the summed elapsed time and launch count of one
  * kernel: 0 ghost fill, 1 panel-edge traces, 2 fused stage, and the kernels
  * of the adjoint: 3 point values, 4 flux and source adjoints, 5 panel-edge
  * adjoints, 6 WENO adjoint, 7 gather to the padded cells, 8 G^T fold. */
+enum { HOPE_PROFILE_SELECT = 0x40000000 };
 int hope_grid_profile(hope_grid* grid, int32_t enable);
 int hope_grid_profile_read(hope_grid* grid, int32_t kernel, double* total_ms, int64_t* launches);
 

@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "hope.h")
 
 HOPE_OK = 0
 HOPE_ERR_NUMERIC = -5
+HOPE_PROFILE_SELECT = 0x40000000
 HOPE_SCHEME_TPP, HOPE_SCHEME_WENO = 0, 1
 HOPE_RK_SSP3, HOPE_RK_WS3 = 0, 1
 

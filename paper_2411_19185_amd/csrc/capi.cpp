@@ -46,7 +46,7 @@ struct Timed {
   hipStream_t s;
   int a = -1;
   Timed(const hope_grid* g, int k, void* stream) : G(const_cast<hope_grid*>(g)), kind(k), s((hipStream_t)stream) {
-    if (!G->timing) return;
+    if (!G->timing || !((G->timing_mask >> kind) & 1u)) return;
     hipEvent_t e = next_event(G);
     if (!e) return;
     a = (int)G->used - 1;
@@ -576,11 +576,21 @@ int hope_grid_get_launch(const hope_grid* G, int32_t* strip_w, int32_t* seg_h) {
 
 int hope_grid_profile(hope_grid* G, int32_t enable) {
   if (!G) return fail(HOPE_ERR_INVALID, "null argument");
+  const uint32_t all = (1u << (3 + kVjpSteps)) - 1u;
+  uint32_t mask = 0;
+  if (enable == 1) {
+    mask = all;
+  } else if (enable != 0) {
+    if (!(enable & HOPE_PROFILE_SELECT) || ((uint32_t)enable & ~(uint32_t)HOPE_PROFILE_SELECT & ~all))
+      return fail(HOPE_ERR_INVALID, "profile: 0, 1 or HOPE_PROFILE_SELECT | kernel bits");
+    mask = (uint32_t)enable & all;
+  }
   if (enable) {
     G->recs.clear();
     G->used = 0;
   }
   G->timing = enable != 0;
+  G->timing_mask = mask;
   return HOPE_OK;
 }
 

@@ -30,6 +30,7 @@ struct hope_grid {
   int64_t gt_nnz = 0;
   // optional per-kernel timing with HIP events on the launch stream
   bool timing = false;
+  uint32_t timing_mask = 0;   // bit k: kernel index k is timed
   std::vector<hipEvent_t> pool;
   struct Rec { int kind; int a, b; };
   std::vector<Rec> recs;

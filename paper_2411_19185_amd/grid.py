@@ -7,7 +7,8 @@ import os
 
 import torch
 
-from ._lib import (HOPE_ERR_NUMERIC, HOPE_OK, HOPE_RK_SSP3, HOPE_RK_WS3, Layout, check, lib, make_desc)
+from ._lib import (HOPE_ERR_NUMERIC, HOPE_OK, HOPE_PROFILE_SELECT, HOPE_RK_SSP3, HOPE_RK_WS3, Layout, check, lib,
+                   make_desc)
 
 
 def _stream() -> ctypes.c_void_p:
@@ -165,8 +166,18 @@ class Grid:
     KERNELS = {"fill_halo": 0, "edge_traces": 1, "stage": 2, "vjp_traces": 3, "vjp_points": 4, "vjp_edges": 5,
                "vjp_weno": 6, "vjp_gather": 7, "vjp_ghost_t": 8}
 
-    def profile(self, enable: bool):
-        check(lib().hope_grid_profile(self._h, 1 if enable else 0))
+    def profile(self, enable: bool, only: tuple[str, ...] | None = None):
+        """Start (clearing the record) or stop per-kernel timing; with ``only``,
+        just those kernels are bracketed by events."""
+        if not enable:
+            code = 0
+        elif only is None:
+            code = 1
+        else:
+            code = HOPE_PROFILE_SELECT
+            for name in only:
+                code |= 1 << self.KERNELS[name]
+        check(lib().hope_grid_profile(self._h, code))
 
     def profile_read(self, kernel: str):
         """(total ms, launches) of one kernel since profile(True)."""

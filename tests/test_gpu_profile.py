@@ -1,0 +1,36 @@
+"""GPU test of the per-kernel timing: every kernel, or only selected ones,
+is bracketed by events, and timing does not change results."""
+import ctypes
+
+import pytest
+import torch
+
+from cases import STATES, to_padded
+
+pytestmark = pytest.mark.gpu
+
+
+def test_profile_all_or_selected_kernels():
+    from paper_2411_19185_amd import Grid
+    from paper_2411_19185_amd._lib import HOPE_PROFILE_SELECT, lib
+    n = 24
+    alpha, q = STATES["member"](n, 3, nq=2)
+    g = Grid(n, 5, "weno", axis_tilt=alpha)
+    qp = to_padded(q, g.r)
+    ref = g.tendency(qp)
+    g.profile(True)
+    a = g.tendency(qp)
+    g.profile(False)
+    assert [g.profile_read(k)[1] for k in ("fill_halo", "edge_traces", "stage")] == [1, 1, 1]
+    assert all(g.profile_read(k)[0] > 0 for k in ("fill_halo", "edge_traces", "stage"))
+    g.profile(True, only=("stage",))
+    b = g.tendency(qp)
+    b2 = g.tendency(qp)
+    g.profile(False)
+    assert [g.profile_read(k)[1] for k in ("fill_halo", "edge_traces", "stage")] == [0, 0, 2]
+    torch.cuda.synchronize()
+    assert torch.equal(a, ref) and torch.equal(b, ref) and torch.equal(b2, ref)
+    # codes other than 0, 1 and HOPE_PROFILE_SELECT | kernel bits are rejected
+    assert lib().hope_grid_profile(g._h, 2) == -1
+    assert lib().hope_grid_profile(g._h, HOPE_PROFILE_SELECT | (1 << 12)) == -1
+    assert lib().hope_grid_profile(g._h, 0) == 0
