@@ -20,19 +20,20 @@
 
 namespace hope {
 
+template <int LANES>
 __global__ __launch_bounds__(256) void k_fill_halo_batch(const BatchGrid* __restrict__ grids, int n_grids,
                                                          int total_rows, const int32_t* __restrict__ mlist,
                                                          const BatchMember* __restrict__ mem,
                                                          double* __restrict__ base) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);   // contiguous rows per L2 domain
-  const int row = (int)((lb * (size_t)blockDim.x + threadIdx.x) / kHaloLanes);
+  const int row = (int)((lb * (size_t)blockDim.x + threadIdx.x) / LANES);
   if (row >= total_rows) return;   // the whole lane group leaves together
   int gi = 0;
   while (gi + 1 < n_grids && grids[gi + 1].row_begin <= row) ++gi;
   const BatchGrid& bg = grids[gi];
   const GhostDev& g = bg.g;
   const int r = row - bg.row_begin;
-  const int lane = threadIdx.x % kHaloLanes;
+  const int lane = threadIdx.x % LANES;
   const size_t plane = (size_t)6 * bg.P * bg.P;
   const int b = g.ptr[r], e = g.ptr[r + 1];
   const int d = g.dst[r];
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(256) void k_fill_halo_batch(const BatchGrid* __rest
     double acc[kHaloChunk][3];
 #pragma unroll
     for (int t = 0; t < kHaloChunk; ++t) acc[t][0] = acc[t][1] = acc[t][2] = 0.0;
-    for (int k = b + lane; k < e; k += kHaloLanes) {
+    for (int k = b + lane; k < e; k += LANES) {
       const GhostEnt en = g.ent[k];
       const int c = en.col;
       const int j = en.ce & 0x1fff, f = en.ce >> 13;
@@ -69,10 +70,10 @@ __global__ __launch_bounds__(256) void k_fill_halo_batch(const BatchGrid* __rest
 #pragma unroll
     for (int t = 0; t < kHaloChunk; ++t) {
 #pragma unroll
-      for (int off = kHaloLanes / 2; off > 0; off >>= 1) {
-        acc[t][0] += __shfl_xor(acc[t][0], off, kHaloLanes);
-        acc[t][1] += __shfl_xor(acc[t][1], off, kHaloLanes);
-        acc[t][2] += __shfl_xor(acc[t][2], off, kHaloLanes);
+      for (int off = LANES / 2; off > 0; off >>= 1) {
+        acc[t][0] += __shfl_xor(acc[t][0], off, LANES);
+        acc[t][1] += __shfl_xor(acc[t][1], off, LANES);
+        acc[t][2] += __shfl_xor(acc[t][2], off, LANES);
       }
       if (lane == 0 && t < cnt) {
         double* q = qm[t];
@@ -137,13 +138,18 @@ __global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu(K
 // Launchers
 // ---------------------------------------------------------------------------
 int launch_batch_fill_halo(const BatchGrid* grids, int n_grids, int total_rows, const int32_t* members_by_grid,
-                           const BatchMember* members, double* base, void* stream) {
+                           const BatchMember* members, double* base, int lanes, void* stream) {
   if (total_rows == 0) return 0;
   const int threads = 256;
-  int blocks = (int)(((size_t)total_rows * kHaloLanes + threads - 1) / threads);
+  if (lanes != 32 && lanes != 64) return (int)hipErrorInvalidValue;
+  int blocks = (int)(((size_t)total_rows * lanes + threads - 1) / threads);
   blocks = (blocks + kXcds - 1) / kXcds * kXcds;
-  hipLaunchKernelGGL(k_fill_halo_batch, dim3(blocks), dim3(threads), 0, (hipStream_t)stream, grids, n_grids,
-                     total_rows, members_by_grid, members, base);
+  if (lanes == 64)
+    hipLaunchKernelGGL(k_fill_halo_batch<64>, dim3(blocks), dim3(threads), 0, (hipStream_t)stream, grids, n_grids,
+                       total_rows, members_by_grid, members, base);
+  else
+    hipLaunchKernelGGL(k_fill_halo_batch<32>, dim3(blocks), dim3(threads), 0, (hipStream_t)stream, grids, n_grids,
+                       total_rows, members_by_grid, members, base);
   return (int)hipGetLastError();
 }
 

@@ -91,7 +91,8 @@ int upload_members(hope_batch* B) {
 
 int batch_stage(const hope_batch* B, double* in, const double* qn, double* out, int out_padded, double ca,
                 double cb, double cs, const double* dt, void* stream) {
-  int e = launch_batch_fill_halo(B->dgrids, B->n_grids, B->total_rows, B->mlist, B->mem, in, stream);
+  int e = launch_batch_fill_halo(B->dgrids, B->n_grids, B->total_rows, B->mlist, B->mem, in, halo_lanes(B->k),
+                                 stream);
   if (e) return hip_fail((hipError_t)e, "batch fill_halo launch");
   e = launch_batch_edge_traces(B->k, B->weno, B->mem, B->edge_member, B->total_edges, in, B->bt, stream);
   if (e) return hip_fail((hipError_t)e, "batch edge_traces launch");

@@ -46,8 +46,9 @@ struct BatchStage {
 };
 
 // All enqueue on `stream`; return a hipError_t value.
+// lanes: lanes per ghost row, halo_lanes(order) as in the single-grid fill
 int launch_batch_fill_halo(const BatchGrid* grids, int n_grids, int total_rows, const int32_t* members_by_grid,
-                           const BatchMember* members, double* base, void* stream);
+                           const BatchMember* members, double* base, int lanes, void* stream);
 // edge_member: the member of each block of 64 flattened panel-edge sides
 int launch_batch_edge_traces(int k, int weno, const BatchMember* members, const int32_t* edge_member,
                              int total_edges, const double* in, double* bt, void* stream);

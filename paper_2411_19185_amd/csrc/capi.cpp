@@ -386,7 +386,7 @@ int hope_fill_halo(const hope_grid* G, double* q, void* stream) {
   if (!G || !q) return fail(HOPE_ERR_INVALID, "null argument");
   if (reinterpret_cast<uintptr_t>(q) % 8) return fail(HOPE_ERR_INVALID, "misaligned state");
   Timed tm(G, 0, stream);
-  int e = launch_fill_halo(G->g, q, 6 * G->h.P * G->h.P, stream);
+  int e = launch_fill_halo(G->g, q, 6 * G->h.P * G->h.P, halo_lanes(G->h.k), stream);
   if (e) return hip_fail((hipError_t)e, "fill_halo launch");
   return HOPE_OK;
 }
@@ -415,7 +415,7 @@ static int run_stage(const hope_grid* G, double* q, const double* qn, double* ou
   int e;
   {
     Timed tm(G, 0, stream);
-    e = launch_fill_halo(G->g, q, 6 * G->h.P * G->h.P, stream);
+    e = launch_fill_halo(G->g, q, 6 * G->h.P * G->h.P, halo_lanes(G->h.k), stream);
   }
   if (e) return hip_fail((hipError_t)e, "fill_halo launch");
   {
@@ -452,7 +452,7 @@ int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq
   int e;
   {
     Timed tm(G, 0, stream);
-    e = launch_fill_halo(G->g, q, 6 * h.P * h.P, stream);
+    e = launch_fill_halo(G->g, q, 6 * h.P * h.P, halo_lanes(h.k), stream);
   }
   if (e) return hip_fail((hipError_t)e, "fill_halo launch");
   VjpArgs a;

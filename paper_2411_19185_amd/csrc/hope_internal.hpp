@@ -127,6 +127,11 @@ HOPE_HD constexpr TabOffsets tab_offsets(int k, bool weno, int m, int n) {
 // against this rule when it builds a grid.
 HOPE_HD constexpr bool weno_mixed_axis(int k, int m, int a) { return k == 5 && m % 2 == 1 && a == 2 + m / 2; }
 
+// lanes that share one ghost row in the ghost-fill kernels: 32, or 64 from
+// order 7 on, whose rows hold several hundred entries each (the single-grid
+// and batched fills use the same count, so their sums agree bitwise)
+HOPE_HD constexpr int halo_lanes(int k) { return k >= 7 ? 64 : 32; }
+
 // Scalars every kernel needs.
 struct GridScalars {
   double radius, omega2, eps, inv_delta;
@@ -168,7 +173,8 @@ inline int stage_items(int strip_w, int n_strips, int n_segs) {
 
 // Launchers implemented in kernels.hip.  All enqueue on `stream` and return a
 // hipError_t value (0 on success).
-int launch_fill_halo(const GhostDev& g, double* q, int plane, void* stream);
+// lanes: lanes per ghost row, halo_lanes(order)
+int launch_fill_halo(const GhostDev& g, double* q, int plane, int lanes, void* stream);
 // bad[0] += number of interior cells of the padded state q with variable 0 not
 // positive and finite, or variables 1, 2 not finite; bad must be zeroed before
 int launch_check_state(const double* q, int n, int r, unsigned long long* bad, void* stream);

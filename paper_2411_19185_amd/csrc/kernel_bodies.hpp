@@ -47,14 +47,9 @@ __device__ __forceinline__ void frame_apply(int f, double c1, double c2, double&
 constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_block(int b, int nb) { return (b % kXcds) * (nb / kXcds) + b / kXcds; }
 
-// lanes that share one ghost row in the ghost-fill kernels
-#ifndef HOPE_HALO_LANES
-#define HOPE_HALO_LANES 32
-#endif
-constexpr int kHaloLanes = HOPE_HALO_LANES;
-
-// one ghost row of g = G q, reduced over kHaloLanes lanes (lane = 0.. of the
+// one ghost row of g = G q, reduced over LANES lanes (lane = 0.. of the
 // group): entries in column order, values from the row's canonical row
+template <int LANES>
 __device__ __forceinline__ void halo_row(const GhostDev& g, double* __restrict__ q, size_t plane, int row, int lane) {
   const int b = g.ptr[row], e = g.ptr[row + 1];
   const int info = g.info[row];
@@ -62,7 +57,7 @@ __device__ __forceinline__ void halo_row(const GhostDev& g, double* __restrict__
   const double* q1 = q + plane;
   const double* q2 = q + 2 * (size_t)plane;
   double mass = 0, mu = 0, mv = 0;
-  for (int k = b + lane; k < e; k += kHaloLanes) {
+  for (int k = b + lane; k < e; k += LANES) {
     const GhostEnt en = g.ent[k];
     const int c = en.col;
     const int j = en.ce & 0x1fff, f = en.ce >> 13;
@@ -75,10 +70,10 @@ __device__ __forceinline__ void halo_row(const GhostDev& g, double* __restrict__
     mv = fma(w3, q1[c], fma(w4, q2[c], mv));
   }
 #pragma unroll
-  for (int off = kHaloLanes / 2; off > 0; off >>= 1) {
-    mass += __shfl_xor(mass, off, kHaloLanes);
-    mu += __shfl_xor(mu, off, kHaloLanes);
-    mv += __shfl_xor(mv, off, kHaloLanes);
+  for (int off = LANES / 2; off > 0; off >>= 1) {
+    mass += __shfl_xor(mass, off, LANES);
+    mu += __shfl_xor(mu, off, LANES);
+    mv += __shfl_xor(mv, off, LANES);
   }
   if (lane == 0) {
     const int d = g.dst[row];

@@ -1,7 +1,7 @@
 // HIP kernels (gfx950, FP64) of the HOPE right-hand side on one grid; the
 // bodies they run are in kernel_bodies.hpp.
 //
-//  k_fill_halo     ghost cells g = G q (appendix (7.12)); kHaloLanes lanes per ghost row
+//  k_fill_halo     ghost cells g = G q (appendix (7.12)); halo_lanes(k) lanes per ghost row
 //  k_edge_traces   at every panel-edge Gauss point, the neighbour panel's own
 //                  trace, converted into this panel's variables (3.26)-(3.29);
 //                  one group of kEdgeLanes lanes per panel-edge cell side
@@ -23,12 +23,13 @@ namespace hope {
 // ---------------------------------------------------------------------------
 // Ghost fill
 // ---------------------------------------------------------------------------
+template <int LANES>
 __global__ __launch_bounds__(256) void k_fill_halo(GhostDev g, double* __restrict__ q, int plane) {
   // each L2 domain takes a contiguous range of rows (the rows are ordered for it)
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int row = (int)((lb * (size_t)blockDim.x + threadIdx.x) / kHaloLanes);
+  const int row = (int)((lb * (size_t)blockDim.x + threadIdx.x) / LANES);
   if (row >= g.rows) return;   // the whole lane group leaves together
-  halo_row(g, q, plane, row, threadIdx.x % kHaloLanes);
+  halo_row<LANES>(g, q, plane, row, threadIdx.x % LANES);
 }
 
 // ---------------------------------------------------------------------------
@@ -105,12 +106,16 @@ int launch_check_state(const double* q, int n, int r, unsigned long long* bad, v
   return (int)hipGetLastError();
 }
 
-int launch_fill_halo(const GhostDev& g, double* q, int plane, void* stream) {
+int launch_fill_halo(const GhostDev& g, double* q, int plane, int lanes, void* stream) {
   if (g.rows == 0) return 0;
+  if (lanes != 32 && lanes != 64) return (int)hipErrorInvalidValue;
   const int threads = 256;
-  int blocks = (int)(((size_t)g.rows * kHaloLanes + threads - 1) / threads);
+  int blocks = (int)(((size_t)g.rows * lanes + threads - 1) / threads);
   blocks = (blocks + kXcds - 1) / kXcds * kXcds;
-  hipLaunchKernelGGL(k_fill_halo, dim3(blocks), dim3(threads), 0, (hipStream_t)stream, g, q, plane);
+  if (lanes == 64)
+    hipLaunchKernelGGL(k_fill_halo<64>, dim3(blocks), dim3(threads), 0, (hipStream_t)stream, g, q, plane);
+  else
+    hipLaunchKernelGGL(k_fill_halo<32>, dim3(blocks), dim3(threads), 0, (hipStream_t)stream, g, q, plane);
   return (int)hipGetLastError();
 }
 
