@@ -167,3 +167,18 @@ def test_library_ghost_map_commutes_with_cube_rotations(n, k, axis_perm, signs):
                 got = b[:, p2, j2 + r, i2 + r]
                 worst = max(worst, np.abs(want - got).max() / scale)
     assert worst < 1e-13, worst
+
+
+def test_entry_points_reject_null_handles_without_a_device():
+    """Argument checks come before any device work: null grids and buffers
+    are rejected with HOPE_ERR_INVALID and a message."""
+    L = lib()
+    n_bad = ctypes.c_int64(5)
+    assert L.hope_check_state(None, None, ctypes.byref(n_bad), None) == -1
+    assert n_bad.value == 0
+    assert L.hope_fill_halo(None, None, None) == -1
+    assert L.hope_tendency(None, None, None, None) == -1
+    assert L.hope_rk_step(None, None, 1.0, 0, None, 0, None) == -1
+    assert L.hope_grid_profile(None, 1) == -1
+    assert L.hope_grid_layout(None, None) == -1
+    assert L.hope_last_error().decode()
