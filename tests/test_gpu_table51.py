@@ -1,12 +1,19 @@
 """The paper's accuracy experiment (section 5.1, Table 5.1) on the GPU path:
 the steady-state geostrophic flow integrated for 12 days with the paper's
 three-stage Runge-Kutta scheme and time steps, with TPP3 to TPP11 at C30 to
-C360.  The normalised geopotential errors must equal the printed values to
-the five significant digits the paper prints, and so the printed rates.  The
-paper ran in quadruple precision; FP64 rounding, accumulated over up to 2e4
-steps of relative error 1.1e-16 each, adds at most about 1e-14 to a
-normalised error, so the cases kept are those whose printed errors lie well
-above that floor (all of TPP3 and TPP5, TPP7 to C90, TPP9 and TPP11 to C45).
+C360.  The paper ran in quadruple precision; FP64 rounding, accumulated over
+up to 2e4 steps of relative error 1.1e-16 each, adds up to about 1e-14 to a
+normalised error, so the cases kept are those whose printed errors lie above
+that floor (all of TPP3 and TPP5, TPP7 to C90, TPP9 and TPP11 to C45).
+
+Each normalised geopotential error must equal the printed one to within half
+a unit of its fifth printed digit plus that floor, 1e-14 absolute.  Where the
+printed error exceeds about 2e-10 the floor is below the fifth digit, and
+this is agreement to the five printed digits.  Below that (TPP7 at C90, TPP9
+and TPP11 at C45) the floor dominates and the check is weaker: TPP11 C45
+L-infinity agrees to four digits only (2.8594e-12 against 2.8579e-12).
+There the convergence rates, checked to 2e-3 against the printed ones at
+every resolution pair, are what hold the result.
 This pins the readings the path shares with the oracle end to end, including
 the second stage of (3.40) taken from q^n, and the high-order kernels."""
 import math
@@ -62,7 +69,7 @@ def test_table_5_1_rates_and_errors(order):
     for norm in ("L1", "L2", "Linf"):
         for n in res:
             printed = errors[(key, norm)][n]
-            # printed with 5 significant digits: half a unit of the last digit is <= 5e-5 relative
+            # half a unit of the fifth printed digit (<= 5e-5 relative) plus the FP64 floor
             assert abs(got[n][norm] - printed) <= 5.1e-5 * printed + FP64_FLOOR, (norm, n, got[n][norm], printed)
         for a, b in zip(res, res[1:]):
             printed = rates[(key, norm)][b]

@@ -108,3 +108,18 @@ def test_split_weights():
     gp, gm, sp, sm = W.split_weights(g)
     assert np.allclose(gp - gm, g) and (gp >= 0).all() and (gm >= 0).all()
     assert np.allclose(sp - sm, 1.0)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 7, 11, 13])
+def test_weights_mirror_symmetry(k):
+    """Reflecting x -> -x maps a stencil S to -S and its cell o to -o, so the
+    weight of cell o of S at xi equals the weight of cell -o of -S at -xi:
+    as polynomials in xi, c_S[o][j] (-1)^j = c_{-S}[-o][j], exactly.  Checked
+    for every sub-stencil of width k that contains the target cell."""
+    for start in range(-(k - 1), 1):
+        offs = tuple(range(start, start + k))
+        mirror = tuple(sorted(-o for o in offs))
+        c, cm = W.recon_poly_1d(offs), W.recon_poly_1d(mirror)
+        for oi, o in enumerate(offs):
+            mi = mirror.index(-o)
+            assert [cj * (-1) ** j for j, cj in enumerate(c[oi])] == list(cm[mi])
