@@ -80,6 +80,19 @@ def flops_per_cell(order: int, scheme: str, direct: bool = False) -> float:
     return 3 * per_var + lmars + src + 15 + 18
 
 
+# Reference per-cell estimates of the method's arithmetic (separable FMA
+# formulation, FMA = 2, add/mul/div/sqrt = 1), independent of this
+# implementation's shortcuts: the roofline's headline "achieved" uses these.
+REFERENCE_FLOPS_PER_CELL = {("tpp", 3): 1100.0, ("weno", 5): 14800.0, ("tpp", 11): 14100.0}
+# the adjoint recomputes the forward point values and applies the transpose
+# of every step; its reference estimate is 2.5x the forward (range 2.5-3x)
+VJP_FACTOR = 2.5
+
+
+def reference_flops(order: int, scheme: str):
+    return REFERENCE_FLOPS_PER_CELL.get((scheme, order))
+
+
 STAGE_SOURCES = ("paper_2411_19185_amd/csrc/kernels.hip", "paper_2411_19185_amd/csrc/kernel_bodies.hpp",
                  "paper_2411_19185_amd/csrc/device_common.hpp", "paper_2411_19185_amd/csrc/hope_internal.hpp",
                  "paper_2411_19185_amd/build.py")
@@ -122,6 +135,52 @@ def measured_traffic(n, order, scheme):
                 "copy_factor_write": float(kv["copy_factor_write"])}
     except (KeyError, ValueError):
         return None
+
+
+COUNTER_FILE = "profiles/hope_weno5_c360_fp64_insts.txt"
+
+
+def measured_flops(n, order, scheme):
+    """Executed FP64 FLOPs per cell of each kernel (lane operations, FMA = 2)
+    from the committed counter summary, or None when it is missing, is for
+    another workload, or was taken from other kernel sources."""
+    path = os.path.join(ROOT, COUNTER_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv.get("source_hash") != stage_source_hash():
+            return None
+        if (int(kv["n"]), int(kv["order"]), kv["scheme"]) != (n, order, scheme):
+            return None
+        return {k[len("flops_per_cell."):]: float(v) for k, v in kv.items() if k.startswith("flops_per_cell.")}
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_info():
+    """Host CPU model, logical CPU count and torch's intra-op thread count."""
+    import torch
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "torch_threads": torch.get_num_threads(),
+            "torch_version": torch.__version__}
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def copy_calibration():
@@ -170,16 +229,17 @@ def run(args):
     # inside the timed region only the stage kernel carries HIP events (an
     # event between every launch would add a few microseconds each to the step)
     g.profile(True, only=("stage",))
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    progress(f"C{n} {scheme}{order}: timing {args.steps} SSP-RK3 steps after {args.warmup} warm-up steps")
+    evs[0].record(stream)
+    for i in range(args.steps):
         g.rk_step(q, dt, "ssp3", ws)
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     g.profile(False)
-    ms = ev0.elapsed_time(ev1)
+    ms = evs[0].elapsed_time(evs[-1])
+    step_ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
     cells = 6 * n * n
     evals = 3 * args.steps
     value = cells * evals / (ms / 1e3)
@@ -195,7 +255,17 @@ def run(args):
     edge_ms, edge_n = g.profile_read("edge_traces")
     stage_avg = st_ms / max(st_n, 1)
     fpc = flops_per_cell(order, scheme)
-    achieved = fpc * cells / (stage_avg / 1e3)
+    ref_fpc = reference_flops(order, scheme)
+    head_fpc = ref_fpc if ref_fpc is not None else fpc
+    achieved = head_fpc * cells / (stage_avg / 1e3)
+    counters = measured_flops(n, order, scheme)
+
+    def rate(f):
+        return {"flops_per_cell": f, "achieved_TFLOPs": f * cells / (stage_avg / 1e3) / 1e12,
+                "frac": f * cells / (stage_avg / 1e3) / PEAK_FP64}
+    models = {"as_implemented": rate(fpc), "point_by_point": rate(flops_per_cell(order, scheme, direct=True))}
+    if counters and "k_stage" in counters:
+        models["executed_fp64_counters"] = rate(counters["k_stage"])
     qfin = g.interior(q).double().cpu()
     finite = bool(torch.isfinite(qfin).all())
     out = {
@@ -206,6 +276,7 @@ def run(args):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
+        "step_ms": {"median": step_ms[len(step_ms) // 2], "min": step_ms[0], "max": step_ms[-1]},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -217,8 +288,11 @@ def run(args):
         "roofline": {"bound": "alu", "kernel": "k_stage", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
                      "traffic": None if traffic is None else traffic["bytes_per_launch"],
+                     "flops_per_cell": head_fpc,
+                     "flop_model": ("reference estimate of the method, separable FMA form (FMA = 2, div/sqrt = 1), "
+                                    "x cells per launch" if ref_fpc is not None else "as implemented (bench.flops_per_cell)"),
+                     "other_flop_models": models,
                      "traffic_detail": traffic, "stage_source_hash": stage_source_hash(),
-                     "flops_per_cell": fpc, "flops_per_cell_direct": flops_per_cell(order, scheme, direct=True),
                      "stage_avg_ms": stage_avg, "stage_launches": st_n,
                      "hbm_effective_GBps": stage_bytes_per_cell() * cells / (stage_avg / 1e3) / 1e9,
                      "hbm_frac": stage_bytes_per_cell() * cells / (stage_avg / 1e3) / PEAK_HBM},
@@ -228,15 +302,38 @@ def run(args):
         "setup_s": setup_s,
     }
     if not args.no_adjoint:
+        progress("forward + adjoint")
         out["fwd_vjp"] = adjoint(g, n, args, dt)
+        pair_ms = out["fwd_vjp"]["pair"]["ms"]
+        f_pair = head_fpc * (1.0 + VJP_FACTOR)
+        ach = f_pair * cells / (pair_ms / 1e3)
+        ex = None
+        if counters:
+            # the tendency's fill, traces and stage, then the adjoint's own fill and kernels
+            ex = sum(v for k, v in counters.items() if k.startswith("k_vjp") or k in
+                     ("k_fill_halo", "k_edge_traces", "k_stage")) + counters.get("k_fill_halo", 0.0)
+        out["fwd_vjp"]["roofline"] = {
+            "bound": "alu", "kernels": "tendency + hope_tendency_vjp, wall time of the pair",
+            "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP64,
+            "flops_per_cell": f_pair,
+            "flop_model": f"forward reference estimate x (1 + {VJP_FACTOR}): the adjoint recomputes the "
+                          "forward point values and applies the transpose of every step",
+            "executed_fp64_flops_per_cell": ex,
+            "executed_frac": None if ex is None else ex * cells / (pair_ms / 1e3) / PEAK_FP64}
     if not args.no_tpp11:
+        progress("TPP11 C90")
         out["tpp11_c90"] = tpp11(args)
+    if not args.no_rh:
+        progress("Rossby-Haurwitz wave at C90")
+        out["rossby_haurwitz_c90"] = rossby_haurwitz(args)
     if not args.no_ensemble:
         del g
         torch.cuda.empty_cache()
+        progress("64-member ensemble")
         out["ensemble"] = ensemble(args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(qfin, n, order, scheme)
+        progress("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(qfin, n, order, scheme, args)
     print(json.dumps(out), flush=True)
 
 
@@ -260,13 +357,14 @@ def tpp11(args):
     # the stage's work-item shape, tuned on this grid (order 11 fits one
     # workgroup per CU, so the default shape for order 5 does not carry over)
     from paper_2411_19185_amd import autotune
-    autotune.tune_grid(g, qp)
+    autotune.tune_grid(g, qp, cache=args.tune_cache or None)
     w = torch.from_numpy(hi.normal_array(args.seed + 7, (3, 6, n, n))).cuda()
     dq = torch.empty_like(w)
     gq = torch.empty_like(w)
     vws = g.vjp_workspace()
     rws = g.rk_vjp_workspace()
     ws = g.workspace()
+    tws = g.tendency_workspace()
     stream = torch.cuda.current_stream()
 
     def timed(fn, reps=10):
@@ -281,7 +379,7 @@ def tpp11(args):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
-    t_fwd = timed(lambda: g.tendency(qp, dq))
+    t_fwd = timed(lambda: g.tendency(qp, dq, tws))
     t_vjp = timed(lambda: g.tendency_vjp(qp, w, gq, vws))
     qs = qp.clone()
     t_step = timed(lambda: g.rk_step(qs, dt, "ssp3", ws))
@@ -326,7 +424,7 @@ def ensemble(args):
     setup_s = time.time() - t0
     t0 = time.time()
     with tempfile.TemporaryDirectory() as tmp:
-        sw, sh, blocks = autotune.tune_ensemble(ens, q_all, cache=os.path.join(tmp, "tune.json"))
+        sw, sh, blocks = autotune.tune_ensemble(ens, q_all, cache=args.tune_cache or os.path.join(tmp, "tune.json"))
     tune_s = time.time() - t0
     shapes = {n: [sw[ns.index(n)], sh[ns.index(n)]] for n in sizes}
     cells = sum(6 * n * n for n in ns)
@@ -394,6 +492,44 @@ def ensemble(args):
                     "hope_rk_step per member on its resolution's grid (timing only)"}
 
 
+def rossby_haurwitz(args):
+    """The wavenumber-4 Rossby-Haurwitz wave (5.9)-(5.15) at C90 (the grid of
+    the paper's order comparison), one SSP-RK3 step per timing, for TPP of
+    orders 3, 5 and 7 and WENO5 with their default launch shapes."""
+    import torch
+
+    import hope_inputs as hi
+    from paper_2411_19185_amd import Grid, workloads
+
+    n = 90
+    a = hi.PAPER_RADIUS
+    q = workloads.cell_average(hi.RossbyHaurwitz(radius=a), n, radius=a)
+    dt = workloads.cfl_dt(q, radius=a)
+    cells = 6 * n * n
+    stream = torch.cuda.current_stream()
+    out = {"cells": cells, "dt_s": dt, "unit": "cell-tendency evals/s", "steps": args.rh_steps, "by_scheme": {}}
+    for order, scheme in ((3, "tpp"), (5, "tpp"), (7, "tpp"), (5, "weno")):
+        g = Grid(n, order, scheme, radius=a)
+        qp = g.new_state()
+        g.interior(qp).copy_(torch.from_numpy(q))
+        ws = g.workspace()
+        for _ in range(3):
+            g.rk_step(qp, dt, "ssp3", ws)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(args.rh_steps):
+            g.rk_step(qp, dt, "ssp3", ws)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / args.rh_steps
+        out["by_scheme"][f"{scheme}{order}"] = {"ms_per_step": ms, "value": 3 * cells / (ms / 1e3),
+                                                "launch": list(g.get_launch()),
+                                                "state_finite": bool(torch.isfinite(qp).all())}
+        del g, qp, ws
+    return out
+
+
 def adjoint(g, n, args, dt):
     """Forward+adjoint throughput: (1) tendency + hope_tendency_vjp pairs on
     one state, (2) the adjoint rollout of a height-mismatch loss."""
@@ -409,10 +545,11 @@ def adjoint(g, n, args, dt):
     qp = g.new_state()
     g.interior(qp).copy_(q0)
     ws = g.vjp_workspace()
+    tws = g.tendency_workspace()
     dq = torch.empty(3, 6, n, n, dtype=torch.float64, device="cuda")
     gq = torch.empty_like(dq)
     for _ in range(2):
-        g.tendency(qp, dq)
+        g.tendency(qp, dq, tws)
         g.tendency_vjp(qp, w, gq, ws)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -420,7 +557,7 @@ def adjoint(g, n, args, dt):
     ev[0].record(stream)
     reps = args.vjp_reps
     for _ in range(reps):
-        g.tendency(qp, dq)
+        g.tendency(qp, dq, tws)
         g.tendency_vjp(qp, w, gq, ws)
     ev[1].record(stream)
     torch.cuda.synchronize()
@@ -484,30 +621,64 @@ def adjoint(g, n, args, dt):
     }
 
 
-def cpu_baseline(q, n, order, scheme, evals=2):
-    """The FP64 oracle on the host cores: full right-hand-side evaluations
-    (ghost fixed point, reconstruction, LMARS, quadrature) of the same grid
-    and state, as it stands (not tuned)."""
+def cpu_baseline(q, n, order, scheme, args, evals=2):
+    """The FP64 oracle on the host cores, as it stands (not tuned): full
+    right-hand-side evaluations (ghost fixed point, reconstruction, LMARS,
+    quadrature) of the benchmark grid and its final state on all threads
+    (the headline value); one evaluation at C90 of the same scheme on one
+    thread; and the oracle's autograd adjoint (forward + backward of
+    <w, dq/dt>) at C12 and C90 TPP11 and at C90 WENO5."""
     import torch
 
+    import hope_inputs as hi
+    from oracle.ic import cell_average
     from oracle.rhs import Grid as OracleGrid
     from oracle.rhs import Params
+    info = cpu_info()
     threads = torch.get_num_threads()
     og = OracleGrid(n, order, scheme, Params())
     t0 = time.time()
     for _ in range(evals):
         og.tendency(q)
     sec = time.time() - t0
-    return {"value": evals * 6 * n * n / sec, "unit": "cell-tendency evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{evals} full RHS evaluations at C{n} (6x{n}x{n} cells) of the final benchmark state, "
-                      f"{sec:.1f} s"}
+    out = {"value": evals * 6 * n * n / sec, "unit": "cell-tendency evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"{evals} full RHS evaluations at C{n} (6x{n}x{n} cells) of the final benchmark state, "
+                     f"{sec:.1f} s on {threads} threads", **info}
+    if args.cpu_extra:
+        radius = hi.EARTH_RADIUS
+        q90 = cell_average(hi.RestingLayer(seed=args.seed, with_cap=False), 90, radius, nq=2)
+        og90 = OracleGrid(90, order, scheme, Params())
+        torch.set_num_threads(1)
+        try:
+            t0 = time.time()
+            og90.tendency(q90)
+            sec1 = time.time() - t0
+        finally:
+            torch.set_num_threads(threads)
+        out["one_thread"] = {"value": 6 * 90 * 90 / sec1, "unit": "cell-tendency evals/s", "cores": 1,
+                             "sample": f"1 RHS evaluation at C90 {scheme.upper()}{order}, {sec1:.1f} s"}
+        vjp = {}
+        for nn, k, sch in ((12, 11, "tpp"), (90, 11, "tpp"), (90, 5, "weno")):
+            f = hi.BalancedFlow(alpha=hi.draw_tilt(args.seed), radius=radius)
+            qq = cell_average(f, nn, radius, nq=2)
+            qq = qq * (1.0 + 1e-3 * torch.tensor(hi.normal_array(args.seed + 1000, tuple(qq.shape))))
+            w = torch.tensor(hi.normal_array(args.seed + 7, tuple(qq.shape)))
+            ogv = OracleGrid(nn, k, sch, Params(alpha=f.alpha))
+            x = qq.clone().requires_grad_(True)
+            t0 = time.time()
+            (ogv.tendency(x) * w).sum().backward()
+            secv = time.time() - t0
+            vjp[f"C{nn}_{sch}{k}"] = {"value": 6 * nn * nn / secv, "unit": "cell-(tendency+VJP) evals/s",
+                                      "seconds": secv, "cores": threads}
+        out["autograd_vjp"] = vjp
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=360)
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--scheme", default="weno")
@@ -517,6 +688,11 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-tpp11", action="store_true")
+    ap.add_argument("--no-rh", action="store_true", help="skip the Rossby-Haurwitz throughput section")
+    ap.add_argument("--rh-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-extra", dest="cpu_extra", action="store_false",
+                    help="CPU baseline: only the headline all-thread forward evaluations")
+    ap.add_argument("--tune-cache", default="", help="autotuner cache file (default: a fresh one per run)")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--ensemble-steps", type=int, default=50)
     ap.add_argument("--no-ensemble-vjp", dest="ensemble_vjp", action="store_false")

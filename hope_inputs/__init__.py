@@ -226,3 +226,154 @@ def normal_array(seed: int, shape) -> np.ndarray:
 
 def uniform_array(seed: int, shape, lo=-1.0, hi=1.0) -> np.ndarray:
     return np.random.default_rng(seed).uniform(lo, hi, shape)
+
+
+# --------------------------------------------------------------------------
+# Rossby-Haurwitz wave with wavenumber R = 4, eqs (5.9)-(5.15).
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class RossbyHaurwitz:
+    """phi = phi0 + a^2 [A(th) + B(th) cos(R lam) + C(th) cos(2 R lam)] (5.10),
+    us = a w cos th + a K cos^(R-1) th (R sin^2 th - cos^2 th) cos(R lam) (5.11),
+    vs = -a K R cos^(R-1) th sin th sin(R lam) (5.12), with A, B, C of
+    (5.13)-(5.15), K = w = 7.848e-6 1/s, h0 = 8000 m.  ``shift`` rotates
+    the pattern eastwards by that many radians (the pattern at time t is,
+    for the barotropic vorticity equation, the initial one shifted by c t
+    with the angular phase speed c of (5.9))."""
+
+    radius: float = PAPER_RADIUS
+    omega: float = OMEGA
+    w: float = 7.848e-6
+    wavenumber: int = 4
+    h0: float = 8000.0
+    gravity: float = GRAVITY
+    shift: float = 0.0
+
+    @property
+    def phase_speed(self) -> float:
+        """Angular phase speed c of (5.9), rad/s."""
+        R = self.wavenumber
+        return (R * (R + 3) * self.w - 2.0 * self.omega) / ((R + 1) * (R + 2))
+
+    def __call__(self, p):
+        lam, th = lonlat(p)
+        lam = lam - self.shift
+        R, w, K, a, Om = self.wavenumber, self.w, self.w, self.radius, self.omega
+        c, s = np.cos(th), np.sin(th)
+        c2 = c * c
+        # cos^(2R) th times the bracket of (5.13), with its cos^-2 th term folded
+        # into the power so that the poles need no division
+        A = 0.5 * w * (2.0 * Om + w) * c2 + 0.25 * K * K * (
+            (R + 1) * c ** (2 * R + 2) + (2.0 * R * R - R - 2.0) * c ** (2 * R) - 2.0 * R * R * c ** (2 * R - 2))
+        B = 2.0 * (Om + w) * K / ((R + 1) * (R + 2)) * c ** R * (R * R + 2 * R + 2 - (R + 1) ** 2 * c2)
+        C = 0.25 * K * K * c ** (2 * R) * ((R + 1) * c2 - R - 2.0)
+        phi = self.gravity * self.h0 + a * a * (A + B * np.cos(R * lam) + C * np.cos(2 * R * lam))
+        us = a * w * c + a * K * c ** (R - 1) * (R * s * s - c2) * np.cos(R * lam)
+        vs = -a * K * R * c ** (R - 1) * s * np.sin(R * lam)
+        return phi, us, vs
+
+
+# --------------------------------------------------------------------------
+# Bottom topography (section 2, (2.13)-(2.14)) and the states over it.  A
+# surface is a callable phis(p) -> surface geopotential g h_s (m^2/s^2).  A
+# field over topography returns the layer's own geopotential phi = g h
+# (depth), so that phi + phis is the total (free-surface) geopotential.
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class ConeMountain:
+    """The isolated mountain of section 5.2, (5.8): h_s = h_s0 (1 - r/R) with
+    r = sqrt(min(R^2, (lam - lam_c)^2 + (th - th_c)^2)), h_s0 = 2000 m,
+    R = pi/9, (lam_c, th_c) = (3 pi/2, pi/6); longitudes in [0, 2 pi).  Its
+    slope is discontinuous at the peak and along the rim."""
+
+    hs0: float = 2000.0
+    R: float = math.pi / 9
+    lam_c: float = 1.5 * math.pi
+    th_c: float = math.pi / 6
+    gravity: float = GRAVITY
+
+    def __call__(self, p):
+        lam, th = lonlat(p)
+        lam = np.mod(lam, 2.0 * math.pi)
+        r = np.sqrt(np.minimum(self.R ** 2, (lam - self.lam_c) ** 2 + (th - self.th_c) ** 2))
+        return self.gravity * self.hs0 * (1.0 - r / self.R)
+
+
+@dataclass(frozen=True)
+class MountainFlow:
+    """Initial state of section 5.2: the zonal flow of (5.1)-(5.3) with
+    h0 = 5960 m and u0 = 20 m/s (untilted), whose free surface follows the
+    balanced profile, over the cone: depth phi = phi_total - phis."""
+
+    radius: float = PAPER_RADIUS
+    omega: float = OMEGA
+    gravity: float = GRAVITY
+    h0: float = 5960.0
+    u0: float = 20.0
+
+    @property
+    def surface(self):
+        return ConeMountain(gravity=self.gravity)
+
+    def __call__(self, p):
+        lam, th = lonlat(p)
+        s = np.sin(th)
+        phit = self.gravity * self.h0 - (self.radius * self.omega * self.u0 + 0.5 * self.u0 ** 2) * s * s
+        us = self.u0 * np.cos(th)
+        return phit - self.surface(p), us, np.zeros_like(us)
+
+
+@dataclass(frozen=True)
+class LakeAtRest:
+    """Fluid at rest with a flat free surface over a surface: depth
+    phi = phit0 - phis, no wind.  The exact state whose preservation is the
+    "C-property" of section 2."""
+
+    surface: object
+    phit0: float = GRAVITY * 5960.0
+
+    def __call__(self, p):
+        z = np.zeros(p.shape[:-1])
+        return self.phit0 - self.surface(p), z, z.copy()
+
+
+@dataclass(frozen=True)
+class AxisRidge:
+    """A smooth ridge that is constant along the circles about an axis tilted
+    by alpha (the flow lines of the tilted balanced flow):
+    phis = g h_r exp(-((s - s0)/w)^2), s = -cos(lam)cos(th)sin(alpha) + sin(th)cos(alpha)."""
+
+    alpha: float = 0.0
+    h_r: float = 400.0
+    s0: float = 0.3
+    width: float = 0.4
+    gravity: float = GRAVITY
+
+    def __call__(self, p):
+        lam, th = lonlat(p)
+        ca, sa = math.cos(self.alpha), math.sin(self.alpha)
+        s = -np.cos(lam) * np.cos(th) * sa + np.sin(th) * ca
+        return self.gravity * self.h_r * np.exp(-((s - self.s0) / self.width) ** 2)
+
+
+@dataclass(frozen=True)
+class BalancedFlowOverRidge:
+    """An exact steady state with topography: the tilted balanced flow of
+    (5.1)-(5.3) whose free surface is the balanced profile, over an AxisRidge
+    about the same axis, depth phi = phi_balanced - phis.  The ridge is
+    constant along the (non-divergent) flow lines, so the mass flux divergence
+    is unchanged, and the momentum balance involves only the total
+    geopotential (2.13)-(2.14), which is that of the balanced flow."""
+
+    alpha: float = 0.0
+    radius: float = EARTH_RADIUS
+    omega: float = OMEGA
+    gravity: float = GRAVITY
+
+    @property
+    def surface(self):
+        return AxisRidge(alpha=self.alpha, gravity=self.gravity)
+
+    def __call__(self, p):
+        phi, us, vs = BalancedFlow(alpha=self.alpha, radius=self.radius, omega=self.omega)(p)
+        return phi - self.surface(p), us, vs

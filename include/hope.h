@@ -25,12 +25,15 @@
  *
  * Ownership.  Every state, tendency, cotangent and workspace buffer is a
  * device allocation owned by the caller; hope_grid_layout gives the sizes.
- * The grid owns only its constant tables and a small scratch buffer for
- * panel-edge traces, allocated by hope_grid_create; no call allocates
- * afterwards.  Forward calls (hope_tendency, hope_rk_step) that use the same
- * grid must not run concurrently on different streams (they share that
- * scratch); the adjoint calls use only the caller's workspace.  Grids are
- * otherwise independent.
+ * The grid owns only its constant tables, allocated by hope_grid_create, and
+ * no call allocates afterwards.  Every scratch buffer a call needs (the
+ * panel-edge traces of a stage, the stage states of a Runge-Kutta step, the
+ * adjoint's intermediates) comes from the workspace the caller passes, so a
+ * grid is read-only once created: calls on one grid may run concurrently on
+ * different streams, as long as each has its own state, output and workspace
+ * buffers.  The exceptions are the calls that change the grid
+ * (hope_grid_set_launch, hope_grid_profile), which must not overlap other
+ * calls on it, and hope_check_state, whose concurrent calls take turns.
  *
  * Errors.  Every int-returning function returns HOPE_OK (0) or a negative
  * status; a thread-local message is available from hope_last_error().
@@ -104,7 +107,8 @@ typedef struct hope_layout {
   int32_t n, r, padded, n_gauss;
   int64_t state_elems;      /* 3*6*P*P: one padded state */
   int64_t interior_elems;   /* 3*6*n*n: one unpadded field */
-  int64_t rk_workspace_bytes;  /* workspace of hope_rk_step */
+  int64_t rk_workspace_bytes;  /* workspace of hope_rk_step: two padded states, then
+                                  tendency_workspace_bytes */
   int64_t vjp_workspace_bytes;     /* workspace of hope_tendency_vjp */
   int64_t rk_vjp_workspace_bytes;  /* workspace of hope_rk_step_vjp */
   int64_t ghost_cells;      /* ghost cells per variable, all panels */
@@ -112,6 +116,9 @@ typedef struct hope_layout {
   int64_t device_bytes;     /* device memory owned by the grid (tables, maps, scratch) */
   int32_t ghost_sweeps;     /* sweeps of the ghost-map build (ghost_iters if set) */
   int32_t tables_cached;    /* 1 if the host tables were read from cache_dir */
+  int64_t tendency_workspace_bytes;  /* workspace of hope_tendency: the panel-edge
+                                        traces of one stage, 8 * 24 * n * n_gauss * 3
+                                        bytes rounded up to 256 */
 } hope_layout;
 
 /* Build a grid: equiangular metrics, reconstruction and WENO tables, the
@@ -146,8 +153,9 @@ int hope_fill_halo(const hope_grid* grid, double* q, void* stream);
  * number, or whose momentum (variables 1, 2) is not finite.  Ghost rings are
  * not read.  The count goes to *n_bad (host memory, may be NULL).  Waits for
  * the work queued on the stream before it, so call it between steps, not
- * inside a captured graph.  It uses a counter in the grid's scratch, like
- * the forward calls.  Returns HOPE_ERR_NUMERIC when the count is not zero,
+ * inside a captured graph.  It counts in a word the grid owns; calls from
+ * several threads take turns on it (a lock held until the count is read).
+ * Returns HOPE_ERR_NUMERIC when the count is not zero,
  * else HOPE_OK. */
 int hope_check_state(const hope_grid* grid, const double* q, int64_t* n_bad, void* stream);
 
@@ -156,8 +164,12 @@ int hope_check_state(const hope_grid* grid, const double* q, int64_t* n_bad, voi
  * points (TPP or genuine 2D WENO), takes the neighbour panel's converted
  * trace at panel edges (3.26)-(3.29), evaluates the LMARS flux (3.30)-(3.38)
  * with upwind term |m|(q_R - q_L), integrates fluxes (3.5) and the metric and
- * Coriolis sources (2.2)-(2.3) (3.6), and writes dqdt [3][6][n][n]. */
-int hope_tendency(const hope_grid* grid, double* q, double* dqdt, void* stream);
+ * Coriolis sources (2.2)-(2.3) (3.6), and writes dqdt [3][6][n][n].
+ * ws: caller-owned device scratch of at least layout.tendency_workspace_bytes
+ * (the converted neighbour traces at the panel-edge points); its contents
+ * are overwritten and need not be kept.  Returns HOPE_ERR_INVALID for a null
+ * or misaligned buffer or a workspace that is too small. */
+int hope_tendency(const hope_grid* grid, double* q, double* dqdt, double* ws, size_t ws_bytes, void* stream);
 
 /* Vector-Jacobian product of hope_tendency: given w = dL/d(dqdt) [3][6][n][n]
  * writes gq = dL/dq over the interior cells [3][6][n][n] (overwritten), the
@@ -172,14 +184,16 @@ int hope_tendency_vjp(const hope_grid* grid, double* q, const double* w, double*
 /* One three-stage Runge-Kutta step (section 3.5) in place on the padded
  * state q: HOPE_RK_SSP3 (Shu-Osher), or HOPE_RK_WS3 (3.39)-(3.41) with the
  * second stage from q^n.  ws: device workspace of at least
- * layout.rk_workspace_bytes (two padded states). */
+ * layout.rk_workspace_bytes (two padded stage states and the panel-edge
+ * traces). */
 int hope_rk_step(const hope_grid* grid, double* q, double dt, int32_t scheme, double* ws,
                  size_t ws_bytes, void* stream);
 
 /* Vector-Jacobian product of one hope_rk_step from the state q = q^n
  * (padded; its ghost rings are scratch, its interior is read only): given
  * gout = dL/dq^{n+1} [3][6][n][n] writes gin = dL/dq^n [3][6][n][n]
- * (gin must not alias gout).  The stage states are recomputed.  ws: at least
+ * (gin must not alias gout).  The stage states are recomputed, with their
+ * panel-edge traces in the workspace too.  ws: at least
  * layout.rk_vjp_workspace_bytes. */
 int hope_rk_step_vjp(const hope_grid* grid, double* q, double dt, int32_t scheme, const double* gout,
                      double* gin, double* ws, size_t ws_bytes, void* stream);

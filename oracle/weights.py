@@ -179,6 +179,26 @@ def axis_weights(offsets: tuple, m: int) -> np.ndarray:
     return np.array([[float(v) for v in weights_1d_mp(offsets, x)] for x in edge_points_mp(m)])
 
 
+def derivative_weights_1d_mp(offsets, xi) -> list:
+    """d/dxi of the weights of weights_1d_mp at xi (mpmath): the derivative
+    of the reconstruction polynomial (3.14) at xi from the cell averages."""
+    coef = recon_poly_1d(tuple(offsets))
+    x = mp.mpf(xi) if not isinstance(xi, Fraction) else mp.mpf(xi.numerator) / xi.denominator
+    out = []
+    for row in coef:
+        v = mp.mpf(0)
+        for j in range(len(row) - 1, 0, -1):
+            v = v * x + j * mp.mpf(row[j].numerator) / row[j].denominator
+        out.append(v)
+    return out
+
+
+@lru_cache(maxsize=None)
+def axis_derivative_weights(offsets: tuple, m: int) -> np.ndarray:
+    """(2+m, k) FP64 derivative weights of a stencil at the 2+m axis coordinates."""
+    return np.array([[float(v) for v in derivative_weights_1d_mp(offsets, x)] for x in edge_points_mp(m)])
+
+
 # ----------------------------------------------------------------------------
 # Genuine 2D WENO: linear weights by least squares (3.16)-(3.20)
 # ----------------------------------------------------------------------------

@@ -63,6 +63,7 @@ class Layout(ctypes.Structure):
         ("device_bytes", ctypes.c_int64),
         ("ghost_sweeps", ctypes.c_int32),
         ("tables_cached", ctypes.c_int32),
+        ("tendency_workspace_bytes", ctypes.c_int64),
     ]
 
 
@@ -90,7 +91,7 @@ _SIGS = {
     "hope_grid_layout": (_I32, [_P, ctypes.POINTER(Layout)]),
     "hope_fill_halo": (_I32, [_P, _P, _P]),
     "hope_check_state": (_I32, [_P, _P, ctypes.POINTER(ctypes.c_int64), _P]),
-    "hope_tendency": (_I32, [_P, _P, _P, _P]),
+    "hope_tendency": (_I32, [_P, _P, _P, _P, ctypes.c_size_t, _P]),
     "hope_tendency_vjp": (_I32, [_P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "hope_rk_step": (_I32, [_P, _P, ctypes.c_double, _I32, _P, ctypes.c_size_t, _P]),
     "hope_rk_step_vjp": (_I32, [_P, _P, ctypes.c_double, _I32, _P, _P, _P, ctypes.c_size_t, _P]),

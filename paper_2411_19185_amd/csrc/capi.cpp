@@ -62,18 +62,16 @@ struct Timed {
 };
 }  // namespace
 
-// The grid's scratch: panel-edge traces (24 n m x 3 doubles), then the
-// counter of hope_check_state.
+// The grid's one mutable word: the counter of hope_check_state.  Every
+// other scratch buffer of a call comes from the caller's workspace.
 static int alloc_scratch(hope_grid* G) {
-  const size_t traces = 24 * (size_t)G->h.n * G->h.m * 3;
-  const size_t bytes = sizeof(double) * traces + 256;
+  const size_t bytes = 256;
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc (grid scratch)");
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc (check_state counter)");
   G->allocs.push_back(p);
   G->device_bytes += bytes;
-  G->bt = static_cast<double*>(p);
-  G->bad = reinterpret_cast<unsigned long long*>(G->bt + traces);
+  G->bad = static_cast<unsigned long long*>(p);
   return 0;
 }
 
@@ -367,7 +365,8 @@ int hope_grid_layout(const hope_grid* G, hope_layout* out) {
   out->n_gauss = h.m;
   out->state_elems = 18LL * h.P * h.P;
   out->interior_elems = 18LL * h.n * h.n;
-  out->rk_workspace_bytes = 2 * out->state_elems * (int64_t)sizeof(double);
+  out->tendency_workspace_bytes = (int64_t)trace_bytes(h);
+  out->rk_workspace_bytes = 2 * out->state_elems * (int64_t)sizeof(double) + out->tendency_workspace_bytes;
   {
     size_t nT, nD, nG;
     out->vjp_workspace_bytes = (int64_t)(vjp_elems(G->h, &nT, &nD, &nG) * sizeof(double));
@@ -396,6 +395,9 @@ int hope_check_state(const hope_grid* G, const double* q, int64_t* n_bad, void* 
   if (!G || !q) return fail(HOPE_ERR_INVALID, "null argument");
   if (reinterpret_cast<uintptr_t>(q) % 8) return fail(HOPE_ERR_INVALID, "misaligned state");
   hipStream_t s = (hipStream_t)stream;
+  // the counter is the grid's: concurrent calls take turns (each ends with a
+  // wait for its stream, so its counter use is over when it unlocks)
+  std::lock_guard<std::mutex> lock(G->check_mu);
   hipError_t e = hipMemsetAsync(G->bad, 0, sizeof(unsigned long long), s);
   if (e != hipSuccess) return hip_fail(e, "check_state clear");
   int le = launch_check_state(q, G->h.n, G->h.r, G->bad, stream);
@@ -410,8 +412,10 @@ int hope_check_state(const hope_grid* G, const double* q, int64_t* n_bad, void* 
   return HOPE_OK;
 }
 
+// one stage: ghost fill, panel-edge traces into bt (the caller's scratch,
+// trace_elems doubles), fused stage kernel
 static int run_stage(const hope_grid* G, double* q, const double* qn, double* out, int out_padded, double ca,
-                     double cb, double cc, void* stream) {
+                     double cb, double cc, double* bt, void* stream) {
   int e;
   {
     Timed tm(G, 0, stream);
@@ -420,23 +424,25 @@ static int run_stage(const hope_grid* G, double* q, const double* qn, double* ou
   if (e) return hip_fail((hipError_t)e, "fill_halo launch");
   {
     Timed tm(G, 1, stream);
-    e = launch_edge_traces(G->h.k, G->h.weno, G->tab, G->itab, G->gs, q, G->bt, stream);
+    e = launch_edge_traces(G->h.k, G->h.weno, G->tab, G->itab, G->gs, q, bt, stream);
   }
   if (e) return hip_fail((hipError_t)e, "edge_traces launch");
   {
     Timed tm(G, 2, stream);
-    e = launch_stage(G->h.k, G->h.weno, G->tab, G->itab, G->gs, q, qn, out, out_padded, ca, cb, cc, G->bt,
+    e = launch_stage(G->h.k, G->h.weno, G->tab, G->itab, G->gs, q, qn, out, out_padded, ca, cb, cc, bt,
                      G->strip_w, G->seg_h, stream);
   }
   if (e) return hip_fail((hipError_t)e, "stage launch");
   return HOPE_OK;
 }
 
-int hope_tendency(const hope_grid* G, double* q, double* dqdt, void* stream) {
-  if (!G || !q || !dqdt) return fail(HOPE_ERR_INVALID, "null argument");
-  if (reinterpret_cast<uintptr_t>(q) % 8 || reinterpret_cast<uintptr_t>(dqdt) % 8)
+int hope_tendency(const hope_grid* G, double* q, double* dqdt, double* ws, size_t ws_bytes, void* stream) {
+  if (!G || !q || !dqdt || !ws) return fail(HOPE_ERR_INVALID, "null argument");
+  if (reinterpret_cast<uintptr_t>(q) % 8 || reinterpret_cast<uintptr_t>(dqdt) % 8 ||
+      reinterpret_cast<uintptr_t>(ws) % 8)
     return fail(HOPE_ERR_INVALID, "misaligned buffer");
-  return run_stage(G, q, nullptr, dqdt, 0, 0.0, 0.0, 1.0, stream);
+  if (ws_bytes < trace_elems(G->h) * sizeof(double)) return fail(HOPE_ERR_INVALID, "workspace too small");
+  return run_stage(G, q, nullptr, dqdt, 0, 0.0, 0.0, 1.0, ws, stream);
 }
 
 int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq, double* ws, size_t ws_bytes,
@@ -520,9 +526,10 @@ int hope_rk_step_vjp(const hope_grid* G, double* q, double dt, int32_t scheme, c
   double* v = cur + field;
   double* vws = v + field;
   int st;
-  // recompute the stage states
-  if ((st = run_stage(G, q, nullptr, q1, 1, 0.0, b[0], c[0], stream))) return st;
-  if ((st = run_stage(G, q1, q, q2, 1, a[1], b[1], c[1], stream))) return st;
+  // recompute the stage states (their panel-edge traces use the start of the
+  // adjoint's scratch, which the reverse sweep overwrites only after them)
+  if ((st = run_stage(G, q, nullptr, q1, 1, 0.0, b[0], c[0], vws, stream))) return st;
+  if ((st = run_stage(G, q1, q, q2, 1, a[1], b[1], c[1], vws, stream))) return st;
   // reverse sweep: cur = dL/dq_{s+1}; gin accumulates dL/dq_0
   double* qs[3] = {q, q1, q2};
   int e = launch_combine(field, cur, gout, nullptr, nullptr, 1.0, 0.0, 0.0, stream);
@@ -542,21 +549,38 @@ int hope_rk_step_vjp(const hope_grid* G, double* q, double dt, int32_t scheme, c
 int hope_rk_step(const hope_grid* G, double* q, double dt, int32_t scheme, double* ws, size_t ws_bytes,
                  void* stream) {
   if (!G || !q || !ws) return fail(HOPE_ERR_INVALID, "null argument");
+  return rk_step_ws(G, q, dt, scheme, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+size_t hope::rk_workspace_bytes(const hope_grid* G) {
+  return 2 * 18ULL * G->h.P * G->h.P * sizeof(double) + trace_bytes(G->h);
+}
+
+int hope::rk_step_ws(const hope_grid* G, double* q, double dt, int scheme, double* ws, size_t ws_bytes,
+                     void* stream) {
   if (scheme != HOPE_RK_SSP3 && scheme != HOPE_RK_WS3) return fail(HOPE_ERR_INVALID, "bad RK scheme");
   const size_t state = 18ULL * G->h.P * G->h.P;
-  if (ws_bytes < 2 * state * sizeof(double)) return fail(HOPE_ERR_INVALID, "workspace too small");
+  if (ws_bytes < 2 * state * sizeof(double) + trace_elems(G->h) * sizeof(double))
+    return fail(HOPE_ERR_INVALID, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(q) % 8 || reinterpret_cast<uintptr_t>(ws) % 8)
+    return fail(HOPE_ERR_INVALID, "misaligned buffer");
   if (!std::isfinite(dt)) return fail(HOPE_ERR_INVALID, "dt not finite");
   double* w0 = ws;
   double* w1 = ws + state;
+  double* bt = ws + 2 * state;
   double a[3], b[3], c[3];
   rk_coefs(scheme, a, b, c);
   for (double& x : c) x *= dt;
   int st;
-  if ((st = run_stage(G, q, nullptr, w0, 1, a[0], b[0], c[0], stream))) return st;
-  if ((st = run_stage(G, w0, q, w1, 1, a[1], b[1], c[1], stream))) return st;
-  if ((st = run_stage(G, w1, q, q, 1, a[2], b[2], c[2], stream))) return st;
+  if ((st = run_stage(G, q, nullptr, w0, 1, a[0], b[0], c[0], bt, stream))) return st;
+  if ((st = run_stage(G, w0, q, w1, 1, a[1], b[1], c[1], bt, stream))) return st;
+  if ((st = run_stage(G, w1, q, q, 1, a[2], b[2], c[2], bt, stream))) return st;
   return HOPE_OK;
 }
+
+extern "C" {
 
 int hope_grid_set_launch(hope_grid* G, int32_t strip_w, int32_t seg_h) {
   if (!G) return fail(HOPE_ERR_INVALID, "null argument");

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,8 +18,8 @@ struct hope_grid {
   hope::GhostDev g{};
   std::vector<void*> allocs;
   size_t device_bytes = 0;
-  double* bt = nullptr;      // panel-edge trace scratch, 24*n*m*3
-  unsigned long long* bad = nullptr;   // hope_check_state's counter, after bt
+  unsigned long long* bad = nullptr;   // hope_check_state's counter
+  mutable std::mutex check_mu;         // held by hope_check_state from clearing the counter to reading it
   int strip_w = 62, seg_h = 8;
   bool tables_cached = false;   // host tables read from a cache file
   // G^T by the interior cells some ghost row reads (adjoint of the ghost fill)
@@ -46,4 +47,13 @@ const char* last_error();
 void rk_coefs(int scheme, double a[3], double b[3], double cs[3]);
 // strips of at most 62 columns, balanced over n
 void balanced_strip(int n, int* strip_w, int* strips);
+// one Runge-Kutta step of hope_rk_step with the workspace ws (stage states,
+// then panel-edge traces); checks everything but the null pointers
+int rk_step_ws(const hope_grid* G, double* q, double dt, int scheme, double* ws, size_t ws_bytes, void* stream);
+// bytes of that workspace
+size_t rk_workspace_bytes(const hope_grid* G);
+// elements of the panel-edge trace scratch of one stage: 24 panel sides x n x m points x 3 variables
+inline size_t trace_elems(const HostTables& h) { return 24 * (size_t)h.n * h.m * 3; }
+// bytes of that scratch, rounded up to 256
+inline size_t trace_bytes(const HostTables& h) { return (trace_elems(h) * sizeof(double) + 255) / 256 * 256; }
 }  // namespace hope

@@ -100,12 +100,18 @@ class Grid:
         check(lib().hope_fill_halo(self._h, _ptr(q), _stream()))
         return q
 
-    def tendency(self, q: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    def tendency(self, q: torch.Tensor, out: torch.Tensor | None = None,
+                 ws: torch.Tensor | None = None) -> torch.Tensor:
+        """dq/dt (interior) of the padded state q; its ghost rings are
+        overwritten.  ws: scratch of tendency_workspace() size, else one is
+        allocated for the call."""
         self._check_padded(q)
         if out is None:
             out = torch.empty(3, 6, self.n, self.n, dtype=torch.float64, device=q.device)
         self._check_field(out)
-        check(lib().hope_tendency(self._h, _ptr(q), _ptr(out), _stream()))
+        if ws is None:
+            ws = self.tendency_workspace()
+        check(lib().hope_tendency(self._h, _ptr(q), _ptr(out), _ptr(ws), ws.numel() * 8, _stream()))
         return out
 
     def tendency_vjp(self, q: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None,
@@ -121,6 +127,9 @@ class Grid:
             ws = self.vjp_workspace()
         check(lib().hope_tendency_vjp(self._h, _ptr(q), _ptr(w), _ptr(out), _ptr(ws), ws.numel() * 8, _stream()))
         return out
+
+    def tendency_workspace(self) -> torch.Tensor:
+        return torch.empty(self.layout.tendency_workspace_bytes // 8, dtype=torch.float64, device="cuda")
 
     def workspace(self) -> torch.Tensor:
         return torch.empty(self.layout.rk_workspace_bytes // 8, dtype=torch.float64, device="cuda")

@@ -68,7 +68,13 @@ def smooth_perturbed_balanced(n, seed=0, nq=4):
     return alpha, q * (1.0 + 1e-2 * smooth_cell_field(n, seed + 3000))
 
 
-STATES = {"balanced": balanced, "dam_break": dam_break, "smooth_random": smooth_random, "member": member,
+def rossby_haurwitz(n, seed=0, nq=4):
+    """The wavenumber-4 Rossby-Haurwitz wave of (5.10)-(5.12) (no seeded
+    part; seed unused), at the radius the other states use."""
+    return 0.0, cell_average(hi.RossbyHaurwitz(radius=A), n, A, nq=nq)
+
+
+STATES = {"rossby_haurwitz": rossby_haurwitz, "balanced": balanced, "dam_break": dam_break, "smooth_random": smooth_random, "member": member,
           "perturbed_balanced": perturbed_balanced, "perturbed_member": perturbed_member,
           "smooth_perturbed_balanced": smooth_perturbed_balanced}
 

@@ -38,6 +38,10 @@ CASES = [
     (5, 5, "weno", "dam_break", 26),
     (9, 9, "tpp", "perturbed_balanced", 27),
     (11, 11, "tpp", "member", 28),
+    # the Rossby-Haurwitz wave of section 5.3 at the orders of its figures
+    (45, 3, "tpp", "rossby_haurwitz", 0),
+    (45, 9, "tpp", "rossby_haurwitz", 0),
+    (32, 5, "weno", "rossby_haurwitz", 0),
 ]
 
 
@@ -99,6 +103,50 @@ def test_launch_shape_does_not_change_results(sw, sh):
     other = g.tendency(to_padded(q, g.r))
     torch.cuda.synchronize()
     assert torch.equal(base, other)
+
+
+@pytest.mark.parametrize("order", [7, 11, 13])
+def test_launch_shape_does_not_change_results_high_orders(order):
+    """The TPP orders whose stage kernel takes other paths (all cell nodes at
+    order 7, chunks of node columns at 11 and 13): full strips (more than 30
+    columns, one per workgroup, including a ragged second strip), half strips
+    and one-row segments all give bitwise the same tendency."""
+    n = 40
+    print(f"case n={n} TPP{order} launch shapes", flush=True)
+    alpha, q = STATES["perturbed_member"](n, 70 + order)
+    g = _gpu_grid(n, order, "tpp", alpha)
+    assert g.get_launch()[0] > 30            # the default is one full strip of 40 columns
+    base = g.tendency(to_padded(q, g.r))
+    for sw, sh in [(40, 40), (33, 5), (20, 3), (13, 1), (62, 7)]:
+        g.set_launch(sw, sh)
+        other = g.tendency(to_padded(q, g.r))
+        torch.cuda.synchronize()
+        assert torch.equal(base, other), (sw, sh)
+
+
+@pytest.mark.parametrize("n,order,launches", [(45, 11, [None]), (45, 13, [None]), (90, 11, [None, (45, 4)])])
+def test_high_order_full_strips_match_oracle(n, order, launches):
+    """TPP11 and TPP13 on the grids where the stage runs full strips of more
+    than 30 columns (C45 by default; C90 TPP11, the timing grid of the
+    differentiation configuration, with its default half strips and with a
+    full-strip shape the autotuner may choose), element by element against
+    the oracle."""
+    print(f"case C{n} TPP{order} launches={launches}", flush=True)
+    alpha, q = STATES["perturbed_balanced"](n, 80 + order, nq=2)
+    og = oracle_grid(n, order, "tpp", alpha)
+    ref = og.tendency(q)
+    print("oracle done", flush=True)
+    g = _gpu_grid(n, order, "tpp", alpha)
+    if n == 45:
+        assert g.get_launch()[0] == 45
+    for launch in launches:
+        if launch:
+            g.set_launch(*launch)
+        out = g.tendency(to_padded(q, g.r))
+        torch.cuda.synchronize()
+        err = rel_err(out, ref)
+        print("launch", g.get_launch(), "rel err", err, flush=True)
+        assert max(err) < TOL, err
 
 
 @pytest.mark.parametrize("n,order,scheme,state,steps,rk", [(30, 3, "tpp", "balanced", 10, "ssp3"),
@@ -187,3 +235,51 @@ def test_dam_break_c90_weno5_100_steps_conserves_mass():
     m1 = float(g.interior(qp)[0].sum())
     print("relative mass change", abs(m1 - m0) / m0, flush=True)
     assert abs(m1 - m0) <= 1e-13 * m0
+
+
+@pytest.mark.parametrize("n,order,scheme", [(48, 5, "weno"), (24, 11, "tpp")])
+def test_one_grid_on_two_streams_matches_serial(n, order, scheme):
+    """A grid is read-only once created: hope_tendency and hope_rk_step on
+    one grid, issued alternately on two streams with their own buffers and
+    workspaces so that their kernels overlap, give bitwise the results of
+    the same calls made one after another."""
+    print(f"case n={n} order={order} {scheme} two streams", flush=True)
+    alpha, qa = STATES["member"](n, 31)
+    _, qb = STATES["member"](n, 32)
+    g = _gpu_grid(n, order, scheme, alpha)
+    dt = min(cfl_dt(qa), cfl_dt(qb))
+    pa, pb = to_padded(qa, g.r), to_padded(qb, g.r)
+    steps = 4
+
+    def run(p, stream_ws, out, tws):
+        g.tendency(p.clone(), out, tws)
+        q = p.clone()
+        for _ in range(steps):
+            g.rk_step(q, dt, "ssp3", stream_ws)
+        return q
+
+    ref_a = torch.empty(3, 6, n, n, dtype=torch.float64, device="cuda")
+    ref_b = torch.empty_like(ref_a)
+    ra = run(pa, g.workspace(), ref_a, g.tendency_workspace())
+    rb = run(pb, g.workspace(), ref_b, g.tendency_workspace())
+    torch.cuda.synchronize()
+
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    bufs = {}
+    for key, p in (("a", pa), ("b", pb)):
+        bufs[key] = dict(q=p.clone(), qt=p.clone(), out=torch.empty_like(ref_a), ws=g.workspace(),
+                         tws=g.tendency_workspace())
+    torch.cuda.synchronize()
+    for it in range(3):
+        for key, s in (("a", s1), ("b", s2)):
+            with torch.cuda.stream(s):
+                g.tendency(bufs[key]["qt"], bufs[key]["out"], bufs[key]["tws"])
+        for _ in range(steps if it == 0 else 0):
+            for key, s in (("a", s1), ("b", s2)):
+                with torch.cuda.stream(s):
+                    g.rk_step(bufs[key]["q"], dt, "ssp3", bufs[key]["ws"])
+    torch.cuda.synchronize()
+    assert torch.equal(bufs["a"]["out"], ref_a) and torch.equal(bufs["b"]["out"], ref_b)
+    r = g.r
+    assert torch.equal(bufs["a"]["q"][:, :, r:r + n, r:r + n], ra[:, :, r:r + n, r:r + n])
+    assert torch.equal(bufs["b"]["q"][:, :, r:r + n, r:r + n], rb[:, :, r:r + n, r:r + n])

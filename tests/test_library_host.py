@@ -177,7 +177,7 @@ def test_entry_points_reject_null_handles_without_a_device():
     assert L.hope_check_state(None, None, ctypes.byref(n_bad), None) == -1
     assert n_bad.value == 0
     assert L.hope_fill_halo(None, None, None) == -1
-    assert L.hope_tendency(None, None, None, None) == -1
+    assert L.hope_tendency(None, None, None, None, 0, None) == -1
     assert L.hope_rk_step(None, None, 1.0, 0, None, 0, None) == -1
     assert L.hope_grid_profile(None, 1) == -1
     assert L.hope_grid_layout(None, None) == -1
