@@ -5,6 +5,13 @@ State: cell averages (over dx dy in angular coordinates) of
 q = (sqrtG phi, sqrtG phi u, sqrtG phi v) (2.15)-(2.16), shape (3, 6, n, n),
 index [variable, panel, j (y), i (x)].
 
+With bottom topography (section 2, (2.13)-(2.14)) the reconstruction
+variables are (sqrtG phi_t, sqrtG phi u, sqrtG phi v), phi_t = phi + phi_s:
+the cell averages of sqrtG phi_s are added to the mass before the ghost fill
+and the reconstruction, and subtracted again, as point values, at every edge
+and cell Gauss point; the LMARS pressure uses phi_t* = phi* + phi_s and the
+sources gain psi_B = sqrtG phi_s G^ij d(phi_t)/dx^j.
+
 Per evaluation (section 3):
   1. ghost cells by the fixed-point interpolation (section 3.3.1)     ghost.py
   2. reconstruction at the edge Gauss points (EQPs) and cell Gauss points
@@ -26,9 +33,9 @@ import torch
 
 from . import geometry as geo
 from .ghost import GhostMap
-from .weights import (axis_weights, centred, derivative_gram, gauss,
-                      split_weights, substencil_offsets, substencil_poly_1d,
-                      weno_linear_weights)
+from .weights import (axis_derivative_weights, axis_weights, centred,
+                      derivative_gram, gauss, split_weights, substencil_offsets,
+                      substencil_poly_1d, weno_linear_weights)
 
 
 @dataclass
@@ -39,6 +46,7 @@ class Params:
     alpha: float = 0.0          # tilt of the rotation axis (radians)
     weno_eps: float = 1e-12
     split_theta: float = 3.0
+    surface: object = None      # phis(p) -> surface geopotential g h_s at unit vectors p, or None
 
 
 def _t(a):
@@ -144,6 +152,9 @@ class Grid:
             self.weno = WenoTables(order, self.m, self.p.split_theta, self.p.weno_eps)
         self._metric()
         self._boundary_maps()
+        self.topo = self.p.surface is not None
+        if self.topo:
+            self._topography()
 
     # ------------------------------------------------------------------
     # metric at the function points
@@ -196,6 +207,32 @@ class Grid:
                 self.bmap[(A, side)] = (B, bside, torch.as_tensor(idx), torch.as_tensor(hb),
                                         _t(ratio), _t(Cm))
 
+    def _topography(self, nq: int = 4):
+        """Surface geopotential phi_s (section 2): cell averages of
+        sqrtG phi_s (nq x nq Gauss rule per cell), which turn the layer's
+        mass into the reconstruction variable sqrtG phi_t of (2.13), and
+        sqrtG phi_s at every edge point (x edges (6, n, n+1), y edges
+        (6, n+1, n), per Gauss node) and cell point ((6, n, n) per node pair).
+        Also the derivative weights of the centred stencil, d/dxi of (3.14),
+        for d(phi_t)/dx^j in psi_B (2.14)."""
+        n, m, d, a = self.n, self.m, self.delta, self.p.radius
+        f = self.p.surface
+        nodes, wts = gauss(nq)
+        xs = (geo.cell_centres(n, 0)[:, None] + nodes[None, :]) * d
+        X, Y = np.broadcast_arrays(np.tan(xs)[None, None, :, :], np.tan(xs)[:, :, None, None])
+        w = wts[None, :, None, None] * wts[None, None, None, :]
+        sg = geo.sqrt_g(X, Y, a)
+        self.sbar = _t(np.stack([(sg * f(geo.panel_xyz(p, X, Y)) * w).sum(axis=(1, 3)) for p in range(6)]))
+
+        def s_at(X, Y):
+            X, Y = np.broadcast_arrays(X, Y)
+            return _t(np.stack([geo.sqrt_g(X, Y, a) * f(geo.panel_xyz(p, X, Y)) for p in range(6)]))
+
+        self.s_xe = [s_at(self.Xe[None, :], self.Xg[:, h][:, None]) for h in range(m)]
+        self.s_ye = [s_at(self.Xg[:, h][None, :], self.Xe[:, None]) for h in range(m)]
+        self.s_cq = [[s_at(self.Xg[:, h][None, :], self.Xg[:, v][:, None]) for h in range(m)] for v in range(m)]
+        self.wd = _t(axis_derivative_weights(centred(self.k), m))
+
     # ------------------------------------------------------------------
     # reconstruction
     # ------------------------------------------------------------------
@@ -225,7 +262,10 @@ class Grid:
     # ------------------------------------------------------------------
     # Riemann solver (3.30)-(3.38)
     # ------------------------------------------------------------------
-    def lmars(self, qL, qR, X, Y, direction):
+    def lmars(self, qL, qR, X, Y, direction, phis=None):
+        """phis: surface geopotential at the points (topography): the
+        pressure (3.38) then uses phi_t* = phi* + phis, with phi* of (3.33)
+        from the layer's own phi on both sides."""
         a = self.p.radius
         sg = _t(geo.sqrt_g(X, Y, a))
         g11, g12, g22 = (_t(v) for v in geo.g_upper(X, Y, a))
@@ -237,10 +277,12 @@ class Grid:
         upR = (qR[vel] / qR[0]) / sq
         c = 0.5 * (torch.sqrt(phiL) + torch.sqrt(phiR))  # (3.34)-(3.35)
         mstar = 0.5 * (upL + upR - (phiR - phiL) / c)    # (3.32)
-        phis = 0.5 * (phiL + phiR - c * (upR - upL))     # (3.33)
+        phistar = 0.5 * (phiL + phiR - c * (upR - upL))  # (3.33)
         mm = mstar * sq                                  # (3.36)
         F = 0.5 * (mm * (qL + qR) - mm.abs() * (qR - qL))   # (3.37), upwind term |m|
-        pres = 0.5 * sg * phis * phis                       # (3.38)
+        if phis is not None:
+            phistar = phistar + phis
+        pres = 0.5 * sg * phistar * phistar                 # (3.38)
         if direction == 1:
             P = torch.stack([torch.zeros_like(pres), pres * g11, pres * g12])
         else:
@@ -271,7 +313,11 @@ class Grid:
     def tendency(self, q: torch.Tensor, ghost_sweeps: int | None = None) -> torch.Tensor:
         """dq/dt of (3.1) for interior cell averages q (3, 6, n, n)."""
         n, m, d = self.n, self.m, self.delta
-        qpad = self.ghost.fill(q, sweeps=ghost_sweeps)
+        qr = q
+        if self.topo:
+            # reconstruction variables (sqrtG phi_t, sqrtG phi u, sqrtG phi v) (2.13)
+            qr = torch.cat([q[:1] + self.sbar, q[1:]])
+        qpad = self.ghost.fill(qr, sweeps=ghost_sweeps)
         xe, ye, cq = self.reconstruct(qpad)
         outs = self.outside_traces(xe, ye)
 
@@ -285,7 +331,13 @@ class Grid:
             X = self.Xe[None, :]                               # (1, n+1)
             Y = self.Xg[:, h][:, None]                         # (n, 1)
             X, Y = np.broadcast_arrays(X, Y)
-            F = self.lmars(qL, qR, X, Y, 1)                    # (3, 6, n, n+1)
+            phis = None
+            if self.topo:
+                sp = self.s_xe[h]                              # sqrtG phi_s, same on both sides
+                qL = torch.cat([qL[:1] - sp, qL[1:]])
+                qR = torch.cat([qR[:1] - sp, qR[1:]])
+                phis = sp / _t(geo.sqrt_g(X, Y, self.p.radius))
+            F = self.lmars(qL, qR, X, Y, 1, phis)              # (3, 6, n, n+1)
             Fbar = Fbar + self.gw[h] * F
         # ---- y-edges ------------------------------------------------------
         Gbar = 0.0
@@ -297,15 +349,28 @@ class Grid:
             X = self.Xg[:, h][None, :]                         # (1, n) along i
             Y = self.Xe[:, None]                               # (n+1, 1)
             X, Y = np.broadcast_arrays(X, Y)
-            G = self.lmars(qL, qR, X, Y, 2)                    # (3, 6, n+1, n)
+            phis = None
+            if self.topo:
+                sp = self.s_ye[h]
+                qL = torch.cat([qL[:1] - sp, qL[1:]])
+                qR = torch.cat([qR[:1] - sp, qR[1:]])
+                phis = sp / _t(geo.sqrt_g(X, Y, self.p.radius))
+            G = self.lmars(qL, qR, X, Y, 2, phis)              # (3, 6, n+1, n)
             Gbar = Gbar + self.gw[h] * G
         # ---- sources at the CQPs ------------------------------------------
-        S = self.sources(cq)
+        S = self.sources(cq, qpad)
         dq = -(Fbar[..., 1:] - Fbar[..., :-1]) / d - (Gbar[..., 1:, :] - Gbar[..., :-1, :]) / d + S
         return dq
 
-    def sources(self, cq):
-        """Cell average (3.6) of S = (0, psi_M + psi_C) (2.2)-(2.3), no topography."""
+    def sources(self, cq, qpad=None):
+        """Cell average (3.6) of S = (0, psi_M + psi_C + psi_B) (2.2)-(2.3),
+        (2.14).  With topography cq holds sqrtG phi_t at the cell points; the
+        layer's sqrtG phi is that minus sqrtG phi_s, and psi_B takes
+        d(phi_t)/dx^j from the derivative of the order-k polynomial of
+        sqrtG phi_t on the centred stencil (the linear reconstruction, also
+        under WENO): d/dx = (1/Delta) d/dxi, and
+        d(phi_t)/dx = (d(sqrtG phi_t)/dx - phi_t d(sqrtG)/dx) / sqrtG with
+        d(ln sqrtG)/dx = X (2Y^2 - X^2 - 1) / delta^2 from (2.8)."""
         n, m, a = self.n, self.m, self.p.radius
         Sbar1, Sbar2 = 0.0, 0.0
         for v in range(m):
@@ -318,6 +383,17 @@ class Grid:
                 g11, g12, g22 = (_t(t) for t in geo.g_upper(X, Y, a))
                 Xt, Yt = _t(X), _t(Y)
                 d2 = 1.0 + Xt * Xt + Yt * Yt
+                psiB1, psiB2 = 0.0, 0.0
+                if self.topo:
+                    Tt = Q0                                     # sqrtG phi_t at the point
+                    sp = self.s_cq[v][h]
+                    Q0 = Tt - sp
+                    Txi = apply_stencil(qpad[0], n, self.wc[2 + v], self.wd[2 + h], 0, 0)
+                    Teta = apply_stencil(qpad[0], n, self.wd[2 + v], self.wc[2 + h], 0, 0)
+                    dx = (Txi / self.delta - Tt * Xt * (2.0 * Yt * Yt - Xt * Xt - 1.0) / d2) / sg
+                    dy = (Teta / self.delta - Tt * Yt * (2.0 * Xt * Xt - Yt * Yt - 1.0) / d2) / sg
+                    psiB1 = sp * (g11 * dx + g12 * dy)          # (2.14)
+                    psiB2 = sp * (g12 * dx + g22 * dy)
                 phi = Q0 / sg
                 u = Q1 / Q0
                 vv = Q2 / Q0
@@ -331,6 +407,6 @@ class Grid:
                 psiC1 = sg * f * (-g12 * Q1 + g11 * Q2)
                 psiC2 = sg * f * (-g22 * Q1 + g12 * Q2)
                 w = self.gw[h] * self.gw[v]
-                Sbar1 = Sbar1 + w * (psiM1 + psiC1)
-                Sbar2 = Sbar2 + w * (psiM2 + psiC2)
+                Sbar1 = Sbar1 + w * (psiM1 + psiC1 + psiB1)
+                Sbar2 = Sbar2 + w * (psiM2 + psiC2 + psiB2)
         return torch.stack([torch.zeros_like(Sbar1), Sbar1, Sbar2])
