@@ -198,6 +198,24 @@ int hope_rk_step(const hope_grid* grid, double* q, double dt, int32_t scheme, do
 int hope_rk_step_vjp(const hope_grid* grid, double* q, double dt, int32_t scheme, const double* gout,
                      double* gin, double* ws, size_t ws_bytes, void* stream);
 
+/* hope_rk_step without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The two stage states and the panel-edge
+ * traces live instead in a static device array of 64 MiB (HOPE_STATIC_SCRATCH_BYTES)
+ * that each GPU the library runs on holds until the process ends; a grid
+ * whose layout.rk_workspace_bytes exceeds it is refused with
+ * HOPE_ERR_INVALID (C360 at order 5 needs 39 MB).  The call allocates
+ * nothing: the first call on a device only looks up the array's device
+ * address (hipGetSymbolAddress).  Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents (a step reads nothing it did
+ * not write first, so nothing needs clearing): calls that overlap on one GPU
+ * (on different streams, or from different host threads before the earlier
+ * call's kernels have finished) race and give wrong results; calls one
+ * after another on one stream are fine.  The stream must belong to the
+ * current device.  Results are bitwise those of hope_rk_step. */
+enum { HOPE_STATIC_SCRATCH_BYTES = 64 << 20 };
+int hope_rk_step_static(const hope_grid* grid, double* q, double dt, int32_t scheme, void* stream);
+
 /* Message for the last error on this thread ("" if none). */
 const char* hope_last_error(void);
 

@@ -95,6 +95,7 @@ _SIGS = {
     "hope_tendency_vjp": (_I32, [_P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "hope_rk_step": (_I32, [_P, _P, ctypes.c_double, _I32, _P, ctypes.c_size_t, _P]),
     "hope_rk_step_vjp": (_I32, [_P, _P, ctypes.c_double, _I32, _P, _P, _P, ctypes.c_size_t, _P]),
+    "hope_rk_step_static": (_I32, [_P, _P, ctypes.c_double, _I32, _P]),
     "hope_last_error": (ctypes.c_char_p, []),
     "hope_grid_set_launch": (_I32, [_P, _I32, _I32]),
     "hope_grid_get_launch": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),

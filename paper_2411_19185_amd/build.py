@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhope.so")
 
 SOURCES = ["capi.cpp", "batch_capi.cpp", "host_tables.cpp", "grid_cache.cpp", "kernels.hip", "vjp.hip",
-           "batch.hip"]
+           "batch.hip", "static_scratch.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",
