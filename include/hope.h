@@ -100,6 +100,18 @@ typedef struct hope_grid_desc {
                             fails its checksum or range checks is rebuilt; a
                             directory that cannot be written only costs the
                             build. */
+  /* Bottom topography (section 2, (2.13)-(2.14)): NULL for none.  Otherwise
+   * a host function that hope_grid_create calls, on its own thread, to
+   * evaluate the surface geopotential phi_s = g h_s (m^2/s^2) at count points:
+   * xyz[3i], xyz[3i+1], xyz[3i+2] is the i-th unit vector (the panel maps
+   * above), and phis[i] receives phi_s there (finite values; the create call
+   * fails with HOPE_ERR_INVALID otherwise).  It is called a few times per
+   * panel with up to 16 n^2 points.  The state stays the layer's own
+   * (sqrtG phi, sqrtG phi u, sqrtG phi v); the grid then reconstructs
+   * sqrtG phi_t = sqrtG (phi + phi_s), uses phi_t in the pressure of the
+   * flux (3.38) and adds psi_B of (2.14) to the sources. */
+  void (*surface_geopotential)(int64_t count, const double* xyz, double* phis, void* user);
+  void* surface_user;    /* passed back to surface_geopotential */
 } hope_grid_desc;
 
 /* Sizes a caller needs to allocate buffers (all counts are elements). */
@@ -125,7 +137,10 @@ typedef struct hope_layout {
  * ghost-cell map G of appendix (7.12) (the exact fixed point of the iterative
  * interpolation of section 3.3.1, with owner-panel conversion (3.26)-(3.29),
  * or with ghost_iters set the map of that many sweeps), and the panel-edge
- * trace maps; with cache_dir set, the host tables may come from a file.  G commutes with the cube's 24 rotations;
+ * trace maps; with cache_dir set, the host tables may come from a file;
+ * with surface_geopotential set, the topography tables (cell averages of
+ * sqrtG phi_s by a 4 x 4 Gauss rule, their image under G on the ghost cells,
+ * and sqrtG phi_s at every edge and cell Gauss point).  G commutes with the cube's 24 rotations;
  * each row is replaced by the rotation image of one of r*(n+r) canonical rows
  * (they agree to rounding; the build fails with HOPE_ERR_NUMERIC otherwise),
  * and the device keeps the values once per canonical row.  Host work plus
@@ -176,8 +191,10 @@ int hope_tendency(const hope_grid* grid, double* q, double* dqdt, double* ws, si
  * ghost-cell cotangents folded back through G^T.  q's ghost rings are scratch.
  * Non-smooth points (|m|, |beta_i - beta_j|) take the subgradient sign(0)=0.
  * ws: caller-owned device workspace of at least layout.vjp_workspace_bytes
- * (8 * (2*3*(4m+m^2) + 3*order^2) bytes per cell plus one padded state); gq
- * must not alias w. */
+ * (8 * (2*3*(4m+m^2) + 3*order^2) bytes per cell plus one padded state, and
+ * 8 * 2 m^2 bytes per cell more with topography); gq must not alias w.  With
+ * topography the adjoint runs through sqrtG phi_t, the pressure with phi_s
+ * and psi_B (2.14), phi_s being a constant of the grid. */
 int hope_tendency_vjp(const hope_grid* grid, double* q, const double* w, double* gq, double* ws,
                       size_t ws_bytes, void* stream);
 
@@ -281,7 +298,8 @@ typedef struct hope_batch_info {
   int64_t ghost_rows;          /* ghost rows of all distinct grids */
 } hope_batch_info;
 
-/* grids[i]: the grid of member i (they must outlive the batch).  axis_tilt:
+/* grids[i]: the grid of member i (they must outlive the batch; grids with
+ * topography are refused with HOPE_ERR_UNSUPPORTED).  axis_tilt:
  * per-member tilt of the rotation axis (radians), or NULL to use each grid's
  * own.  Allocates device tables; synchronous. */
 int hope_batch_create(const hope_grid* const* grids, int32_t n_members, const double* axis_tilt,

@@ -29,6 +29,11 @@ class HopeError(RuntimeError):
         self.code = code
 
 
+# surface_geopotential(count, xyz, phis, user) of hope_grid_desc
+SURFACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                              ctypes.c_void_p)
+
+
 class GridDesc(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_int32),
@@ -44,6 +49,8 @@ class GridDesc(ctypes.Structure):
         ("weno_eps", ctypes.c_double),
         ("split_theta", ctypes.c_double),
         ("cache_dir", ctypes.c_char_p),
+        ("surface_geopotential", SURFACE_FN),
+        ("surface_user", ctypes.c_void_p),
     ]
 
 
@@ -143,8 +150,19 @@ def check(code: int):
         raise HopeError(code, lib().hope_last_error().decode())
 
 
+def surface_callback(surface):
+    """A SURFACE_FN that evaluates the Python callable surface(p) -> phi_s at
+    the unit vectors p (count, 3) the library asks for (marshalling only)."""
+    import numpy as np
+
+    def cb(count, xyz, out, user):
+        p = np.ctypeslib.as_array(xyz, shape=(count, 3))
+        np.ctypeslib.as_array(out, shape=(count,))[:] = np.asarray(surface(p), dtype=np.float64)
+    return SURFACE_FN(cb)
+
+
 def make_desc(n, order, scheme="tpp", radius=6.371e6, omega=7.292e-5, axis_tilt=0.0, weno_eps=1e-12,
-              split_theta=3.0, gravity=9.80616, ghost_iters=0, cache_dir=None) -> GridDesc:
+              split_theta=3.0, gravity=9.80616, ghost_iters=0, cache_dir=None, surface_fn=None) -> GridDesc:
     d = GridDesc()
     d.struct_size = ctypes.sizeof(GridDesc)
     d.n = n
@@ -159,6 +177,8 @@ def make_desc(n, order, scheme="tpp", radius=6.371e6, omega=7.292e-5, axis_tilt=
     d.split_theta = split_theta
     d.ghost_iters = ghost_iters
     d.cache_dir = None if cache_dir is None else os.fsencode(cache_dir)
+    if surface_fn is not None:
+        d.surface_geopotential = surface_fn
     return d
 
 

@@ -125,6 +125,7 @@ int hope_batch_create(const hope_grid* const* grids, int32_t n_members, const do
     if (!grids[i]) return fail(HOPE_ERR_INVALID, "null grid");
     if (grids[i]->h.k != grids[0]->h.k || grids[i]->h.weno != grids[0]->h.weno)
       return fail(HOPE_ERR_UNSUPPORTED, "all members must share order and scheme");
+    if (grids[i]->topo.sbar) return fail(HOPE_ERR_UNSUPPORTED, "the batched kernels are built without topography");
     if (axis_tilt && !std::isfinite(axis_tilt[i])) return fail(HOPE_ERR_INVALID, "axis_tilt not finite");
   }
   hope_batch* B = new (std::nothrow) hope_batch();

@@ -177,6 +177,11 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
     std::vector<double> tab(O.total, 0.0);
     auto put = [&](int64_t off, const std::vector<double>& v) { std::copy(v.begin(), v.end(), tab.begin() + off); };
     put(O.wc, h.wc);
+    {
+      std::vector<double> wd;
+      derivative_weights(h.k, h.m, wd);
+      put(O.wd, wd);
+    }
     if (h.weno) {
       put(O.wsub, h.wsub);
       put(O.gp, h.gp);
@@ -276,6 +281,23 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
     if (e2) { free_grid(G); return e2; }
     G->gt_nnz = (int64_t)nnz;
   }
+  if (desc->surface_geopotential) {
+    TopoHost th;
+    std::string err;
+    int et = 0;
+    try {
+      et = build_topography(h, desc->surface_geopotential, desc->surface_user, th, err);
+    } catch (const std::bad_alloc&) {
+      free_grid(G);
+      return fail(HOPE_ERR_NOMEM, "host allocation while building the topography tables");
+    }
+    if (et) { free_grid(G); return fail(et, err); }
+    int e4 = upload(G, th.sbar, &G->topo.sbar);
+    if (!e4) e4 = upload(G, th.sx, &G->topo.sx);
+    if (!e4) e4 = upload(G, th.sy, &G->topo.sy);
+    if (!e4) e4 = upload(G, th.sc, &G->topo.sc);
+    if (e4) { free_grid(G); return e4; }
+  }
   int e3 = alloc_scratch(G);
   if (e3) { free_grid(G); return e3; }
   default_launch(G);
@@ -313,6 +335,7 @@ int hope_grid_derive(const hope_grid* base, double axis_tilt, hope_grid** out) {
   coriolis_coefs(axis_tilt, h.fcoef.data());
   G->gs = base->gs;
   G->g = base->g;
+  G->topo = base->topo;
   G->itab = base->itab;
   G->gt_rows = base->gt_rows;
   G->gt_cell = base->gt_cell;
@@ -346,14 +369,18 @@ void hope_grid_destroy(hope_grid* grid) {
   free_grid(grid);
 }
 
-// adjoint scratch: point values T, their cotangents, WENO stencil cotangents, padded cotangent
-static size_t vjp_elems(const HostTables& h, size_t* nT, size_t* nD, size_t* nG) {
+// adjoint scratch: point values T, their cotangents, stencil cotangents,
+// padded cotangent, and with topography the cotangents of the mass
+// derivatives at the cell nodes
+static size_t vjp_elems(const hope_grid* G, size_t* nT, size_t* nD, size_t* nG) {
+  const HostTables& h = G->h;
   const size_t cells = 6ULL * h.n * h.n;
   const size_t np = 4 * h.m + h.m * h.m;
   *nT = cells * np * 3;
   *nD = cells * h.k * h.k * 3;
   *nG = 18ULL * h.P * h.P;
-  return 2 * *nT + *nD + *nG;
+  const size_t nL = G->topo.sbar ? 2 * cells * h.m * h.m : 0;
+  return 2 * *nT + *nD + *nG + nL;
 }
 
 int hope_grid_layout(const hope_grid* G, hope_layout* out) {
@@ -369,7 +396,7 @@ int hope_grid_layout(const hope_grid* G, hope_layout* out) {
   out->rk_workspace_bytes = 2 * out->state_elems * (int64_t)sizeof(double) + out->tendency_workspace_bytes;
   {
     size_t nT, nD, nG;
-    out->vjp_workspace_bytes = (int64_t)(vjp_elems(G->h, &nT, &nD, &nG) * sizeof(double));
+    out->vjp_workspace_bytes = (int64_t)(vjp_elems(G, &nT, &nD, &nG) * sizeof(double));
   }
   out->rk_vjp_workspace_bytes =
       (2 * out->state_elems + 2 * out->interior_elems) * (int64_t)sizeof(double) + out->vjp_workspace_bytes;
@@ -424,13 +451,13 @@ static int run_stage(const hope_grid* G, double* q, const double* qn, double* ou
   if (e) return hip_fail((hipError_t)e, "fill_halo launch");
   {
     Timed tm(G, 1, stream);
-    e = launch_edge_traces(G->h.k, G->h.weno, G->tab, G->itab, G->gs, q, bt, stream);
+    e = launch_edge_traces(G->h.k, G->h.weno, G->tab, G->itab, G->gs, q, bt, G->topo, stream);
   }
   if (e) return hip_fail((hipError_t)e, "edge_traces launch");
   {
     Timed tm(G, 2, stream);
     e = launch_stage(G->h.k, G->h.weno, G->tab, G->itab, G->gs, q, qn, out, out_padded, ca, cb, cc, bt,
-                     G->strip_w, G->seg_h, stream);
+                     G->strip_w, G->seg_h, G->topo, stream);
   }
   if (e) return hip_fail((hipError_t)e, "stage launch");
   return HOPE_OK;
@@ -454,7 +481,7 @@ int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq
   if (gq == w) return fail(HOPE_ERR_INVALID, "gq must not alias w");
   const HostTables& h = G->h;
   size_t nT, nD, nG;
-  if (ws_bytes < vjp_elems(h, &nT, &nD, &nG) * sizeof(double)) return fail(HOPE_ERR_INVALID, "workspace too small");
+  if (ws_bytes < vjp_elems(G, &nT, &nD, &nG) * sizeof(double)) return fail(HOPE_ERR_INVALID, "workspace too small");
   int e;
   {
     Timed tm(G, 0, stream);
@@ -479,6 +506,8 @@ int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq
   a.gt_ref = G->gt_ref;
   a.gcval = G->g.cval;
   a.gt_nnz = G->gt_nnz;
+  a.topo = G->topo;
+  a.Lder = ws + 2 * nT + nD + nG;
   for (int step = 0; step < kVjpSteps; ++step) {
     Timed tm(G, 3 + step, stream);
     e = launch_vjp(h.k, h.weno, a, step, stream);
@@ -511,7 +540,7 @@ int hope_rk_step_vjp(const hope_grid* G, double* q, double dt, int32_t scheme, c
   if (gin == gout) return fail(HOPE_ERR_INVALID, "gin must not alias gout");
   const size_t state = 18ULL * G->h.P * G->h.P, field = 18ULL * G->h.n * G->h.n;
   size_t nT, nD, nG;
-  const size_t nv = vjp_elems(G->h, &nT, &nD, &nG);
+  const size_t nv = vjp_elems(G, &nT, &nD, &nG);
   if (ws_bytes < (2 * state + 2 * field + nv) * sizeof(double)) return fail(HOPE_ERR_INVALID, "workspace too small");
   if (reinterpret_cast<uintptr_t>(q) % 8 || reinterpret_cast<uintptr_t>(ws) % 8 ||
       reinterpret_cast<uintptr_t>(gout) % 8 || reinterpret_cast<uintptr_t>(gin) % 8)

@@ -39,8 +39,12 @@ __device__ __forceinline__ double sqrt_g(double x) {
 
 // LMARS flux (3.30)-(3.38) with upwind term |m|(q_R - q_L); dir 0 = x, 1 = y.
 // sqx = sqrt(1 + X^2), sqy = sqrt(1 + Y^2) come from tables, ia = 1/a.
+// TOPO: bottom topography (2.13); q holds the layer's own sqrtG phi and
+// sps = sqrtG phi_s at the point, so the pressure uses phi_t* = phi* + phi_s
+// (both sides share phi_s, so the height jump of (3.32) is that of phi_t).
+template <bool TOPO = false>
 __device__ __forceinline__ void lmars(const double* qL, const double* qR, double X, double Y, double sqx,
-                                      double sqy, int dir, double ia, double* F) {
+                                      double sqy, int dir, double ia, double* F, double sps = 0.0) {
   const double ox = sqx * sqx, oy = sqy * sqy;
   const double d2 = fma(X, X, oy);
   const double dl = sqrt_g(d2);
@@ -53,7 +57,8 @@ __device__ __forceinline__ void lmars(const double* qL, const double* qR, double
   const double upR = qR[iv] * rcp(qR[0] * sgii);
   const double c = 0.5 * (sqrt_g(phiL) + sqrt_g(phiR));           // (3.34)-(3.35)
   const double ms = 0.5 * (upL + upR - (phiR - phiL) * rcp(c));   // (3.32)
-  const double ps = 0.5 * (phiL + phiR - c * (upR - upL));        // (3.33)
+  double ps = 0.5 * (phiL + phiR - c * (upR - upL));              // (3.33)
+  if constexpr (TOPO) ps = fma(sps, isg, ps);                     // phi_t* = phi* + phi_s
   const double mm = ms * sgii;                                    // (3.36)
   const double am = fabs(mm);
 #pragma unroll
@@ -82,6 +87,66 @@ __device__ __forceinline__ void sources(double Q0, double Q1, double Q2, double 
   const double c2 = f * (X * Y * Q2 - (1.0 + X2) * Q1);
   s1 = (m1 + c1) * id2;
   s2 = (m2 + c2) * id2;
+}
+
+// sqrtG phi_s of the topography tables at point h of the side sd (0 left,
+// 1 right, 2 bottom, 3 top) of cell (i, j) of panel p
+template <int M>
+__device__ __forceinline__ double topo_cell_side(const TopoDev& tp, int n, int p, int i, int j, int sd, int h) {
+  if (sd < 2) return tp.sx[(((size_t)p * n + j) * (n + 1) + i + sd) * M + h];
+  return tp.sy[(((size_t)p * (n + 1) + j + (sd - 2)) * n + i) * M + h];
+}
+
+// the same at point h of a panel's boundary side idx = (panel*4 + side)*n + t
+template <int M>
+__device__ __forceinline__ double topo_side_point(const TopoDev& tp, int n, int idx, int h) {
+  const int p = idx / (4 * n), side = (idx / n) % 4, t = idx % n;
+  if (side < 2) return tp.sx[(((size_t)p * n + t) * (n + 1) + (side ? n : 0)) * M + h];
+  return tp.sy[(((size_t)p * (n + 1) + (side == 3 ? n : 0)) * n + t) * M + h];
+}
+
+// Bottom-topography source psi_B (2.14) at one point.  T = sqrtG phi_t,
+// (Txi, Teta) its derivatives in the unit-cell coordinates of the
+// reconstruction polynomial, sps = sqrtG phi_s; invd = 1/Delta, ia = 1/a.
+// With D_j = dT/dx^j - T d(ln sqrtG)/dx^j, d(ln sqrtG)/dx = X (2Y^2 - X^2 - 1)
+// / delta^2 (from (2.8)), d(phi_t)/dx^j = D_j / sqrtG, and
+// psi_B^i = sps G^ij D_j / sqrtG = sps delta^5 / (a^4 ox^2 oy^2) times
+// (oy D_x + X Y D_y, X Y D_x + ox D_y), ox = 1 + X^2, oy = 1 + Y^2.
+__device__ __forceinline__ double psi_b_scale(double X, double Y, double sps, double ia, double& ox, double& oy,
+                                              double& ex, double& ey) {
+  const double X2 = X * X, Y2 = Y * Y;
+  ox = 1.0 + X2;
+  oy = 1.0 + Y2;
+  const double d2 = ox + Y2;
+  const double id2 = rcp(d2);
+  ex = X * (2.0 * Y2 - X2 - 1.0) * id2;
+  ey = Y * (2.0 * X2 - Y2 - 1.0) * id2;
+  const double ia2 = ia * ia;
+  const double oo = rcp(ox * oy);
+  return sps * d2 * d2 * sqrt_g(d2) * ia2 * ia2 * oo * oo;
+}
+
+__device__ __forceinline__ void psi_b(double T, double Txi, double Teta, double X, double Y, double sps, double invd,
+                                      double ia, double& b1, double& b2) {
+  double ox, oy, ex, ey;
+  const double c = psi_b_scale(X, Y, sps, ia, ox, oy, ex, ey);
+  const double Dx = fma(Txi, invd, -T * ex), Dy = fma(Teta, invd, -T * ey);
+  const double xy = X * Y;
+  b1 = c * fma(oy, Dx, xy * Dy);
+  b2 = c * fma(xy, Dx, ox * Dy);
+}
+
+// reverse mode of psi_b: given (b1b, b2b) = dL/d(b1, b2), the cotangents of
+// T, Txi and Teta
+__device__ __forceinline__ void psi_b_adj(double X, double Y, double sps, double invd, double ia, double b1b,
+                                          double b2b, double& Tb, double& Txib, double& Tetab) {
+  double ox, oy, ex, ey;
+  const double c = psi_b_scale(X, Y, sps, ia, ox, oy, ex, ey);
+  const double xy = X * Y;
+  const double Dxb = c * fma(oy, b1b, xy * b2b), Dyb = c * fma(xy, b1b, ox * b2b);
+  Txib = Dxb * invd;
+  Tetab = Dyb * invd;
+  Tb = -(Dxb * ex + Dyb * ey);
 }
 
 // ---------------------------------------------------------------------------

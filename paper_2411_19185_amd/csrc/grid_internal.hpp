@@ -16,6 +16,7 @@ struct hope_grid {
   const int32_t* itab = nullptr;   // panel-edge map
   hope::GridScalars gs{};
   hope::GhostDev g{};
+  hope::TopoDev topo{};            // bottom topography tables (null: none)
   std::vector<void*> allocs;
   size_t device_bytes = 0;
   unsigned long long* bad = nullptr;   // hope_check_state's counter

@@ -61,6 +61,22 @@ struct HostTables {
 // Coriolis coefficients of the 6 panels for a rotation axis tilted by tilt (18 values).
 void coriolis_coefs(double tilt, double* out);
 
+// d/dxi of the centred order-k weights at the 2+m axis points ((2+m) x k).
+void derivative_weights(int k, int m, std::vector<double>& out);
+
+// Bottom topography (section 2, (2.13)-(2.14)): the surface geopotential
+// phi_s comes from a host function evaluated at unit vectors.
+typedef void (*SurfaceFn)(int64_t count, const double* xyz, double* phis, void* user);
+struct TopoHost {
+  std::vector<double> sbar;   // 6 P P: cell averages of sqrtG phi_s; ghost cells: G applied to them
+  std::vector<double> sx;     // 6 n (n+1) m: sqrtG phi_s at the x-edge Gauss points [p][j][edge i][h]
+  std::vector<double> sy;     // 6 (n+1) n m: at the y-edge Gauss points [p][edge j][i][h]
+  std::vector<double> sc;     // 6 n n m m: at the cell Gauss points [p][j][i][w (y node)][h (x node)]
+};
+// Builds the tables from the host ghost map of t (g_*, still present);
+// returns 0 or a HOPE_ERR code with err set.
+int build_topography(const HostTables& t, SurfaceFn fn, void* user, TopoHost& out, std::string& err);
+
 // Builds every table; returns 0 on success, else a HOPE_ERR code with error set.
 // ghost_iters: 0 for the fixed-point ghost map, N > 0 for N Jacobi sweeps from 0.
 int build_tables(HostTables& t, int n, int k, int weno, double radius, double omega, double tilt,
@@ -85,7 +101,7 @@ int build_tables_cached(HostTables& t, const char* dir, bool* loaded, int n, int
 #endif
 
 struct TabOffsets {
-  int64_t wc, wsub, gp, gm, sp, sm, d1, theta, V, lam, gw, fcoef, fixed;
+  int64_t wc, wd, wsub, gp, gm, sp, sm, d1, theta, V, lam, gw, fcoef, fixed;
   int64_t Xe, sqe, Xg, sqg, bt_conv, total;
   int64_t i_cell, i_side, i_rev, i_total;
 };
@@ -94,7 +110,8 @@ HOPE_HD constexpr TabOffsets tab_offsets(int k, bool weno, int m, int n) {
   const int NA = 2 + m, NP = 4 * m + m * m, L = (k + 1) / 2, S = L * L;
   TabOffsets o{};
   o.wc = 0;
-  o.wsub = o.wc + NA * k;
+  o.wd = o.wc + NA * k;                 // derivative of the centred weights (topography)
+  o.wsub = o.wd + NA * k;
   o.gp = o.wsub + (weno ? L * NA * L : 0);
   o.gm = o.gp + (weno ? NP * S : 0);
   o.sp = o.gm + (weno ? NP * S : 0);
@@ -161,6 +178,15 @@ struct GhostDev {
   int rows;
 };
 
+// Topography tables on the device (the TopoHost arrays); a null sbar means
+// no topography.
+struct TopoDev {
+  const double* sbar = nullptr;
+  const double* sx = nullptr;
+  const double* sy = nullptr;
+  const double* sc = nullptr;
+};
+
 // Strips of the fused stage of up to 30 columns (32 lanes with the two ring
 // lanes) run two per workgroup, one in each half of its lanes, side by side
 // over the same rows; wider strips take all 64 lanes.  Work items of a stage
@@ -181,9 +207,9 @@ int launch_check_state(const double* q, int n, int r, unsigned long long* bad, v
 int launch_combine(size_t len, double* out, const double* x, const double* y, const double* z, double a, double b,
                    double c, void* stream);
 int launch_edge_traces(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs,
-                       const double* q, double* bt, void* stream);
+                       const double* q, double* bt, const TopoDev& topo, void* stream);
 int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs,
                  const double* q, const double* qn, double* out, int out_padded, double ca, double cb, double cc,
-                 const double* bt, int strip_w, int seg_h, void* stream);
+                 const double* bt, int strip_w, int seg_h, const TopoDev& topo, void* stream);
 
 }  // namespace hope

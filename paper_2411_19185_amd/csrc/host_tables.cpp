@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <limits>
 #include <cstdio>
 #include <cstring>
 
@@ -984,6 +985,145 @@ int build_tables(HostTables& t, int n, int k, int weno, double radius, double om
   if (!st) st = compress_ghost_map(t);
   if (st) return st;
   return build_edge_maps(t);
+}
+
+// d/dxi of the centred weights of order k at the 2+m axis points (x-edges,
+// Gauss nodes), out[a*k + i]: the primitive U is the Lagrange interpolant of
+// the interfaces, p = U', so dp/dxi = U'' and cell i's weight is the sum of
+// L_e''(xi) over the interfaces e to its right.
+void derivative_weights(int k, int m, std::vector<double>& out) {
+  std::vector<ld> gx, gwt;
+  gauss_rule(m, gx, gwt);
+  std::vector<ld> axis(2 + m);
+  axis[0] = -0.5L;
+  axis[1] = 0.5L;
+  for (int i = 0; i < m; ++i) axis[2 + i] = gx[i];
+  const int r = (k - 1) / 2;
+  std::vector<ld> xe(k + 1), d2(k + 1);
+  for (int e = 0; e <= k; ++e) xe[e] = -r - 0.5L + e;
+  out.assign((2 + m) * k, 0.0);
+  for (int a = 0; a < 2 + m; ++a) {
+    const ld xi = axis[a];
+    for (int e = 0; e <= k; ++e) {
+      ld sum = 0;
+      for (int l = 0; l <= k; ++l) {
+        if (l == e) continue;
+        for (int q = 0; q <= k; ++q) {
+          if (q == e || q == l) continue;
+          ld prod = 1 / ((xe[e] - xe[l]) * (xe[e] - xe[q]));
+          for (int o = 0; o <= k; ++o) {
+            if (o == e || o == l || o == q) continue;
+            prod *= (xi - xe[o]) / (xe[e] - xe[o]);
+          }
+          sum += prod;
+        }
+      }
+      d2[e] = sum;
+    }
+    for (int i = 0; i < k; ++i) {
+      ld acc = 0;
+      for (int e = i + 1; e <= k; ++e) acc += d2[e];
+      out[a * k + i] = (double)acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bottom topography (section 2, (2.13)-(2.14)).  The kernels reconstruct the
+// mass as sqrtG phi_t = sqrtG phi + sqrtG phi_s: they add the cell averages
+// of sqrtG phi_s (ghost cells: the ghost map applied to them, as to any
+// reconstruction variable) before reconstructing, and subtract the point
+// values of sqrtG phi_s at every edge and cell Gauss point afterwards.
+// ---------------------------------------------------------------------------
+int build_topography(const HostTables& t, SurfaceFn fn, void* user, TopoHost& out, std::string& err) {
+  const int n = t.n, m = t.m, P = t.P, r = t.r;
+  const ld a = t.radius;
+  auto sg_at = [&](ld X, ld Y) {
+    const ld d2 = 1 + X * X + Y * Y;
+    return a * a * (1 + X * X) * (1 + Y * Y) / (d2 * std::sqrt(d2));
+  };
+  std::vector<double> xyz, val;
+  // phi_s at npt points of panel p given by coords(i, X, Y)
+  auto eval = [&](int p, size_t npt, auto coords, auto store) -> bool {
+    xyz.resize(3 * npt);
+    val.assign(npt, std::numeric_limits<double>::quiet_NaN());
+    std::vector<ld> XX(npt), YY(npt);
+    for (size_t i = 0; i < npt; ++i) {
+      coords(i, XX[i], YY[i]);
+      ld u[3];
+      unit_vec(p, XX[i], YY[i], u);
+      for (int c = 0; c < 3; ++c) xyz[3 * i + c] = (double)u[c];
+    }
+    fn((int64_t)npt, xyz.data(), val.data(), user);
+    for (size_t i = 0; i < npt; ++i) {
+      if (!std::isfinite(val[i])) {
+        err = "surface_geopotential returned a value that is not finite";
+        return false;
+      }
+      store(i, sg_at(XX[i], YY[i]) * (ld)val[i]);
+    }
+    return true;
+  };
+  // cell averages over dx dy by an nq x nq Gauss rule
+  constexpr int nq = 4;
+  std::vector<ld> qx, qw;
+  gauss_rule(nq, qx, qw);
+  const ld h = kPi / (2 * (ld)n);
+  out.sbar.assign(6 * (size_t)P * P, 0.0);
+  std::vector<ld> acc((size_t)n * n);
+  for (int p = 0; p < 6; ++p) {
+    std::fill(acc.begin(), acc.end(), 0.0L);
+    const size_t npt = (size_t)n * n * nq * nq;
+    auto coords = [&](size_t idx, ld& X, ld& Y) {
+      const size_t cell = idx / (nq * nq);
+      const int q = (int)(idx % (nq * nq));
+      const int i = (int)(cell % n), j = (int)(cell / n);
+      X = std::tan((i + 0.5L - n / 2.0L + qx[q % nq]) * h);
+      Y = std::tan((j + 0.5L - n / 2.0L + qx[q / nq]) * h);
+    };
+    auto store = [&](size_t idx, ld v) {
+      const int q = (int)(idx % (nq * nq));
+      acc[idx / (nq * nq)] += qw[q % nq] * qw[q / nq] * v;
+    };
+    if (!eval(p, npt, coords, store)) return HOPE_ERR_INVALID;
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i)
+        out.sbar[((size_t)p * P + j + r) * P + i + r] = (double)acc[(size_t)j * n + i];
+  }
+  for (size_t row = 0; row + 1 < t.g_ptr.size(); ++row) {
+    ld s = 0;
+    for (int32_t k = t.g_ptr[row]; k < t.g_ptr[row + 1]; ++k) s += (ld)t.g_val[k] * out.sbar[t.g_col[k]];
+    out.sbar[t.g_dst[row]] = (double)s;
+  }
+  // point values at the edge and cell Gauss points
+  out.sx.assign(6 * (size_t)n * (n + 1) * m, 0.0);
+  out.sy.assign(6 * (size_t)(n + 1) * n * m, 0.0);
+  out.sc.assign(6 * (size_t)n * n * m * m, 0.0);
+  for (int p = 0; p < 6; ++p) {
+    double* sx = out.sx.data() + (size_t)p * n * (n + 1) * m;
+    auto cx = [&](size_t idx, ld& X, ld& Y) {        // [j][i][h], i = edge 0..n
+      const int hh = (int)(idx % m), i = (int)((idx / m) % (n + 1)), j = (int)(idx / (m * (n + 1)));
+      X = t.Xe[i];
+      Y = t.Xg[j * m + hh];
+    };
+    if (!eval(p, (size_t)n * (n + 1) * m, cx, [&](size_t idx, ld v) { sx[idx] = (double)v; })) return HOPE_ERR_INVALID;
+    double* sy = out.sy.data() + (size_t)p * (n + 1) * n * m;
+    auto cy = [&](size_t idx, ld& X, ld& Y) {        // [j][i][h], j = edge 0..n
+      const int hh = (int)(idx % m), i = (int)((idx / m) % n), j = (int)(idx / (m * n));
+      X = t.Xg[i * m + hh];
+      Y = t.Xe[j];
+    };
+    if (!eval(p, (size_t)(n + 1) * n * m, cy, [&](size_t idx, ld v) { sy[idx] = (double)v; })) return HOPE_ERR_INVALID;
+    double* sc = out.sc.data() + (size_t)p * n * n * m * m;
+    auto cc = [&](size_t idx, ld& X, ld& Y) {        // [j][i][w][h]
+      const int hh = (int)(idx % m), w = (int)((idx / m) % m), i = (int)((idx / (m * m)) % n),
+                j = (int)(idx / ((size_t)m * m * n));
+      X = t.Xg[i * m + hh];
+      Y = t.Xg[j * m + w];
+    };
+    if (!eval(p, (size_t)n * n * m * m, cc, [&](size_t idx, ld v) { sc[idx] = (double)v; })) return HOPE_ERR_INVALID;
+  }
+  return HOPE_OK;
 }
 
 // Coriolis parameter on panel p: f = 2 Omega (Omega_hat . p_hat) with the axis

@@ -90,21 +90,29 @@ __device__ __forceinline__ void halo_row(const GhostDev& g, double* __restrict__
 // reconstructs variable min(g, 2) (lane 3 repeats variable 2, so the group
 // takes no divergent path), the group exchanges its values, and lane g < 3
 // writes component g of the converted trace (3.26)-(3.29)
+// With topography (TP) the mass is reconstructed as sqrtG phi_t (the cell
+// averages of sqrtG phi_s added to the stencil), and the converted trace is
+// the layer's own sqrtG phi again: sqrtG phi_s at this panel's point removed.
 constexpr int kEdgeLanes = 4;
-template <int K, bool W, int M>
+
+template <int K, bool W, int M, bool TP = false>
 __device__ __forceinline__ void edge_trace(cdp tab, cip itab, const GridScalars& gs, const double* __restrict__ q,
-                                           double* __restrict__ bt, int idx, int g) {
+                                           double* __restrict__ bt, int idx, int g, const TopoDev& tp = TopoDev()) {
   using C = Cfg<K, W, M>;
   const int n = gs.n, P = gs.P;
   const TabOffsets O = tab_offsets(K, W, M, n);
   const size_t vs = (size_t)6 * P * P;
   const int v = min(g, 2);
   const double* c0 = q + itab[O.i_cell + idx] + v * vs;
+  const double* s0 = TP ? tp.sbar + itab[O.i_cell + idx] : nullptr;
   const int sd = itab[O.i_side + idx];
   const int rev = itab[O.i_rev + idx];
   double vals[M];
   {
-    auto at = [&](int dy, int dx) -> double { return c0[dy * P + dx]; };
+    auto at = [&](int dy, int dx) -> double {
+      if constexpr (TP) return c0[dy * P + dx] + (v == 0 ? s0[dy * P + dx] : 0.0);
+      else return c0[dy * P + dx];
+    };
     double kap[W ? C::S : 1];
     if constexpr (W) weno_kappa<K, W, M>(tab, gs.eps, at, [&](int j, double x) { kap[j] = x; });
     auto kf = [&](int j) -> double { return kap[j]; };
@@ -140,7 +148,11 @@ __device__ __forceinline__ void edge_trace(cdp tab, cip itab, const GridScalars&
     const double a0 = __shfl(mine, 0, kEdgeLanes), a1 = __shfl(mine, 1, kEdgeLanes), a2 = __shfl(mine, 2, kEdgeLanes);
     cdp cv = tab + O.bt_conv + ((size_t)idx * M + h) * 5;
     double* o = bt + ((size_t)idx * M + h) * 3;
-    if (g == 0) o[0] = cv[0] * a0;
+    if constexpr (TP) {
+      if (g == 0) o[0] = cv[0] * a0 - topo_side_point<M>(tp, n, idx, h);
+    } else {
+      if (g == 0) o[0] = cv[0] * a0;
+    }
     if (g == 1) o[1] = cv[1] * a1 + cv[2] * a2;
     if (g == 2) o[2] = cv[3] * a1 + cv[4] * a2;
   }
@@ -155,6 +167,7 @@ struct StageArgs {
   int out_padded;
   int strip_w, seg_h, n_strips, n_segs;
   int half;                 // strips of <= kHalfStrip columns: two per workgroup, 32 lanes each
+  TopoDev tp;               // bottom topography tables (used by the TP kernels only)
 };
 
 
@@ -164,8 +177,17 @@ struct StageArgs {
 // assembly phases are then split between the three.
 constexpr int kStageThreads = 192;
 
-template <int K, bool W, int M>
-struct StageSmem {
+// with topography, the cell average of psi_B (2.14) of every lane's cell in
+// the current row, formed by wavefront 0 (the mass) for wavefront 2 (sources)
+template <bool TP>
+struct TopoSmem {};
+template <>
+struct TopoSmem<true> {
+  double psb[2][64];
+};
+
+template <int K, bool W, int M, bool TP = false>
+struct StageSmem : TopoSmem<TP> {
   // window columns: one strip of up to 64 lanes plus 2R, or two half strips
   // of 32 lanes plus 2R each
   static constexpr int R = (K - 1) / 2, NR = 2 * R + 1, CW = 64 + 4 * R;
@@ -195,9 +217,16 @@ struct StageSmem {
 // evaluates the flux through every lane's left and bottom edge and the
 // sources, finishes row j-1 (whose top flux is row j's bottom flux) and forms
 // row j's partial tendency.  Step j1 only supplies the top flux of row j1-1.
-template <int K, bool W, int M>
+//
+// With bottom topography (TP, (2.13)-(2.14)) the window holds sqrtG phi_t for
+// the mass (q + the cell averages of sqrtG phi_s); wavefront 0 subtracts
+// sqrtG phi_s from each of its point values, so every later phase sees the
+// layer's own sqrtG phi, and forms psi_B of the row from the derivative of
+// the centred order-k polynomial of sqrtG phi_t at the cell nodes; the LMARS
+// pressure adds phi_s.
+template <int K, bool W, int M, bool TP = false>
 __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp fcb, const GridScalars& gs,
-                                           const StageArgs& A, int item, StageSmem<K, W, M>& sm) {
+                                           const StageArgs& A, int item, StageSmem<K, W, M, TP>& sm) {
   using C = Cfg<K, W, M>;
   constexpr int R = C::R, S = C::S, NR = C::NR, XR = C::XR;
   constexpr int CW = StageSmem<K, W, M>::CW;       // window columns allocated
@@ -248,9 +277,10 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       const int sc = col_of(g);
       const int gc = (sc % A.n_strips) * A.strip_w - 1 + cc;
       const bool used = half ? g < 2 : c < 64 + 2 * R;
-      buf[k] = (idx < 3 * CW && used && pr >= 0 && pr < P && gc >= 0 && gc < P)
-                   ? A.q[(sc / A.n_strips) * plane + v * vs + (size_t)pr * P + gc]
-                   : 0.0;
+      const bool ok = idx < 3 * CW && used && pr >= 0 && pr < P && gc >= 0 && gc < P;
+      const size_t off = (sc / A.n_strips) * plane + (size_t)pr * P + gc;
+      if constexpr (TP) buf[k] = ok ? A.q[off + v * vs] + (v == 0 ? A.tp.sbar[off] : 0.0) : 0.0;
+      else buf[k] = ok ? A.q[off + v * vs] : 0.0;
     }
   };
   auto store = [&](int pr, const double* buf) {
@@ -279,6 +309,69 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
   auto fx = [&](int v, int l) -> double& { return sm.pts[v][SM::PL][l]; };
   auto fy = [&](int v) -> double& { return sm.pts[v][SM::PB][lane]; };
   auto src = [&](int c) -> double& { return sm.pts[c][SM::PI][lane]; };
+  // topography: sqrtG phi_s at this lane's points of row pc (edge indices clamped
+  // for the ring lanes, whose values at a panel edge are not used)
+  const int ie_l = max(0, min(n, i)), ie_r = max(0, min(n, i + 1));
+  auto s_xe = [&](int pc, int ie, int h) -> double {
+    return A.tp.sx[(((size_t)p * n + pc) * (n + 1) + ie) * M + h];
+  };
+  auto s_ye = [&](int je, int h) -> double { return A.tp.sy[(((size_t)p * (n + 1) + je) * n + ic) * M + h]; };
+  auto s_cq = [&](int pc, int w, int h) -> double {
+    return A.tp.sc[((((size_t)p * n + pc) * n + ic) * M + w) * M + h];
+  };
+  // the layer's own mass at a point of this wavefront's variable: with
+  // topography, wavefront 0 removes sqrtG phi_s from sqrtG phi_t
+  auto layer = [&](double val, auto s_of) -> double {
+    if constexpr (TP) return wv == 0 ? val - s_of() : val;
+    else return val;
+  };
+
+  // ---- topography: psi_B of the row, by wavefront 0 --------------------------
+  // centred (xc) and derivative (xd) x-passes of sqrtG phi_t at x axis point px
+  auto tpass = [&](int pc, int px, double* xc, double* xd) {
+    cdp wcc = tab + C::O.wc, wdd = tab + C::O.wd;
+    auto at = win(pc);
+#pragma unroll
+    for (int row = 0; row < NR; ++row) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int a = 0; a < K; ++a) {
+        const double x = at(row - R, a - R);
+        a0 = fma(wcc[px * K + a], x, a0);
+        a1 = fma(wdd[px * K + a], x, a1);
+      }
+      xc[row] = a0;
+      xd[row] = a1;
+    }
+  };
+  // derivative x-pass only (TPP: the centred x-pass is the reconstruction's own)
+  auto dpass = [&](int pc, int px, double* xd) {
+    cdp wdd = tab + C::O.wd;
+    auto at = win(pc);
+#pragma unroll
+    for (int row = 0; row < NR; ++row) {
+      double a1 = 0.0;
+#pragma unroll
+      for (int a = 0; a < K; ++a) a1 = fma(wdd[px * K + a], at(row - R, a - R), a1);
+      xd[row] = a1;
+    }
+  };
+  // adds psi_B at the cell node (x node h, y node w) of row pc, where the
+  // reconstructed sqrtG phi_t is T, weighted by the cell quadrature (3.6)
+  auto psi_add = [&](int pc, int h, int w, double T, const double* xc, const double* xd, double& b1, double& b2) {
+    cdp wcc = tab + C::O.wc, wdd = tab + C::O.wd;
+    double Txi = 0.0, Teta = 0.0;
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+      Txi = fma(wcc[(2 + w) * K + b], xd[b], Txi);
+      Teta = fma(wdd[(2 + w) * K + b], xc[b], Teta);
+    }
+    double c1, c2;
+    psi_b(T, Txi, Teta, Xg[ic * M + h], Xg[pc * M + w], s_cq(pc, w, h), invd, ia, c1, c2);
+    const double g2 = gw[h] * gw[w];
+    b1 = fma(g2, c1, b1);
+    b2 = fma(g2, c2, b2);
+  };
 
   // ---- reconstruction phase: wavefront wv, variable wv ----------------------
   // every point of row pc
@@ -287,6 +380,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     kappa(pc, kap);
     auto kf = [&](int j) -> double { return kap[j]; };
     double xr[XR];
+    double pb1 = 0.0, pb2 = 0.0;          // topography: psi_B of the row (wavefront 0)
     if constexpr (W) {
       // WENO by columns: the sums over sub-stencil columns are shared by the
       // points of one x axis point
@@ -297,37 +391,68 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
         xpass<K, W, M>(tab, sd, win(pc), xr);
         wcol<K, W, M>(tab, sd, xr, kf, col);
 #pragma unroll
-        for (int h = 0; h < M; ++h) pt(wv, sd * M + h) = wpoint<K, W, M>(tab, sd, 2 + h, sd * M + h, col);
+        for (int h = 0; h < M; ++h)
+          pt(wv, sd * M + h) = layer(wpoint<K, W, M>(tab, sd, 2 + h, sd * M + h, col),
+                                     [&] { return s_xe(pc, sd ? ie_r : ie_l, h); });
       }
 #pragma unroll
       for (int h = 0; h < M; ++h) {
         asm volatile("" ::: "memory");
         xpass<K, W, M>(tab, 2 + h, win(pc), xr);
         wcol<K, W, M>(tab, 2 + h, xr, kf, col);
-        pt(wv, SM::PB + h) = wpoint<K, W, M>(tab, 2 + h, 0, 2 * M + h, col);
-        top[h] = wpoint<K, W, M>(tab, 2 + h, 1, 3 * M + h, col);
+        pt(wv, SM::PB + h) = layer(wpoint<K, W, M>(tab, 2 + h, 0, 2 * M + h, col), [&] { return s_ye(pc, h); });
+        top[h] = layer(wpoint<K, W, M>(tab, 2 + h, 1, 3 * M + h, col), [&] { return s_ye(pc + 1, h); });
+        if constexpr (TP) {
+          double xc[NR], xd[NR];
+          if (wv == 0) tpass(pc, 2 + h, xc, xd);
 #pragma unroll
-        for (int w = 0; w < M; ++w)
-          pt(wv, SM::PI + w * M + h) = wpoint<K, W, M>(tab, 2 + h, 2 + w, 4 * M + w * M + h, col);
+          for (int w = 0; w < M; ++w) {
+            const double v = wpoint<K, W, M>(tab, 2 + h, 2 + w, 4 * M + w * M + h, col);
+            if (wv == 0) psi_add(pc, h, w, v, xc, xd, pb1, pb2);
+            pt(wv, SM::PI + w * M + h) = layer(v, [&] { return s_cq(pc, w, h); });
+          }
+        } else {
+#pragma unroll
+          for (int w = 0; w < M; ++w)
+            pt(wv, SM::PI + w * M + h) = wpoint<K, W, M>(tab, 2 + h, 2 + w, 4 * M + w * M + h, col);
+        }
       }
     } else {
       asm volatile("" ::: "memory");
       xpass<K, W, M>(tab, 0, win(pc), xr);
 #pragma unroll
-      for (int h = 0; h < M; ++h) pt(wv, h) = point<K, W, M>(tab, 2 + h, h, xr, kf);
+      for (int h = 0; h < M; ++h) pt(wv, h) = layer(point<K, W, M>(tab, 2 + h, h, xr, kf), [&] { return s_xe(pc, ie_l, h); });
       asm volatile("" ::: "memory");
       xpass<K, W, M>(tab, 1, win(pc), xr);
 #pragma unroll
-      for (int h = 0; h < M; ++h) pt(wv, M + h) = point<K, W, M>(tab, 2 + h, M + h, xr, kf);
+      for (int h = 0; h < M; ++h)
+        pt(wv, M + h) = layer(point<K, W, M>(tab, 2 + h, M + h, xr, kf), [&] { return s_xe(pc, ie_r, h); });
 #pragma unroll 1
       for (int h = 0; h < M; ++h) {
         asm volatile("" ::: "memory");
         xpass<K, W, M>(tab, 2 + h, win(pc), xr);
-        pt(wv, SM::PB + h) = point<K, W, M>(tab, 0, 2 * M + h, xr, kf);
-        top[h] = point<K, W, M>(tab, 1, 3 * M + h, xr, kf);
+        pt(wv, SM::PB + h) = layer(point<K, W, M>(tab, 0, 2 * M + h, xr, kf), [&] { return s_ye(pc, h); });
+        top[h] = layer(point<K, W, M>(tab, 1, 3 * M + h, xr, kf), [&] { return s_ye(pc + 1, h); });
+        if constexpr (TP) {
+          double xd[NR];
+          if (wv == 0) dpass(pc, 2 + h, xd);
 #pragma unroll
-        for (int w = 0; w < M; ++w)
-          pt(wv, SM::PI + w * M + h) = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+          for (int w = 0; w < M; ++w) {
+            const double v = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+            if (wv == 0) psi_add(pc, h, w, v, xr, xd, pb1, pb2);
+            pt(wv, SM::PI + w * M + h) = layer(v, [&] { return s_cq(pc, w, h); });
+          }
+        } else {
+#pragma unroll
+          for (int w = 0; w < M; ++w)
+            pt(wv, SM::PI + w * M + h) = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+        }
+      }
+    }
+    if constexpr (TP) {
+      if (wv == 0) {
+        sm.psb[0][lane] = pb1;
+        sm.psb[1][lane] = pb2;
       }
     }
   };
@@ -346,9 +471,10 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
         // whether its row is reconstructed whole or only for its side
         WCol<K, M> col;
         wcol<K, W, M>(tab, 2 + h, xr, kf, col);
-        dst(h) = wpoint<K, W, M>(tab, 2 + h, side, (2 + side) * M + h, col);
+        dst(h) = layer(wpoint<K, W, M>(tab, 2 + h, side, (2 + side) * M + h, col),
+                       [&] { return s_ye(pc + side, h); });
       } else {
-        dst(h) = point<K, W, M>(tab, side, (2 + side) * M + h, xr, kf);
+        dst(h) = layer(point<K, W, M>(tab, side, (2 + side) * M + h, xr, kf), [&] { return s_ye(pc + side, h); });
       }
     }
   };
@@ -375,7 +501,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
         qR[v] = real ? pt(v, SM::PB + h) : dflt;
       }
       double F[3];
-      lmars(qL, qR, xg, Xe[j], sqv, sqe[j], 1, ia, F);
+      lmars<TP>(qL, qR, xg, Xe[j], sqv, sqe[j], 1, ia, F, TP ? s_ye(j, h) : 0.0);
 #pragma unroll
       for (int v = 0; v < 3; ++v) gb[v] = fma(gw[h], F[v], gb[v]);
     }
@@ -403,7 +529,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
         qR[v] = xdead ? dflt : (i == n ? btp[(((size_t)1 * n + j) * M + h) * 3 + v] : r);
       }
       double F[3];
-      lmars(qL, qR, Xei, Xg[j * M + h], sqxe, sqg[j * M + h], 0, ia, F);
+      lmars<TP>(qL, qR, Xei, Xg[j * M + h], sqxe, sqg[j * M + h], 0, ia, F, TP ? s_xe(j, ie, h) : 0.0);
 #pragma unroll
       for (int v = 0; v < 3; ++v) fl[v] = fma(gw[h], F[v], fl[v]);
     }
@@ -440,14 +566,16 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     double kap[1];
     auto kf = [&](int jj) -> double { return kap[jj]; };
     double xr[XR];
+    double pb1 = 0.0, pb2 = 0.0;          // topography: psi_B of the row (wavefront 0)
     asm volatile("" ::: "memory");
     xpass<K, W, M>(tab, 0, win(pc), xr);
 #pragma unroll
-    for (int h = 0; h < M; ++h) pt(wv, h) = point<K, W, M>(tab, 2 + h, h, xr, kf);
+    for (int h = 0; h < M; ++h) pt(wv, h) = layer(point<K, W, M>(tab, 2 + h, h, xr, kf), [&] { return s_xe(pc, ie_l, h); });
     asm volatile("" ::: "memory");
     xpass<K, W, M>(tab, 1, win(pc), xr);
 #pragma unroll
-    for (int h = 0; h < M; ++h) pt(wv, M + h) = point<K, W, M>(tab, 2 + h, M + h, xr, kf);
+    for (int h = 0; h < M; ++h)
+      pt(wv, M + h) = layer(point<K, W, M>(tab, 2 + h, M + h, xr, kf), [&] { return s_xe(pc, ie_r, h); });
     s1 = 0.0;
     s2 = 0.0;
 #pragma unroll 1
@@ -457,15 +585,32 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       for (int h = h0; h < h1; ++h) {
         asm volatile("" ::: "memory");
         xpass<K, W, M>(tab, 2 + h, win(pc), xr);
-        pt(wv, SM::PB + h) = point<K, W, M>(tab, 0, 2 * M + h, xr, kf);
-        top[h] = point<K, W, M>(tab, 1, 3 * M + h, xr, kf);
+        pt(wv, SM::PB + h) = layer(point<K, W, M>(tab, 0, 2 * M + h, xr, kf), [&] { return s_ye(pc, h); });
+        top[h] = layer(point<K, W, M>(tab, 1, 3 * M + h, xr, kf), [&] { return s_ye(pc + 1, h); });
+        if constexpr (TP) {
+          double xd[NR];
+          if (wv == 0) dpass(pc, 2 + h, xd);
 #pragma unroll
-        for (int w = 0; w < M; ++w)
-          pt(wv, SM::PI + w * SM::HC + (h - h0)) = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+          for (int w = 0; w < M; ++w) {
+            const double v = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+            if (wv == 0) psi_add(pc, h, w, v, xr, xd, pb1, pb2);
+            pt(wv, SM::PI + w * SM::HC + (h - h0)) = layer(v, [&] { return s_cq(pc, w, h); });
+          }
+        } else {
+#pragma unroll
+          for (int w = 0; w < M; ++w)
+            pt(wv, SM::PI + w * SM::HC + (h - h0)) = point<K, W, M>(tab, 2 + w, 4 * M + w * M + h, xr, kf);
+        }
       }
       __syncthreads();
       if (wv == 2) sources_chunk(pc, h0, h1, s1, s2);
       if (c + 1 < SM::NCH) __syncthreads();
+    }
+    if constexpr (TP) {
+      if (wv == 0) {
+        sm.psb[0][lane] = pb1;
+        sm.psb[1][lane] = pb2;
+      }
     }
   };
   // wavefront 2: metric and Coriolis sources of row j (cell quadrature)
@@ -490,6 +635,10 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
         s1 = fma(g2, a1, s1);
         s2 = fma(g2, a2, s2);
       }
+    }
+    if constexpr (TP) {
+      s1 += sm.psb[0][lane];
+      s2 += sm.psb[1][lane];
     }
     src(0) = s1;
     src(1) = s2;
@@ -545,12 +694,19 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     const int jr = j - 1;
     const size_t o_in = wv * vs + p * plane + (size_t)(jr + R) * P + (i + R);
     const double qn_c = (fin && A.qn) ? A.qn[o_in] : 0.0;
-    const double qs_c = fin ? sm.sq[wv][(jr + R) % NR][wc] : 0.0;
+    // (with topography the window's mass is sqrtG phi_t: q_s is read again)
+    double qs_c = 0.0;
+    if constexpr (TP) qs_c = fin ? (wv == 0 ? A.q[o_in] : sm.sq[wv][(jr + R) % NR][wc]) : 0.0;
+    else qs_c = fin ? sm.sq[wv][(jr + R) % NR][wc] : 0.0;
     if (wv == 1) yflux(j);
     if (!last) {
       if (wv == 0) xflux(j);
       if (wv == 2) {
         if constexpr (SM::kChunk) {
+          if constexpr (TP) {
+            s1c += sm.psb[0][lane];
+            s2c += sm.psb[1][lane];
+          }
           src(0) = s1c;
           src(1) = s2c;
         } else {

@@ -35,25 +35,25 @@ __global__ __launch_bounds__(256) void k_fill_halo(GhostDev g, double* __restric
 // ---------------------------------------------------------------------------
 // Panel-edge traces: bt[((A*4+side)*n + t)*m + h][var], in A's variables
 // ---------------------------------------------------------------------------
-template <int K, bool W, int M>
+template <int K, bool W, int M, bool TP>
 __global__ __launch_bounds__(64) void k_edge_traces(const double* __restrict__ tab_, const int32_t* __restrict__ itab_,
                                                      GridScalars gs, const double* __restrict__ q,
-                                                     double* __restrict__ bt) {
+                                                     double* __restrict__ bt, TopoDev tp) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int idx = t / kEdgeLanes;
   if (idx >= 24 * gs.n) return;   // the whole lane group leaves together
-  edge_trace<K, W, M>((cdp)tab_, (cip)itab_, gs, q, bt, idx, t % kEdgeLanes);
+  edge_trace<K, W, M, TP>((cdp)tab_, (cip)itab_, gs, q, bt, idx, t % kEdgeLanes, tp);
 }
 
 // ---------------------------------------------------------------------------
 // Fused stage kernel: one work item per workgroup
 // ---------------------------------------------------------------------------
-template <int K, bool W, int M>
+template <int K, bool W, int M, bool TP>
 __global__ __launch_bounds__(kStageThreads) void k_stage(const double* __restrict__ tab_, GridScalars gs,
                                                                 StageArgs A) {
   using C = Cfg<K, W, M>;
-  __shared__ StageSmem<K, W, M> sm;
-  stage_tile<K, W, M>(tab_, (cdp)tab_ + C::O.fcoef, gs, A, blockIdx.x, sm);
+  __shared__ StageSmem<K, W, M, TP> sm;
+  stage_tile<K, W, M, TP>(tab_, (cdp)tab_ + C::O.fcoef, gs, A, blockIdx.x, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -121,17 +121,27 @@ int launch_fill_halo(const GhostDev& g, double* q, int plane, int lanes, void* s
 
 template <int K, bool W, int M>
 static int edge_traces_t(const double* tab, const int32_t* itab, const GridScalars& gs, const double* q, double* bt,
-                         void* stream) {
+                         const TopoDev& tp, void* stream) {
   const int total = 24 * gs.n;
-  hipLaunchKernelGGL((k_edge_traces<K, W, M>), dim3((total * kEdgeLanes + 63) / 64), dim3(64), 0, (hipStream_t)stream, tab,
-                     itab, gs, q, bt);
+  const dim3 grid((total * kEdgeLanes + 63) / 64);
+  if (tp.sbar)
+    hipLaunchKernelGGL((k_edge_traces<K, W, M, true>), grid, dim3(64), 0, (hipStream_t)stream, tab, itab, gs, q, bt,
+                       tp);
+  else
+    hipLaunchKernelGGL((k_edge_traces<K, W, M, false>), grid, dim3(64), 0, (hipStream_t)stream, tab, itab, gs, q, bt,
+                       tp);
   return (int)hipGetLastError();
 }
 
 template <int K, bool W, int M>
 static int stage_t(const double* tab, const GridScalars& gs, const StageArgs& a, void* stream) {
   const int items = stage_items(a.strip_w, a.n_strips, a.n_segs);
-  hipLaunchKernelGGL((k_stage<K, W, M>), dim3(items), dim3(kStageThreads), 0, (hipStream_t)stream, tab, gs, a);
+  if (a.tp.sbar)
+    hipLaunchKernelGGL((k_stage<K, W, M, true>), dim3(items), dim3(kStageThreads), 0, (hipStream_t)stream, tab, gs,
+                       a);
+  else
+    hipLaunchKernelGGL((k_stage<K, W, M, false>), dim3(items), dim3(kStageThreads), 0, (hipStream_t)stream, tab, gs,
+                       a);
   return (int)hipGetLastError();
 }
 
@@ -156,15 +166,16 @@ static int stage_t(const double* tab, const GridScalars& gs, const StageArgs& a,
   } while (0)
 
 int launch_edge_traces(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs,
-                       const double* q, double* bt, void* stream) {
-  HOPE_DISPATCH(edge_traces_t, tab, itab, gs, q, bt, stream);
+                       const double* q, double* bt, const TopoDev& topo, void* stream) {
+  HOPE_DISPATCH(edge_traces_t, tab, itab, gs, q, bt, topo, stream);
 }
 
 int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs, const double* q,
                  const double* qn, double* out, int out_padded, double ca, double cb, double cc, const double* bt,
-                 int strip_w, int seg_h, void* stream) {
+                 int strip_w, int seg_h, const TopoDev& topo, void* stream) {
   (void)itab;
   StageArgs a;
+  a.tp = topo;
   a.q = q;
   a.qn = qn;
   a.out = out;

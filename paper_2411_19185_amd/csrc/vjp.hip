@@ -34,9 +34,11 @@ namespace hope {
 // Adjoint helpers
 // ---------------------------------------------------------------------------
 // reverse mode of lmars(): given mu = dL/dF, accumulate dL/dqL and dL/dqR
+// (TOPO: the pressure of phi* + phi_s, phi_s = sps / sqrtG a constant)
+template <bool TOPO = false>
 __device__ __forceinline__ void lmars_adj(const double* qL, const double* qR, double X, double Y, double sqx,
                                           double sqy, int dir, double ia, const double* mu, double* bL,
-                                          double* bR) {
+                                          double* bR, double sps = 0.0) {
   const double ox = sqx * sqx, oy = sqy * sqy;
   const double d2 = fma(X, X, oy);
   const double dl = sqrt_g(d2);
@@ -67,7 +69,7 @@ __device__ __forceinline__ void lmars_adj(const double* qL, const double* qR, do
   }
   mmb += amb * sg;
   const double prb = dir == 0 ? mu[1] * oy + mu[2] * X * Y : mu[1] * X * Y + mu[2] * ox;
-  const double psb = prb * ps * idl;
+  const double psb = prb * (TOPO ? fma(sps, isg, ps) : ps) * idl;
   const double msb = mmb * sgii;
   double phiLb = 0.5 * psb, phiRb = 0.5 * psb;
   double cb = -0.5 * psb * (upR - upL);
@@ -117,9 +119,10 @@ __device__ __forceinline__ int side_pt(int sd, int h) { return sd * M + h; }
 // k_vjp_traces: T[(pt*3 + v)*cells + c], one lane per (variable, cell) (struct of arrays: lanes of
 // neighbouring cells touch neighbouring addresses)
 // ---------------------------------------------------------------------------
-template <int K, bool W, int M>
+template <int K, bool W, int M, bool TP>
 __global__ __launch_bounds__(64) void k_vjp_traces(const double* __restrict__ tab_, GridScalars gs,
-                                                    const double* __restrict__ q, double* __restrict__ T) {
+                                                    const double* __restrict__ q, double* __restrict__ T,
+                                                    TopoDev tp) {
   using C = Cfg<K, W, M>;
   constexpr int NP = 4 * M + M * M;
   const cdp tab = (cdp)tab_;
@@ -130,7 +133,13 @@ __global__ __launch_bounds__(64) void k_vjp_traces(const double* __restrict__ ta
   const int v = idx / cells_i, c = idx % cells_i;   // one lane per (variable, cell)
   const int p = c / (n * n), j = (c / n) % n, i = c % n;
   const size_t vs = (size_t)6 * P * P;
-  const double* c0 = q + (size_t)p * P * P + (size_t)(j + C::R) * P + (i + C::R);
+  const size_t coff = (size_t)p * P * P + (size_t)(j + C::R) * P + (i + C::R);
+  const double* c0 = q + coff;
+  // topography: the mass is reconstructed as sqrtG phi_t (cell averages of
+  // sqrtG phi_s added), and each point value stored is the layer's own
+  // sqrtG phi, as the forward stage kernel computes it
+  const double* s0 = TP ? tp.sbar + coff : nullptr;
+  const bool topo_v = TP && v == 0;
   const size_t cells = (size_t)cells_i;
   double* out = T + c;
   // the lane's stencil of one variable, staged in LDS: all its loads are
@@ -141,11 +150,18 @@ __global__ __launch_bounds__(64) void k_vjp_traces(const double* __restrict__ ta
   {
     if constexpr (kStage) {
 #pragma unroll
-      for (int o = 0; o < K * K; ++o) st[o][lane] = c0[v * vs + (o / K - C::R) * P + (o % K - C::R)];
+      for (int o = 0; o < K * K; ++o) {
+        const int off = (o / K - C::R) * P + (o % K - C::R);
+        st[o][lane] = c0[v * vs + off] + (topo_v ? s0[off] : 0.0);
+      }
     }
     auto at = [&](int dy, int dx) -> double {
       if constexpr (kStage) return st[(dy + C::R) * K + dx + C::R][lane];
-      else return c0[v * vs + dy * P + dx];
+      else return c0[v * vs + dy * P + dx] + (topo_v ? s0[dy * P + dx] : 0.0);
+    };
+    auto sub = [&](double val, auto s_of) -> double {
+      if constexpr (TP) return topo_v ? val - s_of() : val;
+      else return val;
     };
     double kap[W ? C::S : 1];
     if constexpr (W) weno_kappa<K, W, M>(tab, gs.eps, at, [&](int jj, double x) { kap[jj] = x; });
@@ -166,24 +182,32 @@ __global__ __launch_bounds__(64) void k_vjp_traces(const double* __restrict__ ta
     for (int sd = 0; sd < 2; ++sd)
       column(sd, [&](auto val) {
 #pragma unroll
-        for (int h = 0; h < M; ++h) out[((sd * M + h) * 3 + v) * cells] = val(2 + h, sd * M + h);
+        for (int h = 0; h < M; ++h)
+          out[((sd * M + h) * 3 + v) * cells] =
+              sub(val(2 + h, sd * M + h), [&] { return topo_cell_side<M>(tp, n, p, i, j, sd, h); });
       });
 #pragma unroll 1
     for (int h = 0; h < M; ++h)
       column(2 + h, [&](auto val) {
-        out[((2 * M + h) * 3 + v) * cells] = val(0, 2 * M + h);
-        out[((3 * M + h) * 3 + v) * cells] = val(1, 3 * M + h);
+        out[((2 * M + h) * 3 + v) * cells] = sub(val(0, 2 * M + h), [&] { return topo_cell_side<M>(tp, n, p, i, j, 2, h); });
+        out[((3 * M + h) * 3 + v) * cells] = sub(val(1, 3 * M + h), [&] { return topo_cell_side<M>(tp, n, p, i, j, 3, h); });
 #pragma unroll
-        for (int w = 0; w < M; ++w) out[((4 * M + w * M + h) * 3 + v) * cells] = val(2 + w, 4 * M + w * M + h);
+        for (int w = 0; w < M; ++w)
+          out[((4 * M + w * M + h) * 3 + v) * cells] = sub(val(2 + w, 4 * M + w * M + h), [&] {
+            return tp.sc[((((size_t)p * n + j) * n + i) * M + w) * M + h];
+          });
       });
   }
 }
 
 // the converted neighbour trace at panel side sd, position t, Gauss node h of panel p
-template <int M>
+// (topography: the converted sqrtG phi_t, B's stored sqrtG phi plus its
+// sqrtG phi_s, less sqrtG phi_s at this panel's point, as the forward forms it)
+template <int M, bool TP = false>
 __device__ __forceinline__ void outside_state(cdp tab, cip itab, const TabOffsets& O, int n, int P, int r,
                                               const double* __restrict__ T, int p, int sd, int t, int h,
-                                              double* out, cdp* conv, int* bcell, int* bpt) {
+                                              double* out, cdp* conv, int* bcell, int* bpt,
+                                              const TopoDev& tp = TopoDev()) {
   constexpr int NP = 4 * M + M * M;
   const int idx = (p * 4 + sd) * n + t;
   const int off = itab[O.i_cell + idx];
@@ -195,7 +219,10 @@ __device__ __forceinline__ void outside_state(cdp tab, cip itab, const TabOffset
   const size_t cells = (size_t)6 * n * n;
   const double* src = T + (size_t)pt * 3 * cells + cb;
   cdp cv = tab + O.bt_conv + ((size_t)idx * M + h) * 5;
-  out[0] = cv[0] * src[0];
+  if constexpr (TP)
+    out[0] = cv[0] * (src[0] + topo_cell_side<M>(tp, n, B, ib, jb, bs, hb)) - topo_side_point<M>(tp, n, idx, h);
+  else
+    out[0] = cv[0] * src[0];
   out[1] = cv[1] * src[cells] + cv[2] * src[2 * cells];
   out[2] = cv[3] * src[cells] + cv[4] * src[2 * cells];
   *conv = cv;
@@ -212,10 +239,11 @@ __device__ __forceinline__ void outside_state(cdp tab, cip itab, const TabOffset
 // k_vjp_edges).  Each point slot has exactly one writer.  The remaining
 // 6 n^2 lanes take one cell each: the source adjoint at its m^2 nodes.
 // ---------------------------------------------------------------------------
-template <int K, bool W, int M>
+template <int K, bool W, int M, bool TP>
 __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ tab_, const int32_t* __restrict__ itab_,
                                                     GridScalars gs, const double* __restrict__ T,
-                                                    const double* __restrict__ w, double* __restrict__ Lam) {
+                                                    const double* __restrict__ w, double* __restrict__ Lam,
+                                                    TopoDev tp, double* __restrict__ Lder) {
   using C = Cfg<K, W, M>;
   const cdp tab = (cdp)tab_;
   const cip itab = (cip)itab_;
@@ -255,20 +283,24 @@ __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ ta
 #pragma unroll
         for (int v = 0; v < 3; ++v) qL[v] = tr(sdL * M + h, v, cL);
       } else {
-        outside_state<M>(tab, itab, O, n, P, gs.r, T, p, sdR, a, h, qL, &cv, &bc, &bp);
+        outside_state<M, TP>(tab, itab, O, n, P, gs.r, T, p, sdR, a, h, qL, &cv, &bc, &bp, tp);
       }
       if (inR) {
 #pragma unroll
         for (int v = 0; v < 3; ++v) qR[v] = tr(sdR * M + h, v, cR);
       } else {
-        outside_state<M>(tab, itab, O, n, P, gs.r, T, p, sdL, a, h, qR, &cv, &bc, &bp);
+        outside_state<M, TP>(tab, itab, O, n, P, gs.r, T, p, sdL, a, h, qR, &cv, &bc, &bp, tp);
       }
       double X, Y, sx, sy;
       if (dir == 0) { X = Xe[e]; sx = sqe[e]; Y = Xg[a * M + h]; sy = sqg[a * M + h]; }
       else { X = Xg[a * M + h]; sx = sqg[a * M + h]; Y = Xe[e]; sy = sqe[e]; }
       double mu[3] = {gw[h] * dF[0], gw[h] * dF[1], gw[h] * dF[2]};
       double bL[3] = {0, 0, 0}, bR[3] = {0, 0, 0};
-      lmars_adj(qL, qR, X, Y, sx, sy, dir, ia, mu, bL, bR);
+      double sps = 0.0;
+      if constexpr (TP)
+        sps = dir == 0 ? tp.sx[(((size_t)p * n + a) * (n + 1) + e) * M + h]
+                       : tp.sy[(((size_t)p * (n + 1) + e) * n + a) * M + h];
+      lmars_adj<TP>(qL, qR, X, Y, sx, sy, dir, ia, mu, bL, bR, sps);
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         if (inL) lam(sdL * M + h, v, cL) = bL[v];
@@ -291,6 +323,16 @@ __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ ta
       double Qb[3] = {0, 0, 0};
       sources_adj(tr(pt, 0, c), tr(pt, 1, c), tr(pt, 2, c), X, Y, fc[0] + fc[1] * X + fc[2] * Y,
                   gs.omega2, g2 * wv(1, c), g2 * wv(2, c), Qb);
+      if constexpr (TP) {
+        // psi_B (2.14) is linear in sqrtG phi_t at the node and its two
+        // derivatives; the latter's cotangents go to Lder for the stencil adjoint
+        double Tb, Txib, Tetab;
+        psi_b_adj(X, Y, tp.sc[((((size_t)p * n + j) * n + i) * M + vv) * M + h], invd, ia, g2 * wv(1, c),
+                  g2 * wv(2, c), Tb, Txib, Tetab);
+        Qb[0] += Tb;
+        Lder[((size_t)(vv * M + h)) * cells + c] = Txib;
+        Lder[((size_t)(M * M + vv * M + h)) * cells + c] = Tetab;
+      }
 #pragma unroll
       for (int v = 0; v < 3; ++v) lam(pt, v, c) = Qb[v];
     }
@@ -300,10 +342,11 @@ __global__ __launch_bounds__(64) void k_vjp_points(const double* __restrict__ ta
 // k_vjp_edges: the neighbour panel's flux at its edge points, adjoint w.r.t.
 // the converted trace, added to the owning cell's point cotangent
 // ---------------------------------------------------------------------------
-template <int K, bool W, int M>
+template <int K, bool W, int M, bool TP>
 __global__ __launch_bounds__(64) void k_vjp_edges(const double* __restrict__ tab_, const int32_t* __restrict__ itab_,
                                                    GridScalars gs, const double* __restrict__ T,
-                                                   const double* __restrict__ w, double* __restrict__ Lam) {
+                                                   const double* __restrict__ w, double* __restrict__ Lam,
+                                                   TopoDev tp) {
   using C = Cfg<K, W, M>;
   constexpr int NP = 4 * M + M * M;
   const cdp tab = (cdp)tab_;
@@ -327,7 +370,7 @@ __global__ __launch_bounds__(64) void k_vjp_edges(const double* __restrict__ tab
   for (int v = 0; v < 3; ++v) qo[v] = T[((size_t)(sd * M + h) * 3 + v) * nn * 6 + c];
   cdp cv;
   int bc, bp;
-  outside_state<M>(tab, itab, O, n, P, gs.r, T, p, sd, t, h, qn, &cv, &bc, &bp);
+  outside_state<M, TP>(tab, itab, O, n, P, gs.r, T, p, sd, t, h, qn, &cv, &bc, &bp, tp);
   const bool own_is_right = (sd == 0 || sd == 2);
   const int dir = sd < 2 ? 0 : 1;
   const int e = sd == 0 ? 0 : sd == 1 ? n : sd == 2 ? 0 : n;
@@ -341,8 +384,9 @@ __global__ __launch_bounds__(64) void k_vjp_edges(const double* __restrict__ tab
     mu[v] = gw[h] * (own_is_right ? wc : -wc) * invd;
   }
   double bL[3] = {0, 0, 0}, bR[3] = {0, 0, 0};
-  if (own_is_right) lmars_adj(qn, qo, X, Y, sx, sy, dir, ia, mu, bL, bR);
-  else lmars_adj(qo, qn, X, Y, sx, sy, dir, ia, mu, bL, bR);
+  const double sps = TP ? topo_side_point<M>(tp, n, (p * 4 + sd) * n + t, h) : 0.0;
+  if (own_is_right) lmars_adj<TP>(qn, qo, X, Y, sx, sy, dir, ia, mu, bL, bR, sps);
+  else lmars_adj<TP>(qo, qn, X, Y, sx, sy, dir, ia, mu, bL, bR, sps);
   double ob[3];                                   // cotangent of the converted outside state
 #pragma unroll
   for (int v = 0; v < 3; ++v) ob[v] = own_is_right ? bL[v] : bR[v];
@@ -356,10 +400,44 @@ __global__ __launch_bounds__(64) void k_vjp_edges(const double* __restrict__ tab
 // ---------------------------------------------------------------------------
 // k_vjp_weno: Dl[(o*3 + v)*cells + c] = cotangent of stencil cell o of cell c
 // ---------------------------------------------------------------------------
-template <int K, bool W, int M>
+// topography: the cotangents Lder of d(sqrtG phi_t)/dxi and /deta at the
+// cell nodes (psi_B of (2.14)) reach the mass stencil through the centred
+// derivative weights, d/dxi = sum_b wc_y[b] sum_a wd_x[a] q[b][a] and
+// d/deta = sum_b wd_y[b] sum_a wc_x[a] q[b][a] at x node h, y node w
+template <int K, int M, typename Add>
+__device__ __forceinline__ void topo_derivative_adj(cdp tab, const double* __restrict__ Lder, size_t cells, int c,
+                                                    Add add) {
+  using C = Cfg<K, false, M>;
+  cdp wc = tab + C::O.wc, wd = tab + C::O.wd;
+#pragma unroll 1
+  for (int row = 0; row < K; ++row) {
+    double ya[M], yb[M];
+#pragma unroll
+    for (int h = 0; h < M; ++h) {
+      double sa = 0.0, sb = 0.0;
+#pragma unroll
+      for (int w = 0; w < M; ++w) {
+        sa = fma(Lder[(size_t)(w * M + h) * cells + c], wc[(2 + w) * K + row], sa);
+        sb = fma(Lder[(size_t)(M * M + w * M + h) * cells + c], wd[(2 + w) * K + row], sb);
+      }
+      ya[h] = sa;
+      yb[h] = sb;
+    }
+#pragma unroll
+    for (int col = 0; col < K; ++col) {
+      double s = 0.0;
+#pragma unroll
+      for (int h = 0; h < M; ++h) s = fma(ya[h], wd[(2 + h) * K + col], fma(yb[h], wc[(2 + h) * K + col], s));
+      add(row * K + col, s);
+    }
+  }
+}
+
+template <int K, bool W, int M, bool TP>
 __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_, GridScalars gs,
                                                   const double* __restrict__ q, const double* __restrict__ Lam,
-                                                  double* __restrict__ Dl) {
+                                                  double* __restrict__ Dl, TopoDev tp,
+                                                  const double* __restrict__ Lder) {
   using C = Cfg<K, W, M>;
   constexpr int NP = 4 * M + M * M, R = C::R, L = C::L, S = C::S, NR = C::NR, NA = C::NA;
   const cdp tab = (cdp)tab_;
@@ -370,13 +448,19 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
   const int v = idx / cells, c = idx % cells;
   const int p = c / (n * n), j = (c / n) % n, i = c % n;
   const size_t vs = (size_t)6 * P * P;
-  const double* c0 = q + v * vs + (size_t)p * P * P + (size_t)(j + R) * P + (i + R);
-  // the lane's stencil, staged in LDS (see k_vjp_traces)
+  const size_t coff = (size_t)p * P * P + (size_t)(j + R) * P + (i + R);
+  const double* c0 = q + v * vs + coff;
+  // the lane's stencil, staged in LDS (see k_vjp_traces); with topography
+  // the mass stencil is that of sqrtG phi_t
   __shared__ double st[K * K][64];
   __shared__ double sl[NP][64];
   const int lane = threadIdx.x;
+  const bool topo_v = TP && v == 0;
 #pragma unroll
-  for (int o = 0; o < K * K; ++o) st[o][lane] = c0[(o / K - R) * P + (o % K - R)];
+  for (int o = 0; o < K * K; ++o) {
+    const int off = (o / K - R) * P + (o % K - R);
+    st[o][lane] = c0[off] + (topo_v ? tp.sbar[coff + off] : 0.0);
+  }
   auto at = [&](int dy, int dx) -> double { return st[(dy + R) * K + dx + R][lane]; };
   {
     const double* lam = Lam + (size_t)v * cells + c;     // point pt at lam[pt * 3 * cells]
@@ -647,6 +731,9 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
 #pragma unroll
         for (int a = 0; a < L; ++a) dq[row * K + (sx + a)] += V[(sx * L + al) * L + a] * trb[row][al];
   }
+  if constexpr (TP) {
+    if (v == 0) topo_derivative_adj<K, M>(tab, Lder, cells, c, [&](int o, double x) { dq[o] += x; });
+  }
   double* out = Dl + (size_t)v * cells + c;
 #pragma unroll
   for (int o = 0; o < K * K; ++o) out[(size_t)o * 3 * cells] = dq[o];
@@ -658,9 +745,10 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
 // stencil cell (row, col) is sum over points of lam_pt wc[py][row] wc[px][col];
 // per row: first the y-sums for each x axis point, then the x-sums.
 // ---------------------------------------------------------------------------
-template <int K, bool W, int M>
+template <int K, bool W, int M, bool TP>
 __global__ __launch_bounds__(64) void k_vjp_tpp(const double* __restrict__ tab_, GridScalars gs,
-                                                 const double* __restrict__ Lam, double* __restrict__ Dl) {
+                                                 const double* __restrict__ Lam, double* __restrict__ Dl,
+                                                 const double* __restrict__ Lder) {
   using C = Cfg<K, W, M>;
   constexpr int NA = C::NA;
   const cdp tab = (cdp)tab_;
@@ -698,6 +786,10 @@ __global__ __launch_bounds__(64) void k_vjp_tpp(const double* __restrict__ tab_,
       for (int px = 0; px < NA; ++px) s = fma(yr[px], wc[px * K + col], s);
       out[(size_t)(row * K + col) * 3 * cells] = s;
     }
+  }
+  if constexpr (TP) {
+    if (v == 0)
+      topo_derivative_adj<K, M>(tab, Lder, (size_t)cells, c, [&](int o, double x) { out[(size_t)o * 3 * cells] += x; });
   }
 }
 
@@ -810,7 +902,7 @@ __global__ __launch_bounds__(256) void k_vjp_ghost_t(int rows, int n, int P, con
 // ---------------------------------------------------------------------------
 // Launcher of the whole adjoint
 // ---------------------------------------------------------------------------
-template <int K, bool W, int M>
+template <int K, bool W, int M, bool TP>
 static int vjp_t(const VjpArgs& a, int step, void* stream) {
   const hipStream_t s = (hipStream_t)stream;
   const GridScalars& gs = a.gs;
@@ -818,25 +910,26 @@ static int vjp_t(const VjpArgs& a, int step, void* stream) {
   const int cells = 6 * n * n;
   switch (step) {
     case kVjpTraces:
-      hipLaunchKernelGGL((k_vjp_traces<K, W, M>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q, a.T);
+      hipLaunchKernelGGL((k_vjp_traces<K, W, M, TP>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q, a.T,
+                         a.topo);
       break;
     case kVjpPoints:
-      hipLaunchKernelGGL((k_vjp_points<K, W, M>), dim3((12 * n * (n + 1) + cells + 63) / 64), dim3(64), 0, s, a.tab,
-                         a.itab, gs, a.T, a.w, a.Lam);
+      hipLaunchKernelGGL((k_vjp_points<K, W, M, TP>), dim3((12 * n * (n + 1) + cells + 63) / 64), dim3(64), 0, s,
+                         a.tab, a.itab, gs, a.T, a.w, a.Lam, a.topo, a.Lder);
       break;
     case kVjpEdges: {
       const int ept = 24 * n * M;
-      hipLaunchKernelGGL((k_vjp_edges<K, W, M>), dim3((ept + 63) / 64), dim3(64), 0, s, a.tab, a.itab, gs, a.T, a.w,
-                         a.Lam);
+      hipLaunchKernelGGL((k_vjp_edges<K, W, M, TP>), dim3((ept + 63) / 64), dim3(64), 0, s, a.tab, a.itab, gs, a.T,
+                         a.w, a.Lam, a.topo);
       break;
     }
     case kVjpWeno:
       if constexpr (W)
-        hipLaunchKernelGGL((k_vjp_weno<K, W, M>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q, a.Lam,
-                           a.Dl);
+        hipLaunchKernelGGL((k_vjp_weno<K, W, M, TP>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q,
+                           a.Lam, a.Dl, a.topo, a.Lder);
       else
-        hipLaunchKernelGGL((k_vjp_tpp<K, W, M>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.Lam,
-                           a.Dl);
+        hipLaunchKernelGGL((k_vjp_tpp<K, W, M, TP>), dim3((3 * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.Lam,
+                           a.Dl, a.Lder);
       break;
     case kVjpGather: {
       const size_t padded = (size_t)18 * P * P;
@@ -856,23 +949,28 @@ static int vjp_t(const VjpArgs& a, int step, void* stream) {
   return (int)hipGetLastError();
 }
 
-int launch_vjp(int k, int weno, const VjpArgs& a, int step, void* stream) {
+template <bool TP>
+static int launch_vjp_t(int k, int weno, const VjpArgs& a, int step, void* stream) {
   if (!weno) {
     switch (k) {
-      case 3: return vjp_t<3, false, 2>(a, step, stream);
-      case 5: return vjp_t<5, false, 3>(a, step, stream);
-      case 7: return vjp_t<7, false, 4>(a, step, stream);
-      case 9: return vjp_t<9, false, 5>(a, step, stream);
-      case 11: return vjp_t<11, false, 6>(a, step, stream);
-      case 13: return vjp_t<13, false, 7>(a, step, stream);
+      case 3: return vjp_t<3, false, 2, TP>(a, step, stream);
+      case 5: return vjp_t<5, false, 3, TP>(a, step, stream);
+      case 7: return vjp_t<7, false, 4, TP>(a, step, stream);
+      case 9: return vjp_t<9, false, 5, TP>(a, step, stream);
+      case 11: return vjp_t<11, false, 6, TP>(a, step, stream);
+      case 13: return vjp_t<13, false, 7, TP>(a, step, stream);
     }
   } else {
     switch (k) {
-      case 3: return vjp_t<3, true, 2>(a, step, stream);
-      case 5: return vjp_t<5, true, 3>(a, step, stream);
+      case 3: return vjp_t<3, true, 2, TP>(a, step, stream);
+      case 5: return vjp_t<5, true, 3, TP>(a, step, stream);
     }
   }
   return (int)hipErrorInvalidValue;
+}
+
+int launch_vjp(int k, int weno, const VjpArgs& a, int step, void* stream) {
+  return a.topo.sbar ? launch_vjp_t<true>(k, weno, a, step, stream) : launch_vjp_t<false>(k, weno, a, step, stream);
 }
 
 }  // namespace hope

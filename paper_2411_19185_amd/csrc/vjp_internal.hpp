@@ -26,6 +26,9 @@ struct VjpArgs {
                            // | (frame code of the ghost << 27), see GhostDev
   const GhostVal* gcval;   // canonical value records of the ghost map
   int64_t gt_nnz;
+  TopoDev topo;            // bottom topography (null sbar: none)
+  double* Lder;            // topography: cotangents of d(sqrtG phi_t)/dxi, /deta at the cell nodes,
+                           // [2][m*m][6n^2]
 };
 // the adjoint's kernels in launch order
 enum { kVjpTraces = 0, kVjpPoints, kVjpEdges, kVjpWeno, kVjpGather, kVjpGhostT, kVjpSteps };

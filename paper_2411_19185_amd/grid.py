@@ -8,7 +8,7 @@ import os
 import torch
 
 from ._lib import (HOPE_ERR_NUMERIC, HOPE_OK, HOPE_PROFILE_SELECT, HOPE_RK_SSP3, HOPE_RK_WS3, Layout, check, lib,
-                   make_desc)
+                   make_desc, surface_callback)
 
 
 def _stream() -> ctypes.c_void_p:
@@ -21,18 +21,23 @@ def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
 
 class Grid:
     """One cubed-sphere grid (n cells per panel edge), reconstruction order
-    and scheme ('tpp' or 'weno'), with the physical constants of the problem."""
+    and scheme ('tpp' or 'weno'), with the physical constants of the problem.
+    surface: optional bottom topography, a callable p -> phi_s (surface
+    geopotential at unit vectors p of shape (count, 3)), evaluated by the
+    library while the grid is built."""
 
     def __init__(self, n: int, order: int, scheme: str = "tpp", radius: float = 6.371e6,
                  omega: float = 7.292e-5, axis_tilt: float = 0.0, weno_eps: float = 1e-12,
-                 split_theta: float = 3.0, ghost_iters: int = 0, cache_dir: str | None = None):
+                 split_theta: float = 3.0, ghost_iters: int = 0, cache_dir: str | None = None, surface=None):
         if cache_dir is not None:
             cache_dir = os.path.expanduser(cache_dir)
             os.makedirs(cache_dir, exist_ok=True)
+        cb = surface_callback(surface) if surface is not None else None
         self.desc = make_desc(n, order, scheme, radius, omega, axis_tilt, weno_eps, split_theta,
-                              ghost_iters=ghost_iters, cache_dir=cache_dir)
+                              ghost_iters=ghost_iters, cache_dir=cache_dir, surface_fn=cb)
         h = ctypes.c_void_p()
         check(lib().hope_grid_create(ctypes.byref(self.desc), ctypes.byref(h)))
+        self.surface = surface
         self._h = h
         lay = Layout()
         check(lib().hope_grid_layout(h, ctypes.byref(lay)))
