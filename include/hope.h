@@ -310,9 +310,11 @@ int hope_batch_layout(const hope_batch* batch, hope_batch_info* out, int64_t* st
                       int64_t* field_offsets);
 /* Work-item shape per member (strip width 1..62, segment height 1..n; NULL
  * keeps the current values) and the fused-stage grid size (0: one workgroup
- * per item; otherwise that many workgroups stride the item list).  Rebuilds
- * and uploads the item list: allocates and synchronises.  Any values give
- * bitwise identical results. */
+ * per item; otherwise that many workgroups stride the item list).  Waits for
+ * the device, then rebuilds and uploads the item list: allocates and
+ * synchronises.  Any values give bitwise identical results.  Refused with
+ * HOPE_ERR_INVALID once a stage of the batch has been recorded under stream
+ * capture, since the graph refers to the item list. */
 int hope_batch_set_launch(hope_batch* batch, const int32_t* strip_w, const int32_t* seg_h, int32_t blocks);
 int hope_batch_get_launch(const hope_batch* batch, int32_t* strip_w, int32_t* seg_h, int32_t* blocks);
 /* Tendencies (3.1) of all members: fills the ghost rings of q_all, writes

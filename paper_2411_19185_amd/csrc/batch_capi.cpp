@@ -29,6 +29,9 @@ struct hope_batch {
   double* fcoef = nullptr;
   double* bt = nullptr;
   std::vector<void*> allocs;
+  // set once a stage has been recorded into a graph under stream capture: the
+  // graph holds the work-item list and member table, so they stay fixed
+  mutable bool captured = false;
 };
 
 namespace {
@@ -91,6 +94,10 @@ int upload_members(hope_batch* B) {
 
 int batch_stage(const hope_batch* B, double* in, const double* qn, double* out, int out_padded, double ca,
                 double cb, double cs, const double* dt, void* stream) {
+  hipStreamCaptureStatus cs_status = hipStreamCaptureStatusNone;
+  if (stream && hipStreamIsCapturing((hipStream_t)stream, &cs_status) == hipSuccess &&
+      cs_status != hipStreamCaptureStatusNone)
+    B->captured = true;
   int e = launch_batch_fill_halo(B->dgrids, B->n_grids, B->total_rows, B->mlist, B->mem, in, halo_lanes(B->k),
                                  stream);
   if (e) return hip_fail((hipError_t)e, "batch fill_halo launch");
@@ -239,6 +246,9 @@ int hope_batch_layout(const hope_batch* B, hope_batch_info* out, int64_t* state_
 
 int hope_batch_set_launch(hope_batch* B, const int32_t* strip_w, const int32_t* seg_h, int32_t blocks) {
   if (!B) return fail(HOPE_ERR_INVALID, "null argument");
+  if (B->captured)
+    return fail(HOPE_ERR_INVALID, "the launch shape of a batch is fixed once a stage has been captured in a graph "
+                                  "(the graph refers to its work-item list)");
   if (blocks < 0) return fail(HOPE_ERR_INVALID, "blocks must be >= 0");
   for (int i = 0; i < B->n_members; ++i) {
     const int n = B->hmem[i].gs.n;
@@ -255,6 +265,9 @@ int hope_batch_set_launch(hope_batch* B, const int32_t* strip_w, const int32_t* 
     bm.n_segs = (n + bm.seg_h - 1) / bm.seg_h;
     bm.half = bm.strip_w <= kHalfStrip;
   }
+  // work already queued on any stream may still read the member table and items
+  hipError_t e0 = hipDeviceSynchronize();
+  if (e0 != hipSuccess) return hip_fail(e0, "hipDeviceSynchronize");
   B->blocks = blocks;
   int st = upload_members(B);
   if (!st) st = build_items(B);

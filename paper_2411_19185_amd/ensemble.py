@@ -127,6 +127,10 @@ class Ensemble:
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             self.rk_step(q_all, dt, ws, scheme)
+        # the graph refers to this batch's device tables: it keeps the ensemble
+        # (and with it the batch and its grids) alive; the batch's launch shape
+        # is fixed from now on (hope_batch_set_launch refuses)
+        graph._hope_ensemble = self
         return graph
 
     def member_grid(self, i: int) -> Grid:

@@ -134,6 +134,32 @@ def test_batch_graph_replays_equal_eager_steps():
             assert same, (r, i)
 
 
+def test_captured_batch_keeps_its_launch_and_ensemble_alive():
+    """A graph captured from a batch refers to its work-item list and member
+    table: hope_batch_set_launch refuses afterwards (set_launch before the
+    capture works), and the graph keeps the ensemble alive, so a replay after
+    the caller drops it still equals eager steps on a separate ensemble."""
+    import gc
+
+    from paper_2411_19185_amd._lib import HopeError
+    ns = [10, 12]
+    ens, q_all, _, states, _ = _setup(ns, seed=410)
+    ens.set_launch([7, 6], [3, 4], 0)
+    dt = torch.tensor([cfl_dt(q) for q in states], dtype=torch.float64, device="cuda")
+    ref, q_ref, _, _, _ = _setup(ns, seed=410)
+    graph = ens.capture_step(q_all, dt)
+    with pytest.raises(HopeError) as e:
+        ens.set_launch([5, 5], [2, 2], 0)
+    assert "captured" in str(e.value)
+    del ens
+    gc.collect()
+    for _ in range(2):
+        graph.replay()
+        ref.rk_step(q_ref, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(q_all, q_ref)
+
+
 def test_full_size_uneven_ensemble_against_member_grids_and_oracle():
     """The 64-member ensemble of the benchmark (16 members each at C48, C64,
     C90 and C128, WENO5, own tilt and dt): two graph-replayed steps equal, for
