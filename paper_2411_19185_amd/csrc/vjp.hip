@@ -404,73 +404,53 @@ __global__ __launch_bounds__(64) void k_vjp_edges(const double* __restrict__ tab
 // cell nodes (psi_B of (2.14)) reach the mass stencil through the centred
 // derivative weights, d/dxi = sum_b wc_y[b] sum_a wd_x[a] q[b][a] and
 // d/deta = sum_b wd_y[b] sum_a wc_x[a] q[b][a] at x node h, y node w
-template <int K, int M, typename Add>
-__device__ __forceinline__ void topo_derivative_adj(cdp tab, const double* __restrict__ Lder, size_t cells, int c,
-                                                    Add add) {
+// one stencil row: add(col, x) for its K cells; ld(k) = Lder[k * cells + c]
+template <int K, int M, typename Ld, typename Add>
+__device__ __forceinline__ void topo_row_adj(cdp tab, Ld ld, int row, Add add) {
   using C = Cfg<K, false, M>;
   cdp wc = tab + C::O.wc, wd = tab + C::O.wd;
-#pragma unroll 1
-  for (int row = 0; row < K; ++row) {
-    double ya[M], yb[M];
+  double ya[M], yb[M];
 #pragma unroll
-    for (int h = 0; h < M; ++h) {
-      double sa = 0.0, sb = 0.0;
+  for (int h = 0; h < M; ++h) {
+    double sa = 0.0, sb = 0.0;
 #pragma unroll
-      for (int w = 0; w < M; ++w) {
-        sa = fma(Lder[(size_t)(w * M + h) * cells + c], wc[(2 + w) * K + row], sa);
-        sb = fma(Lder[(size_t)(M * M + w * M + h) * cells + c], wd[(2 + w) * K + row], sb);
-      }
-      ya[h] = sa;
-      yb[h] = sb;
+    for (int w = 0; w < M; ++w) {
+      sa = fma(ld(w * M + h), wc[(2 + w) * K + row], sa);
+      sb = fma(ld(M * M + w * M + h), wd[(2 + w) * K + row], sb);
     }
+    ya[h] = sa;
+    yb[h] = sb;
+  }
 #pragma unroll
-    for (int col = 0; col < K; ++col) {
-      double s = 0.0;
+  for (int col = 0; col < K; ++col) {
+    double s = 0.0;
 #pragma unroll
-      for (int h = 0; h < M; ++h) s = fma(ya[h], wd[(2 + h) * K + col], fma(yb[h], wc[(2 + h) * K + col], s));
-      add(row * K + col, s);
-    }
+    for (int h = 0; h < M; ++h) s = fma(ya[h], wd[(2 + h) * K + col], fma(yb[h], wc[(2 + h) * K + col], s));
+    add(col, s);
   }
 }
 
-template <int K, bool W, int M, bool TP>
-__global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_, GridScalars gs,
-                                                  const double* __restrict__ q, const double* __restrict__ Lam,
-                                                  double* __restrict__ Dl, TopoDev tp,
-                                                  const double* __restrict__ Lder) {
+template <int K, int M, typename Add>
+__device__ __forceinline__ void topo_derivative_adj(cdp tab, const double* __restrict__ Lder, size_t cells, int c,
+                                                    Add add) {
+  auto ld = [&](int k) -> double { return Lder[(size_t)k * cells + c]; };
+#pragma unroll 1
+  for (int row = 0; row < K; ++row) topo_row_adj<K, M>(tab, ld, row, [&](int col, double x) { add(row * K + col, x); });
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the genuine 2D WENO reconstruction (3.16)-(3.25) of one variable
+// of one cell: at(dy, dx) is the stencil, lamf(pt) the cotangent of point pt's
+// value; the cotangents of the K x K stencil cells are accumulated into
+// dq(o), o = (dy + R) K + dx + R (zero on entry).  Shared by the per-cell
+// kernel and the marching kernel, so both give the same values bit for bit.
+// ---------------------------------------------------------------------------
+template <int K, bool W, int M, typename At, typename LamF, typename Dq>
+__device__ __forceinline__ void weno_cell_adj(cdp tab, double eps, At at, LamF lamf, Dq dq) {
   using C = Cfg<K, W, M>;
-  constexpr int NP = 4 * M + M * M, R = C::R, L = C::L, S = C::S, NR = C::NR, NA = C::NA;
-  const cdp tab = (cdp)tab_;
-  const int n = gs.n, P = gs.P;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 18 * n * n) return;
-  const int cells = 6 * n * n;
-  const int v = idx / cells, c = idx % cells;
-  const int p = c / (n * n), j = (c / n) % n, i = c % n;
-  const size_t vs = (size_t)6 * P * P;
-  const size_t coff = (size_t)p * P * P + (size_t)(j + R) * P + (i + R);
-  const double* c0 = q + v * vs + coff;
-  // the lane's stencil, staged in LDS (see k_vjp_traces); with topography
-  // the mass stencil is that of sqrtG phi_t
-  __shared__ double st[K * K][64];
-  __shared__ double sl[NP][64];
-  const int lane = threadIdx.x;
-  const bool topo_v = TP && v == 0;
-#pragma unroll
-  for (int o = 0; o < K * K; ++o) {
-    const int off = (o / K - R) * P + (o % K - R);
-    st[o][lane] = c0[off] + (topo_v ? tp.sbar[coff + off] : 0.0);
-  }
-  auto at = [&](int dy, int dx) -> double { return st[(dy + R) * K + dx + R][lane]; };
-  {
-    const double* lam = Lam + (size_t)v * cells + c;     // point pt at lam[pt * 3 * cells]
-#pragma unroll
-    for (int pt = 0; pt < NP; ++pt) sl[pt][lane] = lam[(size_t)pt * 3 * cells];
-  }
+  constexpr int R = C::R, L = C::L, S = C::S, NR = C::NR, NA = C::NA;
+  (void)R;
   cdp V = tab + C::O.V, lamq = tab + C::O.lam, wsub = tab + C::O.wsub;
-  double dq[K * K];
-#pragma unroll
-  for (int o = 0; o < K * K; ++o) dq[o] = 0.0;
   // forward smoothness indicators
   double beta[S];
 #pragma unroll
@@ -511,7 +491,7 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
   double kap[S], kapb[S];
 #pragma unroll
   for (int jj = 0; jj < S; ++jj) {
-    kap[jj] = fma(tau, rcp(beta[jj] + gs.eps), 1.0);
+    kap[jj] = fma(tau, rcp(beta[jj] + eps), 1.0);
     kapb[jj] = 0.0;
   }
   // points, grouped by their x axis point px, evaluated by columns as the
@@ -577,7 +557,7 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
         else { py = k; pt = 4 * M + (k - 2) * M + h; }
       }
       const bool ym = weno_mixed_axis(K, M, py);
-      const double lb = sl[pt][lane];
+      const double lb = lamf(pt);
       // forward of the point
       double T[L], Ta[L];
       double B = 0.0, D = 0.0, A = 0.0, Cs = 0.0;
@@ -670,7 +650,7 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
       for (int row = 0; row < NR; ++row)
 #pragma unroll
         for (int a = 0; a < L; ++a)
-          dq[row * K + (sx + a)] = fma(wsub[(sx * NA + px) * L + a], xrb[sx * NR + row], dq[row * K + (sx + a)]);
+          dq(row * K + (sx + a)) = fma(wsub[(sx * NA + px) * L + a], xrb[sx * NR + row], dq(row * K + (sx + a)));
   };
 #pragma unroll 1
   for (int px = 0; px < NA; ++px) {
@@ -681,7 +661,7 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
   double taub = 0, betab[S];
 #pragma unroll
   for (int jj = 0; jj < S; ++jj) {
-    const double ib = rcp(beta[jj] + gs.eps);
+    const double ib = rcp(beta[jj] + eps);
     taub += kapb[jj] * ib;
     betab[jj] = -kapb[jj] * tau * ib * ib;
   }
@@ -729,8 +709,49 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
 #pragma unroll
       for (int al = 0; al < L; ++al)
 #pragma unroll
-        for (int a = 0; a < L; ++a) dq[row * K + (sx + a)] += V[(sx * L + al) * L + a] * trb[row][al];
+        for (int a = 0; a < L; ++a) dq(row * K + (sx + a)) += V[(sx * L + al) * L + a] * trb[row][al];
   }
+}
+
+template <int K, bool W, int M, bool TP>
+__global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_, GridScalars gs,
+                                                  const double* __restrict__ q, const double* __restrict__ Lam,
+                                                  double* __restrict__ Dl, TopoDev tp,
+                                                  const double* __restrict__ Lder) {
+  using C = Cfg<K, W, M>;
+  constexpr int NP = 4 * M + M * M, R = C::R, L = C::L, S = C::S, NR = C::NR, NA = C::NA;
+  const cdp tab = (cdp)tab_;
+  const int n = gs.n, P = gs.P;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 18 * n * n) return;
+  const int cells = 6 * n * n;
+  const int v = idx / cells, c = idx % cells;
+  const int p = c / (n * n), j = (c / n) % n, i = c % n;
+  const size_t vs = (size_t)6 * P * P;
+  const size_t coff = (size_t)p * P * P + (size_t)(j + R) * P + (i + R);
+  const double* c0 = q + v * vs + coff;
+  // the lane's stencil, staged in LDS (see k_vjp_traces); with topography
+  // the mass stencil is that of sqrtG phi_t
+  __shared__ double st[K * K][64];
+  __shared__ double sl[NP][64];
+  const int lane = threadIdx.x;
+  const bool topo_v = TP && v == 0;
+#pragma unroll
+  for (int o = 0; o < K * K; ++o) {
+    const int off = (o / K - R) * P + (o % K - R);
+    st[o][lane] = c0[off] + (topo_v ? tp.sbar[coff + off] : 0.0);
+  }
+  auto at = [&](int dy, int dx) -> double { return st[(dy + R) * K + dx + R][lane]; };
+  {
+    const double* lam = Lam + (size_t)v * cells + c;     // point pt at lam[pt * 3 * cells]
+#pragma unroll
+    for (int pt = 0; pt < NP; ++pt) sl[pt][lane] = lam[(size_t)pt * 3 * cells];
+  }
+  double dq[K * K];
+#pragma unroll
+  for (int o = 0; o < K * K; ++o) dq[o] = 0.0;
+  weno_cell_adj<K, W, M>(tab, gs.eps, at, [&](int pt) -> double { return sl[pt][lane]; },
+                         [&](int o) -> double& { return dq[o]; });
   if constexpr (TP) {
     if (v == 0) topo_derivative_adj<K, M>(tab, Lder, cells, c, [&](int o, double x) { dq[o] += x; });
   }
@@ -740,53 +761,61 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
 }
 
 // ---------------------------------------------------------------------------
-// k_vjp_tpp: TPP (linear) reconstruction adjoint, Dl as in k_vjp_weno.  A
-// point value is wy[py] (x) wx[px] applied to the stencil, so the cotangent of
-// stencil cell (row, col) is sum over points of lam_pt wc[py][row] wc[px][col];
-// per row: first the y-sums for each x axis point, then the x-sums.
+// Adjoint of the TPP (linear) reconstruction of one variable of one cell, one
+// stencil row at a time: a point value is wy[py] (x) wx[px] applied to the
+// stencil, so the cotangent of stencil cell (row, col) is the sum over points
+// of lam_pt wc[py][row] wc[px][col]: first the y-sums for each x axis point,
+// then the x-sums.  emit(col, x) for the K cells of the row.
+// ---------------------------------------------------------------------------
+template <int K, bool W, int M, typename LamF, typename Emit>
+__device__ __forceinline__ void tpp_row_adj(cdp tab, LamF L, int row, Emit emit) {
+  using C = Cfg<K, W, M>;
+  constexpr int NA = C::NA;
+  cdp wc = tab + C::O.wc;
+  double yr[NA];
+#pragma unroll
+  for (int px = 0; px < 2; ++px) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) s = fma(L(px * M + k), wc[(2 + k) * K + row], s);
+    yr[px] = s;
+  }
+#pragma unroll
+  for (int h = 0; h < M; ++h) {
+    double s = L(2 * M + h) * wc[0 * K + row];
+    s = fma(L(3 * M + h), wc[1 * K + row], s);
+#pragma unroll
+    for (int w = 0; w < M; ++w) s = fma(L(4 * M + w * M + h), wc[(2 + w) * K + row], s);
+    yr[2 + h] = s;
+  }
+#pragma unroll
+  for (int col = 0; col < K; ++col) {
+    double s = 0.0;
+#pragma unroll
+    for (int px = 0; px < NA; ++px) s = fma(yr[px], wc[px * K + col], s);
+    emit(col, s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_vjp_tpp: TPP (linear) reconstruction adjoint, Dl as in k_vjp_weno
 // ---------------------------------------------------------------------------
 template <int K, bool W, int M, bool TP>
 __global__ __launch_bounds__(64) void k_vjp_tpp(const double* __restrict__ tab_, GridScalars gs,
                                                  const double* __restrict__ Lam, double* __restrict__ Dl,
                                                  const double* __restrict__ Lder) {
-  using C = Cfg<K, W, M>;
-  constexpr int NA = C::NA;
   const cdp tab = (cdp)tab_;
   const int n = gs.n;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 18 * n * n) return;
   const int cells = 6 * n * n;
   const int v = idx / cells, c = idx % cells;
-  cdp wc = tab + C::O.wc;
   const double* lam = Lam + (size_t)v * cells + c;     // point pt at lam[pt * 3 * cells]
   auto L = [&](int pt) -> double { return lam[(size_t)pt * 3 * cells]; };
   double* out = Dl + (size_t)v * cells + c;
 #pragma unroll 1
-  for (int row = 0; row < K; ++row) {
-    double yr[NA];
-#pragma unroll
-    for (int px = 0; px < 2; ++px) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < M; ++k) s = fma(L(px * M + k), wc[(2 + k) * K + row], s);
-      yr[px] = s;
-    }
-#pragma unroll
-    for (int h = 0; h < M; ++h) {
-      double s = L(2 * M + h) * wc[0 * K + row];
-      s = fma(L(3 * M + h), wc[1 * K + row], s);
-#pragma unroll
-      for (int w = 0; w < M; ++w) s = fma(L(4 * M + w * M + h), wc[(2 + w) * K + row], s);
-      yr[2 + h] = s;
-    }
-#pragma unroll
-    for (int col = 0; col < K; ++col) {
-      double s = 0.0;
-#pragma unroll
-      for (int px = 0; px < NA; ++px) s = fma(yr[px], wc[px * K + col], s);
-      out[(size_t)(row * K + col) * 3 * cells] = s;
-    }
-  }
+  for (int row = 0; row < K; ++row)
+    tpp_row_adj<K, W, M>(tab, L, row, [&](int col, double x) { out[(size_t)(row * K + col) * 3 * cells] = x; });
   if constexpr (TP) {
     if (v == 0)
       topo_derivative_adj<K, M>(tab, Lder, (size_t)cells, c, [&](int o, double x) { out[(size_t)o * 3 * cells] += x; });
