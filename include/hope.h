@@ -129,8 +129,12 @@ typedef struct hope_layout {
   int32_t ghost_sweeps;     /* sweeps of the ghost-map build (ghost_iters if set) */
   int32_t tables_cached;    /* 1 if the host tables were read from cache_dir */
   int64_t tendency_workspace_bytes;  /* workspace of hope_tendency: the panel-edge
-                                        traces of one stage, 8 * 24 * n * n_gauss * 3
-                                        bytes rounded up to 256 */
+                                        traces of one stage (8 * 24 * n * n_gauss * 3
+                                        bytes rounded up to 256), then the segment
+                                        seams of the current launch shape (none for
+                                        segments of one row or one segment per panel;
+                                        otherwise 8 * 6 * n * (segments - 1) *
+                                        (6 n_gauss + 11) bytes rounded up to 256) */
 } hope_layout;
 
 /* Build a grid: equiangular metrics, reconstruction and WENO tables, the
@@ -181,8 +185,8 @@ int hope_check_state(const hope_grid* grid, const double* q, int64_t* n_bad, voi
  * with upwind term |m|(q_R - q_L), integrates fluxes (3.5) and the metric and
  * Coriolis sources (2.2)-(2.3) (3.6), and writes dqdt [3][6][n][n].
  * ws: caller-owned device scratch of at least layout.tendency_workspace_bytes
- * (the converted neighbour traces at the panel-edge points); its contents
- * are overwritten and need not be kept.  Returns HOPE_ERR_INVALID for a null
+ * (the converted neighbour traces at the panel-edge points and the segment
+ * seams); its contents are overwritten and need not be kept.  Returns HOPE_ERR_INVALID for a null
  * or misaligned buffer or a workspace that is too small. */
 int hope_tendency(const hope_grid* grid, double* q, double* dqdt, double* ws, size_t ws_bytes, void* stream);
 
@@ -201,8 +205,8 @@ int hope_tendency_vjp(const hope_grid* grid, double* q, const double* w, double*
 /* One three-stage Runge-Kutta step (section 3.5) in place on the padded
  * state q: HOPE_RK_SSP3 (Shu-Osher), or HOPE_RK_WS3 (3.39)-(3.41) with the
  * second stage from q^n.  ws: device workspace of at least
- * layout.rk_workspace_bytes (two padded stage states and the panel-edge
- * traces). */
+ * layout.rk_workspace_bytes (two padded stage states, then the workspace of
+ * hope_tendency). */
 int hope_rk_step(const hope_grid* grid, double* q, double dt, int32_t scheme, double* ws,
                  size_t ws_bytes, void* stream);
 
@@ -217,11 +221,11 @@ int hope_rk_step_vjp(const hope_grid* grid, double* q, double dt, int32_t scheme
 
 /* hope_rk_step without a workspace argument, for callers that cannot
  * allocate device memory: code under HIP graph capture, tight serving loops,
- * harnesses that forbid hipMalloc.  The two stage states and the panel-edge
- * traces live instead in a static device array of 64 MiB (HOPE_STATIC_SCRATCH_BYTES)
+ * harnesses that forbid hipMalloc.  The two stage states and the stage
+ * scratch (panel-edge traces, segment seams) live instead in a static device array of 128 MiB (HOPE_STATIC_SCRATCH_BYTES)
  * that each GPU the library runs on holds until the process ends; a grid
  * whose layout.rk_workspace_bytes exceeds it is refused with
- * HOPE_ERR_INVALID (C360 at order 5 needs 39 MB).  The call allocates
+ * HOPE_ERR_INVALID (C360 at order 5 needs 98 MB with its default launch shape).  The call allocates
  * nothing: the first call on a device only looks up the array's device
  * address (hipGetSymbolAddress).  Every call on one GPU shares that GPU's
  * array, which keeps the last call's contents (a step reads nothing it did
@@ -230,7 +234,7 @@ int hope_rk_step_vjp(const hope_grid* grid, double* q, double dt, int32_t scheme
  * call's kernels have finished) race and give wrong results; calls one
  * after another on one stream are fine.  The stream must belong to the
  * current device.  Results are bitwise those of hope_rk_step. */
-enum { HOPE_STATIC_SCRATCH_BYTES = 64 << 20 };
+enum { HOPE_STATIC_SCRATCH_BYTES = 128 << 20 };
 int hope_rk_step_static(const hope_grid* grid, double* q, double dt, int32_t scheme, void* stream);
 
 /* Message for the last error on this thread ("" if none). */
@@ -239,7 +243,11 @@ const char* hope_last_error(void);
 /* Launch shape of the fused stage kernel: each workgroup (three wavefronts,
  * one per variable) owns a strip of strip_w <= 62 interior columns of one
  * panel and marches over seg_h rows; strips of strip_w <= 30 columns run two
- * per workgroup, one in each half of its lanes.  Any values in range give
+ * per workgroup, one in each half of its lanes.  With seg_h >= 2 the flux
+ * through each boundary between two segments is formed by a second kernel
+ * from traces the segments store in the workspace (segment seams), so the
+ * workspace sizes of hope_grid_layout (tendency, rk, rk_vjp) depend on
+ * seg_h: read the layout again after changing it.  Any values in range give
  * bitwise identical results; they only change speed (the autotuner picks
  * them per grid).  Returns HOPE_ERR_INVALID out of range. */
 int hope_grid_set_launch(hope_grid* grid, int32_t strip_w, int32_t seg_h);

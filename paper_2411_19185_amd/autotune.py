@@ -87,13 +87,13 @@ def tune_grid(grid, q: torch.Tensor, reps: int = 5, cache: str | None = None, fo
         grid.set_launch(sw, sh)
         return sw, sh
     out = torch.empty(3, 6, grid.n, grid.n, dtype=torch.float64, device="cuda")
-    ws = grid.tendency_workspace()
     best = None
     for sw in strip_candidates(grid.n):
         for sh in SEG_CANDIDATES:
             if sh > grid.n:
                 continue
             grid.set_launch(sw, sh)
+            ws = grid.tendency_workspace()             # its size depends on the segment height
             grid.tendency(q, out, ws)                  # warm
             t = _time(lambda: grid.tendency(q, out, ws), reps)
             if best is None or t < best[0]:

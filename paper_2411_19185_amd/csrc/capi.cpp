@@ -1,6 +1,7 @@
 // C ABI of the HOPE right-hand side library (declared in include/hope.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -106,20 +107,22 @@ static void default_launch(hope_grid* G) {
   const int n = G->h.n;
   int sw, strips;
   balanced_strip(n, &sw, &strips);
-  // half strips (<= kHalfStrip columns, 32 lanes each) when they leave fewer
-  // lanes idle than full strips (64 lanes each)
+  // half strips (<= kHalfStrip columns, 32 lanes each) unless they leave
+  // more lanes idle than full strips (64 lanes each): twice the work items
   const int hs = (n + kHalfStrip - 1) / kHalfStrip, hw = (n + hs - 1) / hs;
-  if (sw > kHalfStrip && 32L * hs < 64L * strips) {
+  if (sw > kHalfStrip && 32L * hs <= 64L * strips) {
     sw = hw;
     strips = hs;
   }
   G->strip_w = sw;
-  // the tallest segments (fewest re-reconstructed boundary rows) that still
-  // give about 1.4 work items per workgroup slot of the chip (256 CUs x 4
-  // resident workgroups of the order-5 stage)
-  int h = 12;
-  while (h > 2 && stage_items(sw, strips, (n + h - 1) / h) < 1400) --h;
-  G->seg_h = h;
+  // short segments: with segment seams a boundary costs no reconstruction,
+  // so the segments are 3 rows high where that still leaves about 4 work
+  // items per workgroup slot of the chip (256 CUs x 4 resident workgroups of
+  // the order-5 stage), else 2 (measured at C360 WENO5: (30, 3) 0.242 ms,
+  // (30, 4) 0.244, (30, 2) 0.253, (60, 9) 0.30)
+  int h = 3;
+  while (h > 2 && stage_items(sw, strips, (n + h - 1) / h) < 4000) --h;
+  G->seg_h = std::min(h, n);
 }
 
 extern "C" {
@@ -392,14 +395,14 @@ int hope_grid_layout(const hope_grid* G, hope_layout* out) {
   out->n_gauss = h.m;
   out->state_elems = 18LL * h.P * h.P;
   out->interior_elems = 18LL * h.n * h.n;
-  out->tendency_workspace_bytes = (int64_t)trace_bytes(h);
+  out->tendency_workspace_bytes = (int64_t)stage_ws_bytes(h, G->seg_h);
   out->rk_workspace_bytes = 2 * out->state_elems * (int64_t)sizeof(double) + out->tendency_workspace_bytes;
   {
     size_t nT, nD, nG;
     out->vjp_workspace_bytes = (int64_t)(vjp_elems(G, &nT, &nD, &nG) * sizeof(double));
   }
-  out->rk_vjp_workspace_bytes =
-      (2 * out->state_elems + 2 * out->interior_elems) * (int64_t)sizeof(double) + out->vjp_workspace_bytes;
+  out->rk_vjp_workspace_bytes = (2 * out->state_elems + 2 * out->interior_elems) * (int64_t)sizeof(double) +
+                                std::max<int64_t>(out->vjp_workspace_bytes, out->tendency_workspace_bytes);
   out->ghost_cells = G->g.rows;
   out->ghost_nnz = G->g.nnz;
   out->device_bytes = (int64_t)G->device_bytes;
@@ -439,8 +442,9 @@ int hope_check_state(const hope_grid* G, const double* q, int64_t* n_bad, void* 
   return HOPE_OK;
 }
 
-// one stage: ghost fill, panel-edge traces into bt (the caller's scratch,
-// trace_elems doubles), fused stage kernel
+// one stage: ghost fill, panel-edge traces into bt (the caller's scratch of
+// stage_ws_bytes: the traces, then the segment seams), fused stage kernel
+// and, with seams, the seam kernel
 static int run_stage(const hope_grid* G, double* q, const double* qn, double* out, int out_padded, double ca,
                      double cb, double cc, double* bt, void* stream) {
   int e;
@@ -457,7 +461,7 @@ static int run_stage(const hope_grid* G, double* q, const double* qn, double* ou
   {
     Timed tm(G, 2, stream);
     e = launch_stage(G->h.k, G->h.weno, G->tab, G->itab, G->gs, q, qn, out, out_padded, ca, cb, cc, bt,
-                     G->strip_w, G->seg_h, G->topo, stream);
+                     G->strip_w, G->seg_h, G->topo, bt + trace_bytes(G->h) / sizeof(double), stream);
   }
   if (e) return hip_fail((hipError_t)e, "stage launch");
   return HOPE_OK;
@@ -468,7 +472,7 @@ int hope_tendency(const hope_grid* G, double* q, double* dqdt, double* ws, size_
   if (reinterpret_cast<uintptr_t>(q) % 8 || reinterpret_cast<uintptr_t>(dqdt) % 8 ||
       reinterpret_cast<uintptr_t>(ws) % 8)
     return fail(HOPE_ERR_INVALID, "misaligned buffer");
-  if (ws_bytes < trace_elems(G->h) * sizeof(double)) return fail(HOPE_ERR_INVALID, "workspace too small");
+  if (ws_bytes < stage_ws_bytes(G->h, G->seg_h)) return fail(HOPE_ERR_INVALID, "workspace too small");
   return run_stage(G, q, nullptr, dqdt, 0, 0.0, 0.0, 1.0, ws, stream);
 }
 
@@ -541,7 +545,10 @@ int hope_rk_step_vjp(const hope_grid* G, double* q, double dt, int32_t scheme, c
   const size_t state = 18ULL * G->h.P * G->h.P, field = 18ULL * G->h.n * G->h.n;
   size_t nT, nD, nG;
   const size_t nv = vjp_elems(G, &nT, &nD, &nG);
-  if (ws_bytes < (2 * state + 2 * field + nv) * sizeof(double)) return fail(HOPE_ERR_INVALID, "workspace too small");
+  // the region after the two stage states and fields holds the adjoint's
+  // scratch, and first the recomputed stages' traces and seams
+  const size_t nr = std::max(nv, stage_ws_bytes(G->h, G->seg_h) / sizeof(double));
+  if (ws_bytes < (2 * state + 2 * field + nr) * sizeof(double)) return fail(HOPE_ERR_INVALID, "workspace too small");
   if (reinterpret_cast<uintptr_t>(q) % 8 || reinterpret_cast<uintptr_t>(ws) % 8 ||
       reinterpret_cast<uintptr_t>(gout) % 8 || reinterpret_cast<uintptr_t>(gin) % 8)
     return fail(HOPE_ERR_INVALID, "misaligned buffer");
@@ -584,14 +591,14 @@ int hope_rk_step(const hope_grid* G, double* q, double dt, int32_t scheme, doubl
 }  // extern "C"
 
 size_t hope::rk_workspace_bytes(const hope_grid* G) {
-  return 2 * 18ULL * G->h.P * G->h.P * sizeof(double) + trace_bytes(G->h);
+  return 2 * 18ULL * G->h.P * G->h.P * sizeof(double) + stage_ws_bytes(G->h, G->seg_h);
 }
 
 int hope::rk_step_ws(const hope_grid* G, double* q, double dt, int scheme, double* ws, size_t ws_bytes,
                      void* stream) {
   if (scheme != HOPE_RK_SSP3 && scheme != HOPE_RK_WS3) return fail(HOPE_ERR_INVALID, "bad RK scheme");
   const size_t state = 18ULL * G->h.P * G->h.P;
-  if (ws_bytes < 2 * state * sizeof(double) + trace_elems(G->h) * sizeof(double))
+  if (ws_bytes < 2 * state * sizeof(double) + stage_ws_bytes(G->h, G->seg_h))
     return fail(HOPE_ERR_INVALID, "workspace too small");
   if (reinterpret_cast<uintptr_t>(q) % 8 || reinterpret_cast<uintptr_t>(ws) % 8)
     return fail(HOPE_ERR_INVALID, "misaligned buffer");

@@ -57,4 +57,9 @@ size_t rk_workspace_bytes(const hope_grid* G);
 inline size_t trace_elems(const HostTables& h) { return 24 * (size_t)h.n * h.m * 3; }
 // bytes of that scratch, rounded up to 256
 inline size_t trace_bytes(const HostTables& h) { return (trace_elems(h) * sizeof(double) + 255) / 256 * 256; }
+// bytes of one stage's scratch for segments of seg_h rows: the panel-edge
+// traces, then (from byte trace_bytes) the segment seams, rounded up to 256
+inline size_t stage_ws_bytes(const HostTables& h, int seg_h) {
+  return trace_bytes(h) + (seam_elems(h.n, h.m, seg_h) * sizeof(double) + 255) / 256 * 256;
+}
 }  // namespace hope

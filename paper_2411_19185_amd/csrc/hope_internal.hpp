@@ -197,6 +197,33 @@ inline int stage_items(int strip_w, int n_strips, int n_segs) {
   return (strip_w <= kHalfStrip ? (cols + 1) / 2 : cols) * n_segs;
 }
 
+// Segment seams.  Without them a segment reconstructs the top traces of the
+// row below it and the bottom traces of the row above it, rows that the
+// neighbouring segments reconstruct in full anyway.  With them (segments of
+// at least 2 rows), the flux through each internal segment boundary e is
+// left to the seam kernel: the segment below stores the top traces of row
+// e-1 and that row's partial tendency (all but its top flux); the segment
+// above stores the bottom traces of row e, the parts of row e's tendency
+// other than its bottom flux (x-flux difference, sources) and its top flux.
+// The seam kernel forms the boundary flux from the two traces with the same
+// arithmetic and finishes both rows: results are bitwise those of the
+// reconstructing path.  Record of panel p, boundary u (row e = u seg_h,
+// 1 <= u < n_segs), column i: field f at seam[f NS + (p (n_segs-1) + u-1) n + i],
+// NS = 6 (n_segs-1) n (neighbouring columns at neighbouring addresses).
+struct SeamLayout {
+  static constexpr int fields(int M) { return 6 * M + 11; }
+  static constexpr int tt(int M, int h, int v) { return h * 3 + v; }            // top traces of row e-1
+  static constexpr int tb(int M, int h, int v) { return 3 * M + h * 3 + v; }    // bottom traces of row e
+  static constexpr int lo_acc(int M, int v) { return 6 * M + v; }               // row e-1 without its top flux
+  static constexpr int hi_x(int M, int v) { return 6 * M + 3 + v; }             // row e: left minus right x flux
+  static constexpr int hi_src(int M, int k) { return 6 * M + 6 + k; }           // row e: momentum sources
+  static constexpr int hi_gt(int M, int v) { return 6 * M + 8 + v; }            // row e: its top flux
+};
+constexpr bool has_seams(int n, int seg_h) { return seg_h >= 2 && (n + seg_h - 1) / seg_h >= 2; }
+constexpr size_t seam_elems(int n, int M, int seg_h) {
+  return has_seams(n, seg_h) ? (size_t)SeamLayout::fields(M) * 6 * ((n + seg_h - 1) / seg_h - 1) * n : 0;
+}
+
 // Launchers implemented in kernels.hip.  All enqueue on `stream` and return a
 // hipError_t value (0 on success).
 // lanes: lanes per ghost row, halo_lanes(order)
@@ -210,6 +237,6 @@ int launch_edge_traces(int k, int weno, const double* tab, const int32_t* itab, 
                        const double* q, double* bt, const TopoDev& topo, void* stream);
 int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs,
                  const double* q, const double* qn, double* out, int out_padded, double ca, double cb, double cc,
-                 const double* bt, int strip_w, int seg_h, const TopoDev& topo, void* stream);
+                 const double* bt, int strip_w, int seg_h, const TopoDev& topo, double* seam, void* stream);
 
 }  // namespace hope

@@ -168,7 +168,9 @@ struct StageArgs {
   int strip_w, seg_h, n_strips, n_segs;
   int half;                 // strips of <= kHalfStrip columns: two per workgroup, 32 lanes each
   TopoDev tp;               // bottom topography tables (used by the TP kernels only)
+  double* seam = nullptr;   // segment seams (SeamLayout), or null: segments re-reconstruct their neighbours' rows
 };
+
 
 
 // The fused stage runs three wavefronts per work item: in the reconstruction
@@ -224,7 +226,7 @@ struct StageSmem : TopoSmem<TP> {
 // layer's own sqrtG phi, and forms psi_B of the row from the derivative of
 // the centred order-k polynomial of sqrtG phi_t at the cell nodes; the LMARS
 // pressure adds phi_s.
-template <int K, bool W, int M, bool TP = false>
+template <int K, bool W, int M, bool TP = false, bool SEAMS = false>
 __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp fcb, const GridScalars& gs,
                                            const StageArgs& A, int item, StageSmem<K, W, M, TP>& sm) {
   using C = Cfg<K, W, M>;
@@ -373,6 +375,19 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     b2 = fma(g2, c2, b2);
   };
 
+  // segment seams below row j0 (sb) and above row j1-1 (sa); SEAMS compiles
+  // them in (the batched kernel runs without)
+  const bool sb = SEAMS && A.seam && j0 > 0, sa = SEAMS && A.seam && j1 < n;
+  // (32-bit offsets: a seam buffer holds at most 6 n^2 (6m + 11) / 2 elements)
+  const int seam_ns = A.seam ? 6 * (A.n_segs - 1) * n : 0;
+  auto seam_at = [&](int u, int f) -> double& { return A.seam[f * seam_ns + (p * (A.n_segs - 1) + (u - 1)) * n + i]; };
+  // the traces a seam takes, stored as the row's reconstruction forms them:
+  // the bottom traces of row j0 (seam below), the top traces of row j1-1
+  // (seam above)
+  auto seam_traces = [&](int pc, int h, double bot, double topv) {
+    if (sb && pc == j0 && owner) seam_at(seg, SeamLayout::tb(M, h, wv)) = bot;
+    if (sa && pc == j1 - 1 && owner) seam_at(seg + 1, SeamLayout::tt(M, h, wv)) = topv;
+  };
   // ---- reconstruction phase: wavefront wv, variable wv ----------------------
   // every point of row pc
   auto recon_row = [&](int pc, double* top) {
@@ -400,8 +415,11 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
         asm volatile("" ::: "memory");
         xpass<K, W, M>(tab, 2 + h, win(pc), xr);
         wcol<K, W, M>(tab, 2 + h, xr, kf, col);
-        pt(wv, SM::PB + h) = layer(wpoint<K, W, M>(tab, 2 + h, 0, 2 * M + h, col), [&] { return s_ye(pc, h); });
-        top[h] = layer(wpoint<K, W, M>(tab, 2 + h, 1, 3 * M + h, col), [&] { return s_ye(pc + 1, h); });
+        const double vb = layer(wpoint<K, W, M>(tab, 2 + h, 0, 2 * M + h, col), [&] { return s_ye(pc, h); });
+        const double vt = layer(wpoint<K, W, M>(tab, 2 + h, 1, 3 * M + h, col), [&] { return s_ye(pc + 1, h); });
+        pt(wv, SM::PB + h) = vb;
+        top[h] = vt;
+        seam_traces(pc, h, vb, vt);
         if constexpr (TP) {
           double xc[NR], xd[NR];
           if (wv == 0) tpass(pc, 2 + h, xc, xd);
@@ -431,8 +449,11 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       for (int h = 0; h < M; ++h) {
         asm volatile("" ::: "memory");
         xpass<K, W, M>(tab, 2 + h, win(pc), xr);
-        pt(wv, SM::PB + h) = layer(point<K, W, M>(tab, 0, 2 * M + h, xr, kf), [&] { return s_ye(pc, h); });
-        top[h] = layer(point<K, W, M>(tab, 1, 3 * M + h, xr, kf), [&] { return s_ye(pc + 1, h); });
+        const double vb = layer(point<K, W, M>(tab, 0, 2 * M + h, xr, kf), [&] { return s_ye(pc, h); });
+        const double vt = layer(point<K, W, M>(tab, 1, 3 * M + h, xr, kf), [&] { return s_ye(pc + 1, h); });
+        pt(wv, SM::PB + h) = vb;
+        top[h] = vt;
+        seam_traces(pc, h, vb, vt);
         if constexpr (TP) {
           double xd[NR];
           if (wv == 0) dpass(pc, 2 + h, xd);
@@ -585,8 +606,11 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       for (int h = h0; h < h1; ++h) {
         asm volatile("" ::: "memory");
         xpass<K, W, M>(tab, 2 + h, win(pc), xr);
-        pt(wv, SM::PB + h) = layer(point<K, W, M>(tab, 0, 2 * M + h, xr, kf), [&] { return s_ye(pc, h); });
-        top[h] = layer(point<K, W, M>(tab, 1, 3 * M + h, xr, kf), [&] { return s_ye(pc + 1, h); });
+        const double vb = layer(point<K, W, M>(tab, 0, 2 * M + h, xr, kf), [&] { return s_ye(pc, h); });
+        const double vt = layer(point<K, W, M>(tab, 1, 3 * M + h, xr, kf), [&] { return s_ye(pc + 1, h); });
+        pt(wv, SM::PB + h) = vb;
+        top[h] = vt;
+        seam_traces(pc, h, vb, vt);
         if constexpr (TP) {
           double xd[NR];
           if (wv == 0) dpass(pc, 2 + h, xd);
@@ -646,7 +670,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
 
   // ---- prologue: window and the top traces of row j0-1 ------------------
   double nxt[PER];
-  for (int pr = max(0, j0 - 1); pr < j0 + 2 * R; ++pr) {
+  for (int pr = sb ? j0 : max(0, j0 - 1); pr < j0 + 2 * R; ++pr) {
     fetch(pr, nxt);
     store(pr, nxt);
   }
@@ -656,7 +680,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
 #pragma unroll
     for (int h = 0; h < M; ++h)
       sm.ptop[wv][h][lane] = real ? btp[(((size_t)2 * n + ic) * M + h) * 3 + wv] : (wv ? 0.0 : 1.0);
-  } else {
+  } else if (!sb) {
     recon_side(j0 - 1, 1, [&](int h) -> double& { return sm.ptop[wv][h][lane]; });
   }
   double acc = 0.0;                // this wavefront's variable: partial tendency of the previous row
@@ -666,14 +690,14 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     const bool last = (j == j1);
     // the window of step j holds padded rows j .. j+2R; row j+2R was fetched
     // during the previous step and replaces row j-1, no longer read
-    const bool have = !(last && j1 == n) && (j + 2 * R) < P;
+    const bool have = !(last && (j1 == n || sa)) && (j + 2 * R) < P;
     // the slot of row j+2R held padded row j-1, last read by the previous
     // step's reconstruction (behind its flux barriers) or, in the first step,
     // by the prologue's top traces
     if (j == j0) __syncthreads();
     if (have) store(j + 2 * R, nxt);
     __syncthreads();
-    const bool want = (j + 1 < j1 || (j + 1 == j1 && j1 < n)) && (j + 2 * R + 1) < P;
+    const bool want = (j + 1 < j1 || (j + 1 == j1 && j1 < n && !sa)) && (j + 2 * R + 1) < P;
     if (want) fetch(j + 2 * R + 1, nxt);
     double s1c = 0.0, s2c = 0.0;     // chunked mode: this row's sources (wavefront 2)
     if (!last) {
@@ -683,7 +707,7 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
       // bottom traces of the panel's top row: the neighbour's converted trace
 #pragma unroll
       for (int h = 0; h < M; ++h) pt(wv, SM::PB + h) = real ? btp[(((size_t)3 * n + ic) * M + h) * 3 + wv] : 0.0;
-    } else {
+    } else if (!sa) {
       recon_side(j, 0, [&](int h) -> double& { return pt(wv, SM::PB + h); });
     }
     __syncthreads();
@@ -692,13 +716,16 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     // read before the next step's store may replace that row
     const bool fin = j > j0 && owner;
     const int jr = j - 1;
+    const bool ex_lo = last && sa;                  // row j1-1 goes to the seam above
+    const bool ex_gt = sb && j == j0 + 1;           // row j0's top flux goes to the seam below
+    const bool wr = fin && !ex_lo && !ex_gt;        // the row is finished here
     const size_t o_in = wv * vs + p * plane + (size_t)(jr + R) * P + (i + R);
-    const double qn_c = (fin && A.qn) ? A.qn[o_in] : 0.0;
+    const double qn_c = (wr && A.qn) ? A.qn[o_in] : 0.0;
     // (with topography the window's mass is sqrtG phi_t: q_s is read again)
     double qs_c = 0.0;
-    if constexpr (TP) qs_c = fin ? (wv == 0 ? A.q[o_in] : sm.sq[wv][(jr + R) % NR][wc]) : 0.0;
-    else qs_c = fin ? sm.sq[wv][(jr + R) % NR][wc] : 0.0;
-    if (wv == 1) yflux(j);
+    if constexpr (TP) qs_c = wr ? (wv == 0 ? A.q[o_in] : sm.sq[wv][(jr + R) % NR][wc]) : 0.0;
+    else qs_c = wr ? sm.sq[wv][(jr + R) % NR][wc] : 0.0;
+    if (wv == 1 && !(last && sa) && !(j == j0 && sb)) yflux(j);
     if (!last) {
       if (wv == 0) xflux(j);
       if (wv == 2) {
@@ -717,7 +744,11 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     __syncthreads();
     // ---- assembly: wavefront wv, variable wv -----------------------------
     const double gb = fy(wv);
-    if (fin) {
+    if (fin && ex_lo) {
+      // row j1-1 goes to the seam above after the loop
+    } else if (fin && ex_gt) {
+      seam_at(seg, SeamLayout::hi_gt(M, wv)) = gb;
+    } else if (fin) {
       // finish row j-1: its top flux is row j's bottom flux
       const double dq = fma(-gb, invd, acc);
       double val = A.cc * dq;
@@ -732,9 +763,82 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     if (last) break;
     const double fl = fx(wv, lane);
     const double fr = fx(wv, min(lane + 1, 63));
-    acc = wv == 0 ? (fl - fr + gb) * invd : fma(fl - fr + gb, invd, src(wv - 1));
+    if (j == j0 && sb) {
+      // row j0: the parts of its tendency other than the bottom flux
+      if (owner) {
+        seam_at(seg, SeamLayout::hi_x(M, wv)) = fl - fr;
+        if (wv > 0) seam_at(seg, SeamLayout::hi_src(M, wv - 1)) = src(wv - 1);
+      }
+      acc = 0.0;
+    } else {
+      acc = wv == 0 ? (fl - fr + gb) * invd : fma(fl - fr + gb, invd, src(wv - 1));
+    }
 #pragma unroll
     for (int h = 0; h < M; ++h) sm.ptop[wv][h][lane] = top[h];
+  }
+  // row j1-1's partial tendency (all but its top flux) for the seam above
+  if (owner && sa) seam_at(seg + 1, SeamLayout::lo_acc(M, wv)) = acc;
+}
+
+// One segment seam: the flux through the boundary e = u seg_h of panel p at
+// column i (as the stage's y flux forms it), then the tendency (or Runge-Kutta
+// combination) of rows e-1 and e, all three variables.  idx runs over
+// 6 (n_segs-1) n records.
+template <int K, bool W, int M, bool TP = false>
+__device__ __forceinline__ void stage_seam(const double* __restrict__ tab_, const GridScalars& gs,
+                                           const StageArgs& A, size_t idx) {
+  using C = Cfg<K, W, M>;
+  constexpr int R = C::R;
+  cdp tab = (cdp)tab_;
+  const int n = gs.n, P = gs.P;
+  const TabOffsets O = tab_offsets(K, W, M, n);
+  const size_t ns = (size_t)6 * (A.n_segs - 1) * n;
+  const int i = (int)(idx % n);
+  const int u = (int)((idx / n) % (A.n_segs - 1)) + 1;
+  const int p = (int)(idx / ((size_t)(A.n_segs - 1) * n));
+  const int e = u * A.seg_h;
+  const double* rec = A.seam + idx;
+  auto fld = [&](int f) -> double { return rec[(size_t)f * ns]; };
+  const double invd = gs.inv_delta;
+  const double ia = 1.0 / gs.radius;
+  cdp Xg = tab + O.Xg, sqg = tab + O.sqg, Xe = tab + O.Xe, sqe = tab + O.sqe, gw = tab + C::O.gw;
+  double gb[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+  for (int h = 0; h < M; ++h) {
+    double qL[3], qR[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      qL[v] = fld(SeamLayout::tt(M, h, v));
+      qR[v] = fld(SeamLayout::tb(M, h, v));
+    }
+    double F[3];
+    const double sps = TP ? A.tp.sy[(((size_t)p * (n + 1) + e) * n + i) * M + h] : 0.0;
+    lmars<TP>(qL, qR, Xg[i * M + h], Xe[e], sqg[i * M + h], sqe[e], 1, ia, F, sps);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) gb[v] = fma(gw[h], F[v], gb[v]);
+  }
+  const size_t plane = (size_t)P * P, vs = 6 * plane;
+  auto finish = [&](int v, int jr, double dq) {
+    const size_t o_in = v * vs + p * plane + (size_t)(jr + R) * P + (i + R);
+    double val = A.cc * dq;
+    if (A.cb != 0.0) {
+      // q_s as the stage reads it from its window (with topography the window
+      // adds 0 to the momentum)
+      double qs = A.q[o_in];
+      if constexpr (TP) qs = v == 0 ? qs : qs + 0.0;
+      val = fma(A.cb, qs, val);
+    }
+    if (A.qn) val = fma(A.ca, A.qn[o_in], val);
+    if (A.out_padded) A.out[o_in] = val;
+    else A.out[((size_t)(v * 6 + p) * n + jr) * n + i] = val;
+  };
+#pragma unroll
+  for (int v = 0; v < 3; ++v) finish(v, e - 1, fma(-gb[v], invd, fld(SeamLayout::lo_acc(M, v))));
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const double x = fld(SeamLayout::hi_x(M, v));
+    const double acc = v == 0 ? (x + gb[0]) * invd : fma(x + gb[v], invd, fld(SeamLayout::hi_src(M, v - 1)));
+    finish(v, e, fma(-fld(SeamLayout::hi_gt(M, v)), invd, acc));
   }
 }
 

@@ -8,6 +8,8 @@
 //  k_stage         fused reconstruction, LMARS, quadrature, sources, tendency
 //                  and Runge-Kutta combination; one marching work item per
 //                  workgroup (a strip, or two strips of <= 30 columns)
+//  k_stage_seams   the flux through each internal segment boundary and the
+//                  two rows beside it (segments of >= 2 rows)
 //  k_combine       out = a x + b y + c z (the Runge-Kutta adjoint)
 //  k_check_state   count of interior cells with a thickness that is not positive
 //                  or a variable that is not finite
@@ -48,12 +50,21 @@ __global__ __launch_bounds__(64) void k_edge_traces(const double* __restrict__ t
 // ---------------------------------------------------------------------------
 // Fused stage kernel: one work item per workgroup
 // ---------------------------------------------------------------------------
+// (three wavefronts per SIMD at orders <= 5, the occupancy the workgroup's LDS allows)
 template <int K, bool W, int M, bool TP>
-__global__ __launch_bounds__(kStageThreads) void k_stage(const double* __restrict__ tab_, GridScalars gs,
-                                                                StageArgs A) {
+__global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu(K <= 5 ? 3 : 1))) void k_stage(
+    const double* __restrict__ tab_, GridScalars gs, StageArgs A) {
   using C = Cfg<K, W, M>;
   __shared__ StageSmem<K, W, M, TP> sm;
-  stage_tile<K, W, M, TP>(tab_, (cdp)tab_ + C::O.fcoef, gs, A, blockIdx.x, sm);
+  stage_tile<K, W, M, TP, true>(tab_, (cdp)tab_ + C::O.fcoef, gs, A, blockIdx.x, sm);
+}
+
+template <int K, bool W, int M, bool TP>
+__global__ __launch_bounds__(256) void k_stage_seams(const double* __restrict__ tab_, GridScalars gs, StageArgs A,
+                                                     size_t records) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= records) return;
+  stage_seam<K, W, M, TP>(tab_, gs, A, idx);
 }
 
 // ---------------------------------------------------------------------------
@@ -142,6 +153,14 @@ static int stage_t(const double* tab, const GridScalars& gs, const StageArgs& a,
   else
     hipLaunchKernelGGL((k_stage<K, W, M, false>), dim3(items), dim3(kStageThreads), 0, (hipStream_t)stream, tab, gs,
                        a);
+  if (a.seam) {
+    const size_t records = (size_t)6 * (a.n_segs - 1) * gs.n;
+    const dim3 grid((unsigned)((records + 255) / 256));
+    if (a.tp.sbar)
+      hipLaunchKernelGGL((k_stage_seams<K, W, M, true>), grid, dim3(256), 0, (hipStream_t)stream, tab, gs, a, records);
+    else
+      hipLaunchKernelGGL((k_stage_seams<K, W, M, false>), grid, dim3(256), 0, (hipStream_t)stream, tab, gs, a, records);
+  }
   return (int)hipGetLastError();
 }
 
@@ -172,7 +191,7 @@ int launch_edge_traces(int k, int weno, const double* tab, const int32_t* itab, 
 
 int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs, const double* q,
                  const double* qn, double* out, int out_padded, double ca, double cb, double cc, const double* bt,
-                 int strip_w, int seg_h, const TopoDev& topo, void* stream) {
+                 int strip_w, int seg_h, const TopoDev& topo, double* seam, void* stream) {
   (void)itab;
   StageArgs a;
   a.tp = topo;
@@ -189,6 +208,8 @@ int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const 
   a.n_strips = (gs.n + strip_w - 1) / strip_w;
   a.n_segs = (gs.n + seg_h - 1) / seg_h;
   a.half = strip_w <= kHalfStrip;
+  // seams only where the scratch is sized for them (segments of >= 2 rows, >= 2 segments)
+  a.seam = has_seams(gs.n, seg_h) ? seam : nullptr;
   HOPE_DISPATCH(stage_t, tab, gs, a, stream);
 }
 

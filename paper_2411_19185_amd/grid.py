@@ -169,7 +169,12 @@ class Grid:
         return out
 
     def set_launch(self, strip_w: int, seg_h: int):
+        """The stage kernel's launch shape; the workspace sizes depend on
+        seg_h (segment seams), so the layout is read again."""
         check(lib().hope_grid_set_launch(self._h, int(strip_w), int(seg_h)))
+        lay = Layout()
+        check(lib().hope_grid_layout(self._h, ctypes.byref(lay)))
+        self.layout = lay
 
     def get_launch(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()

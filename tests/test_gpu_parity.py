@@ -115,7 +115,7 @@ def test_launch_shape_does_not_change_results_high_orders(order):
     print(f"case n={n} TPP{order} launch shapes", flush=True)
     alpha, q = STATES["perturbed_member"](n, 70 + order)
     g = _gpu_grid(n, order, "tpp", alpha)
-    assert g.get_launch()[0] > 30            # the default is one full strip of 40 columns
+    g.set_launch(40, 4)                      # one full strip of 40 columns
     base = g.tendency(to_padded(q, g.r))
     for sw, sh in [(40, 40), (33, 5), (20, 3), (13, 1), (62, 7)]:
         g.set_launch(sw, sh)
@@ -124,21 +124,49 @@ def test_launch_shape_does_not_change_results_high_orders(order):
         assert torch.equal(base, other), (sw, sh)
 
 
-@pytest.mark.parametrize("n,order,launches", [(45, 11, [None]), (45, 13, [None]), (90, 11, [None, (45, 4)])])
+@pytest.mark.parametrize("n,order,scheme,topo", [(40, 5, "weno", False), (33, 11, "tpp", False),
+                                                  (24, 5, "weno", True)])
+def test_segment_seams_give_the_reconstructing_paths_rk_steps(n, order, scheme, topo):
+    """Segment seams (segments of >= 2 rows: the flux through each boundary
+    between two segments formed by the seam kernel from stored traces) against
+    one-row segments and one segment per panel (every row reconstructed by its
+    own work item): two SSP-RK3 and one WS-RK3 step, whose stages write the
+    padded state with the q_s and q^n terms, bitwise equal; with topography
+    too."""
+    import hope_inputs as hi
+    from paper_2411_19185_amd import Grid
+    print(f"case n={n} order={order} {scheme} topo={topo}: seams vs reconstructed boundaries", flush=True)
+    alpha, q = STATES["perturbed_member"](n, 95 + order)
+    dt = cfl_dt(q)
+    g = Grid(n, order, scheme, axis_tilt=alpha, surface=hi.ConeMountain() if topo else None)
+    outs = []
+    for sw, sh in [(n if n <= 62 else 30, 1), (30, n), (30, 2), (17, 3), (62, 5)]:
+        g.set_launch(sw, sh)
+        qp = to_padded(q, g.r)
+        ws = g.workspace()
+        g.rk_step(qp, dt, "ssp3", ws)
+        g.rk_step(qp, dt, "ssp3", ws)
+        g.rk_step(qp, dt, "ws3", ws)
+        torch.cuda.synchronize()
+        outs.append(((sw, sh), g.interior(qp).clone()))
+    for launch, out in outs[1:]:
+        assert torch.equal(outs[0][1], out), launch
+
+
+@pytest.mark.parametrize("n,order,launches", [(45, 11, [(45, 4), None]), (45, 13, [(45, 3), None]),
+                                              (90, 11, [None, (45, 4)])])
 def test_high_order_full_strips_match_oracle(n, order, launches):
-    """TPP11 and TPP13 on the grids where the stage runs full strips of more
-    than 30 columns (C45 by default; C90 TPP11, the timing grid of the
-    differentiation configuration, with its default half strips and with a
-    full-strip shape the autotuner may choose), element by element against
-    the oracle."""
+    """TPP11 and TPP13 with full strips of more than 30 columns (C45 with one
+    45-column strip per panel, and with its default half strips; C90 TPP11,
+    the timing grid of the differentiation configuration, with its default
+    half strips and with a full-strip shape the autotuner may choose),
+    element by element against the oracle."""
     print(f"case C{n} TPP{order} launches={launches}", flush=True)
     alpha, q = STATES["perturbed_balanced"](n, 80 + order, nq=2)
     og = oracle_grid(n, order, "tpp", alpha)
     ref = og.tendency(q)
     print("oracle done", flush=True)
     g = _gpu_grid(n, order, "tpp", alpha)
-    if n == 45:
-        assert g.get_launch()[0] == 45
     for launch in launches:
         if launch:
             g.set_launch(*launch)
