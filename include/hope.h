@@ -287,6 +287,8 @@ int hope_inspect_ghost_map(const hope_grid_desc* desc, int64_t* rows, int64_t* n
  * members, so a whole Runge-Kutta step is 9 launches whatever the member
  * count, and no call below except create / set_launch / destroy allocates or
  * synchronises: the stage and step calls can be captured in a HIP graph.
+ * (The batched stage reconstructs the rows beside its segment boundaries
+ * itself; it has no segment seams.)
  * Each member's result is bitwise the one hope_rk_step / hope_tendency give
  * on its own grid (with its own axis tilt).
  *
