@@ -73,7 +73,10 @@ def _time(fn, reps: int) -> float:
 
 
 def _device_key() -> str:
-    return torch.cuda.get_device_name(0).replace("|", "/")
+    # the architecture name (the marketing name can read empty under a profiler)
+    props = torch.cuda.get_device_properties(0)
+    name = getattr(props, "gcnArchName", "") or torch.cuda.get_device_name(0) or "gpu"
+    return name.split(":")[0].replace("|", "/")
 
 
 def tune_grid(grid, q: torch.Tensor, reps: int = 5, cache: str | None = None, force: bool = False):

@@ -107,21 +107,31 @@ static void default_launch(hope_grid* G) {
   const int n = G->h.n;
   int sw, strips;
   balanced_strip(n, &sw, &strips);
-  // half strips (<= kHalfStrip columns, 32 lanes each) unless they leave
-  // more lanes idle than full strips (64 lanes each): twice the work items
+  const bool seams = uses_seams(G->h);
+  // half strips (<= kHalfStrip columns, 32 lanes each) when they leave fewer
+  // lanes idle than full strips (64 lanes each), and with segment seams also
+  // when they leave as many (twice the work items)
   const int hs = (n + kHalfStrip - 1) / kHalfStrip, hw = (n + hs - 1) / hs;
-  if (sw > kHalfStrip && 32L * hs <= 64L * strips) {
+  if (sw > kHalfStrip && (32L * hs < 64L * strips || (seams && 32L * hs == 64L * strips))) {
     sw = hw;
     strips = hs;
   }
   G->strip_w = sw;
-  // short segments: with segment seams a boundary costs no reconstruction,
-  // so the segments are 3 rows high where that still leaves about 4 work
-  // items per workgroup slot of the chip (256 CUs x 4 resident workgroups of
-  // the order-5 stage), else 2 (measured at C360 WENO5: (30, 3) 0.242 ms,
-  // (30, 4) 0.244, (30, 2) 0.253, (60, 9) 0.30)
-  int h = 3;
-  while (h > 2 && stage_items(sw, strips, (n + h - 1) / h) < 4000) --h;
+  int h;
+  if (seams) {
+    // short segments: with segment seams a boundary costs no reconstruction,
+    // so the segments are 3 rows high where that still leaves about 4 work
+    // items per workgroup slot of the chip (256 CUs x 4 resident workgroups
+    // of the order-5 stage), else 2 (measured at C360 WENO5: (30, 3)
+    // 0.242 ms, (30, 4) 0.244, (30, 2) 0.253, (60, 9) 0.30)
+    h = 3;
+    while (h > 2 && stage_items(sw, strips, (n + h - 1) / h) < 4000) --h;
+  } else {
+    // the tallest segments (fewest re-reconstructed boundary rows) that still
+    // give about 1.4 work items per workgroup slot
+    h = 12;
+    while (h > 2 && stage_items(sw, strips, (n + h - 1) / h) < 1400) --h;
+  }
   G->seg_h = std::min(h, n);
 }
 
@@ -460,8 +470,9 @@ static int run_stage(const hope_grid* G, double* q, const double* qn, double* ou
   if (e) return hip_fail((hipError_t)e, "edge_traces launch");
   {
     Timed tm(G, 2, stream);
+    double* seam = uses_seams(G->h) ? bt + trace_bytes(G->h) / sizeof(double) : nullptr;
     e = launch_stage(G->h.k, G->h.weno, G->tab, G->itab, G->gs, q, qn, out, out_padded, ca, cb, cc, bt,
-                     G->strip_w, G->seg_h, G->topo, bt + trace_bytes(G->h) / sizeof(double), stream);
+                     G->strip_w, G->seg_h, G->topo, seam, stream);
   }
   if (e) return hip_fail((hipError_t)e, "stage launch");
   return HOPE_OK;

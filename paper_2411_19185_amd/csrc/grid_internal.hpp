@@ -57,9 +57,17 @@ size_t rk_workspace_bytes(const hope_grid* G);
 inline size_t trace_elems(const HostTables& h) { return 24 * (size_t)h.n * h.m * 3; }
 // bytes of that scratch, rounded up to 256
 inline size_t trace_bytes(const HostTables& h) { return (trace_elems(h) * sizeof(double) + 255) / 256 * 256; }
+// whether the grid's stage uses segment seams: where a row's reconstruction
+// is costly (WENO5, TPP9 and up).  At the cheaper orders the seam kernel and
+// its stores cost more than the boundary rows they save (measured at C90:
+// TPP3 0.072 -> 0.090, TPP5 0.108 -> 0.136, TPP7 0.186 -> 0.202 ms per RK
+// step with seams; WENO5 C360 0.280 -> 0.242 and TPP11 C90 0.114 -> 0.082 ms
+// per stage).
+inline bool uses_seams(const HostTables& h) { return (h.weno && h.k == 5) || h.k >= 9; }
 // bytes of one stage's scratch for segments of seg_h rows: the panel-edge
 // traces, then (from byte trace_bytes) the segment seams, rounded up to 256
 inline size_t stage_ws_bytes(const HostTables& h, int seg_h) {
-  return trace_bytes(h) + (seam_elems(h.n, h.m, seg_h) * sizeof(double) + 255) / 256 * 256;
+  const size_t seams = uses_seams(h) ? seam_elems(h.n, h.m, seg_h) : 0;
+  return trace_bytes(h) + (seams * sizeof(double) + 255) / 256 * 256;
 }
 }  // namespace hope

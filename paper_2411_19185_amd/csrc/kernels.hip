@@ -50,13 +50,18 @@ __global__ __launch_bounds__(64) void k_edge_traces(const double* __restrict__ t
 // ---------------------------------------------------------------------------
 // Fused stage kernel: one work item per workgroup
 // ---------------------------------------------------------------------------
-// (three wavefronts per SIMD at orders <= 5, the occupancy the workgroup's LDS allows)
+// segment seams at WENO5 and TPP9 and up (uses_seams); WENO5 is held to
+// three wavefronts per SIMD, the occupancy its workgroup's LDS allows (the
+// seam stores would otherwise raise its allocation past it)
+template <int K, bool W, int M>
+constexpr bool kSeams = (W && K == 5) || K >= 9;
+
 template <int K, bool W, int M, bool TP>
-__global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu(K <= 5 ? 3 : 1))) void k_stage(
+__global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu((W && K == 5) ? 3 : 1))) void k_stage(
     const double* __restrict__ tab_, GridScalars gs, StageArgs A) {
   using C = Cfg<K, W, M>;
   __shared__ StageSmem<K, W, M, TP> sm;
-  stage_tile<K, W, M, TP, true>(tab_, (cdp)tab_ + C::O.fcoef, gs, A, blockIdx.x, sm);
+  stage_tile<K, W, M, TP, kSeams<K, W, M>>(tab_, (cdp)tab_ + C::O.fcoef, gs, A, blockIdx.x, sm);
 }
 
 template <int K, bool W, int M, bool TP>
@@ -145,7 +150,9 @@ static int edge_traces_t(const double* tab, const int32_t* itab, const GridScala
 }
 
 template <int K, bool W, int M>
-static int stage_t(const double* tab, const GridScalars& gs, const StageArgs& a, void* stream) {
+static int stage_t(const double* tab, const GridScalars& gs, const StageArgs& a_in, void* stream) {
+  StageArgs a = a_in;
+  if constexpr (!kSeams<K, W, M>) a.seam = nullptr;   // the kernel is compiled without them
   const int items = stage_items(a.strip_w, a.n_strips, a.n_segs);
   if (a.tp.sbar)
     hipLaunchKernelGGL((k_stage<K, W, M, true>), dim3(items), dim3(kStageThreads), 0, (hipStream_t)stream, tab, gs,
@@ -153,13 +160,17 @@ static int stage_t(const double* tab, const GridScalars& gs, const StageArgs& a,
   else
     hipLaunchKernelGGL((k_stage<K, W, M, false>), dim3(items), dim3(kStageThreads), 0, (hipStream_t)stream, tab, gs,
                        a);
-  if (a.seam) {
-    const size_t records = (size_t)6 * (a.n_segs - 1) * gs.n;
-    const dim3 grid((unsigned)((records + 255) / 256));
-    if (a.tp.sbar)
-      hipLaunchKernelGGL((k_stage_seams<K, W, M, true>), grid, dim3(256), 0, (hipStream_t)stream, tab, gs, a, records);
-    else
-      hipLaunchKernelGGL((k_stage_seams<K, W, M, false>), grid, dim3(256), 0, (hipStream_t)stream, tab, gs, a, records);
+  if constexpr (kSeams<K, W, M>) {
+    if (a.seam) {
+      const size_t records = (size_t)6 * (a.n_segs - 1) * gs.n;
+      const dim3 grid((unsigned)((records + 255) / 256));
+      if (a.tp.sbar)
+        hipLaunchKernelGGL((k_stage_seams<K, W, M, true>), grid, dim3(256), 0, (hipStream_t)stream, tab, gs, a,
+                           records);
+      else
+        hipLaunchKernelGGL((k_stage_seams<K, W, M, false>), grid, dim3(256), 0, (hipStream_t)stream, tab, gs, a,
+                           records);
+    }
   }
   return (int)hipGetLastError();
 }
@@ -208,7 +219,8 @@ int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const 
   a.n_strips = (gs.n + strip_w - 1) / strip_w;
   a.n_segs = (gs.n + seg_h - 1) / seg_h;
   a.half = strip_w <= kHalfStrip;
-  // seams only where the scratch is sized for them (segments of >= 2 rows, >= 2 segments)
+  // seams only where the scratch is sized for them (segments of >= 2 rows,
+  // >= 2 segments) and the kernel is compiled with them
   a.seam = has_seams(gs.n, seg_h) ? seam : nullptr;
   HOPE_DISPATCH(stage_t, tab, gs, a, stream);
 }

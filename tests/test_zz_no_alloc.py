@@ -41,9 +41,9 @@ def test_static_rk_step_matches_workspace_step():
 def test_static_rk_step_refuses_a_grid_too_large():
     from paper_2411_19185_amd import Grid
     from paper_2411_19185_amd._lib import lib
-    n = 480
-    print(f"case n={n} order=3 tpp, two-row segments: workspace beyond the static scratch", flush=True)
-    g = Grid(n, 3, "tpp")
+    n = 400
+    print(f"case n={n} WENO5, two-row segments: workspace beyond the static scratch", flush=True)
+    g = Grid(n, 5, "weno")
     g.set_launch(30, 2)                       # the segment seams' scratch grows as segments shrink
     assert g.layout.rk_workspace_bytes > 128 << 20
     q = g.new_state()
