@@ -575,7 +575,7 @@ def adjoint(g, n, args, dt):
     for k in ("vjp_traces", "vjp_points", "vjp_edges", "vjp_weno", "vjp_gather", "vjp_ghost_t"):
         ms, cnt = g.profile_read(k)
         if cnt:
-            kern[k] = ms / cnt
+            kern[k] = ms / reps          # per adjoint call (the WENO adjoint and gather run once per variable)
     fill_ms, fill_cnt = g.profile_read("fill_halo")
     kern["fill_halo"] = fill_ms / max(fill_cnt, 1)
     vjp_ms = sum(v for k, v in kern.items() if k.startswith("vjp_")) + kern["fill_halo"]

@@ -15,7 +15,8 @@ struct VjpArgs {
   double* gq;
   double* T;       // point values of every cell, [NP][3][6n^2]
   double* Lam;     // their cotangents, same layout
-  double* Dl;      // WENO: stencil cotangents, [K^2][3][6n^2]
+  double* Dl;      // stencil cotangents: one variable [K^2][6n^2] (over T, no longer read by then),
+                   // or all three [K^2][3][6n^2]
   double* gpad;    // padded cotangent, 3 x 6 x P x P
   // G^T by the interior cells that some ghost row reads (gt_rows of them)
   int32_t gt_rows;
@@ -29,8 +30,16 @@ struct VjpArgs {
   TopoDev topo;            // bottom topography (null sbar: none)
   double* Lder;            // topography: cotangents of d(sqrtG phi_t)/dxi, /deta at the cell nodes,
                            // [2][m*m][6n^2]
+  int var = -1;            // the variable of a kVjpWeno / kVjpGather launch (-1: all three)
 };
-// the adjoint's kernels in launch order
+// whether the adjoint takes the stencil cotangents one variable at a time
+// (over the point values' space: 37 % less workspace at C360 WENO5 for
+// about 2 % more time); small grids take all three in one launch, which
+// measured 15 % faster at TPP11 C90 (launches a third the size underfill the
+// chip there)
+inline bool vjp_per_variable(int n) { return n >= 160; }
+// the adjoint's kernels in launch order (kVjpWeno and kVjpGather once per
+// variable, in turn)
 enum { kVjpTraces = 0, kVjpPoints, kVjpEdges, kVjpWeno, kVjpGather, kVjpGhostT, kVjpSteps };
 int launch_vjp(int k, int weno, const VjpArgs& a, int step, void* stream);
 
