@@ -197,9 +197,9 @@ int hope_tendency(const hope_grid* grid, double* q, double* dqdt, double* ws, si
  * ws: caller-owned device workspace of at least layout.vjp_workspace_bytes
  * (8 * 2*3*(4m+m^2) bytes per cell for the point values and their
  * cotangents, plus 8 * 3 * order^2 for the stencil cotangents on grids of
- * n < 160 (from n = 160 those of one variable at a time take the point
- * values' space), plus one padded state, and 8 * 2 m^2 bytes per cell more
- * with topography); gq must not alias w.  With
+ * n < 160 (from n = 160 those of as many variables at a time as fit take the
+ * point values' space), plus one padded state, and 8 * 2 m^2 bytes per cell
+ * more with topography); gq must not alias w.  With
  * topography the adjoint runs through sqrtG phi_t, the pressure with phi_s
  * and psi_B (2.14), phi_s being a constant of the grid. */
 int hope_tendency_vjp(const hope_grid* grid, double* q, const double* w, double* gq, double* ws,

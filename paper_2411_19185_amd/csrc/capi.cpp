@@ -384,15 +384,15 @@ void hope_grid_destroy(hope_grid* grid) {
 
 // adjoint scratch: point values T, their cotangents, the stencil cotangents
 // (nD), padded cotangent, and with topography the cotangents of the mass
-// derivatives at the cell nodes.  On large grids the stencil cotangents of one
-// variable at a time (nD = K^2 cells <= nT) reuse T's space: the point values
-// are not read after the flux adjoints.
+// derivatives at the cell nodes.  On large grids the stencil cotangents of a
+// group of variables at a time (vjp_group: at most nT) reuse T's space: the
+// point values are not read after the flux adjoints.
 static size_t vjp_elems(const hope_grid* G, size_t* nT, size_t* nD, size_t* nG) {
   const HostTables& h = G->h;
   const size_t cells = 6ULL * h.n * h.n;
   const size_t np = 4 * h.m + h.m * h.m;
   *nT = cells * np * 3;
-  *nD = vjp_per_variable(h.n) ? 0 : cells * h.k * h.k * 3;
+  *nD = vjp_grouped(h.n) ? 0 : cells * h.k * h.k * 3;
   *nG = 18ULL * h.P * h.P;
   const size_t nL = G->topo.sbar ? 2 * cells * h.m * h.m : 0;
   return 2 * *nT + *nD + *nG + nL;
@@ -514,7 +514,7 @@ int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq
   a.gq = gq;
   a.T = ws;
   a.Lam = ws + nT;
-  a.Dl = vjp_per_variable(h.n) ? ws : ws + 2 * nT;   // over T, or after T and its cotangents
+  a.Dl = vjp_grouped(h.n) ? ws : ws + 2 * nT;   // over T, or after T and its cotangents
   a.gpad = ws + 2 * nT + nD;
   a.gt_rows = G->gt_rows;
   a.gt_cell = G->gt_cell;
@@ -531,11 +531,12 @@ int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq
   };
   for (int step : {kVjpTraces, kVjpPoints, kVjpEdges})
     if ((e = run(step))) return hip_fail((hipError_t)e, "adjoint launch");
-  // the stencil cotangents and the padded cotangent, each variable in turn
-  // on large grids, all three at once on small ones
-  const bool per_var = vjp_per_variable(h.n);
-  for (int v = per_var ? 0 : -1; v < (per_var ? 3 : 0); ++v) {
-    a.var = v;
+  // the stencil cotangents and the padded cotangent, a group of variables at
+  // a time on large grids, all three at once on small ones
+  const int group = vjp_grouped(h.n) ? vjp_group(h.k, h.m) : 3;
+  for (int v0 = 0; v0 < 3; v0 += group) {
+    a.v0 = v0;
+    a.nv = std::min(group, 3 - v0);
     if ((e = run(kVjpWeno))) return hip_fail((hipError_t)e, "adjoint launch");
     if ((e = run(kVjpGather))) return hip_fail((hipError_t)e, "adjoint launch");
   }

@@ -17,9 +17,9 @@
 //                   nonlinear weights, tau, beta and the sub-stencil values
 //   k_vjp_tpp       TPP: the same for the linear reconstruction (separable)
 //   k_vjp_gather    cotangent of every padded cell (interior and ghost)
-//                   (on large grids these run once per variable, each
-//                   variable's stencil cotangents in the space of the point
-//                   values, no longer read; on small ones once for all three)
+//                   (on large grids these run on groups of variables whose
+//                   stencil cotangents fit in the space of the point values,
+//                   no longer read; on small ones once for all three)
 //   k_vjp_interior  the interior cotangent
 //   k_vjp_ghost_t   plus G^T times the ghost cotangents
 // Every kernel gathers (each output is written by one thread): no atomics.
@@ -720,17 +720,17 @@ template <int K, bool W, int M, bool TP>
 __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_, GridScalars gs,
                                                   const double* __restrict__ q, const double* __restrict__ Lam,
                                                   double* __restrict__ Dl, TopoDev tp,
-                                                  const double* __restrict__ Lder, int var) {
+                                                  const double* __restrict__ Lder, int v0, int nv) {
   using C = Cfg<K, W, M>;
   constexpr int NP = 4 * M + M * M, R = C::R;
   const cdp tab = (cdp)tab_;
   const int n = gs.n, P = gs.P;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int cells = 6 * n * n;
-  if (idx >= (var < 0 ? 3 : 1) * cells) return;
-  const int v = var < 0 ? idx / cells : var, c = var < 0 ? idx % cells : idx;
-  // stencil cotangents: [K^2][cells] for one variable, [K^2][3][cells] for all
-  const size_t dl_stride = var < 0 ? (size_t)3 * cells : (size_t)cells;
+  if (idx >= nv * cells) return;
+  // variables v0 .. v0+nv-1; stencil cotangents [K^2][nv][cells]
+  const int v = v0 + idx / cells, c = idx % cells;
+  const size_t dl_stride = (size_t)nv * cells;
   const int p = c / (n * n), j = (c / n) % n, i = c % n;
   const size_t vs = (size_t)6 * P * P;
   const size_t coff = (size_t)p * P * P + (size_t)(j + R) * P + (i + R);
@@ -760,7 +760,7 @@ __global__ __launch_bounds__(64) void k_vjp_weno(const double* __restrict__ tab_
   if constexpr (TP) {
     if (v == 0) topo_derivative_adj<K, M>(tab, Lder, cells, c, [&](int o, double x) { dq[o] += x; });
   }
-  double* out = Dl + (var < 0 ? (size_t)v * cells : 0) + c;
+  double* out = Dl + (size_t)(v - v0) * cells + c;
 #pragma unroll
   for (int o = 0; o < K * K; ++o) out[(size_t)o * dl_stride] = dq[o];
 }
@@ -808,17 +808,17 @@ __device__ __forceinline__ void tpp_row_adj(cdp tab, LamF L, int row, Emit emit)
 template <int K, bool W, int M, bool TP>
 __global__ __launch_bounds__(64) void k_vjp_tpp(const double* __restrict__ tab_, GridScalars gs,
                                                  const double* __restrict__ Lam, double* __restrict__ Dl,
-                                                 const double* __restrict__ Lder, int var) {
+                                                 const double* __restrict__ Lder, int v0, int nv) {
   const cdp tab = (cdp)tab_;
   const int n = gs.n;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int cells = 6 * n * n;
-  if (idx >= (var < 0 ? 3 : 1) * cells) return;
-  const int v = var < 0 ? idx / cells : var, c = var < 0 ? idx % cells : idx;
-  const size_t dl_stride = var < 0 ? (size_t)3 * cells : (size_t)cells;
+  if (idx >= nv * cells) return;
+  const int v = v0 + idx / cells, c = idx % cells;
+  const size_t dl_stride = (size_t)nv * cells;
   const double* lam = Lam + (size_t)v * cells + c;     // point pt at lam[pt * 3 * cells]
   auto L = [&](int pt) -> double { return lam[(size_t)pt * 3 * cells]; };
-  double* out = Dl + (var < 0 ? (size_t)v * cells : 0) + c;
+  double* out = Dl + (size_t)(v - v0) * cells + c;
 #pragma unroll 1
   for (int row = 0; row < K; ++row)
     tpp_row_adj<K, W, M>(tab, L, row, [&](int col, double x) { out[(size_t)(row * K + col) * dl_stride] = x; });
@@ -835,7 +835,7 @@ __global__ __launch_bounds__(64) void k_vjp_tpp(const double* __restrict__ tab_,
 template <int K, bool W, int M>
 __global__ __launch_bounds__(256) void k_vjp_gather(const double* __restrict__ tab_, GridScalars gs,
                                                      const double* __restrict__ Lam, const double* __restrict__ Dl,
-                                                     double* __restrict__ gpad, int var) {
+                                                     double* __restrict__ gpad, int v0, int nv) {
   using C = Cfg<K, W, M>;
   constexpr int R = C::R;
   (void)tab_;
@@ -843,9 +843,9 @@ __global__ __launch_bounds__(256) void k_vjp_gather(const double* __restrict__ t
   const int n = gs.n, P = gs.P;
   const size_t plane = (size_t)6 * P * P;              // one variable's padded plane
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (var < 0 ? 3 : 1) * plane) return;
-  const int v = var < 0 ? (int)(idx / plane) : var;
-  const size_t pi = var < 0 ? idx % plane : idx;
+  if (idx >= (size_t)nv * plane) return;
+  const int v = v0 + (int)(idx / plane);
+  const size_t pi = idx % plane;
   const int ii = pi % P, jj = (pi / P) % P, p = (int)(pi / ((size_t)P * P));
   const size_t cells = (size_t)6 * n * n;
   double acc = 0.0;
@@ -857,7 +857,7 @@ __global__ __launch_bounds__(256) void k_vjp_gather(const double* __restrict__ t
       if (i < 0 || i >= n) continue;
       const int c = (p * n + j) * n + i;
       const int o = (dy + R) * K + (dx + R);
-      acc += var < 0 ? Dl[((size_t)o * 3 + v) * cells + c] : Dl[(size_t)o * cells + c];
+      acc += Dl[((size_t)o * nv + (v - v0)) * cells + c];
     }
   }
   gpad[(size_t)v * plane + pi] = acc;
@@ -962,16 +962,16 @@ static int vjp_t(const VjpArgs& a, int step, void* stream) {
     }
     case kVjpWeno:
       if constexpr (W)
-        hipLaunchKernelGGL((k_vjp_weno<K, W, M, TP>), dim3(((a.var < 0 ? 3 : 1) * cells + 63) / 64), dim3(64), 0, s,
-                           a.tab, gs, a.q, a.Lam, a.Dl, a.topo, a.Lder, a.var);
+        hipLaunchKernelGGL((k_vjp_weno<K, W, M, TP>), dim3((a.nv * cells + 63) / 64), dim3(64), 0, s, a.tab, gs, a.q,
+                           a.Lam, a.Dl, a.topo, a.Lder, a.v0, a.nv);
       else
-        hipLaunchKernelGGL((k_vjp_tpp<K, W, M, TP>), dim3(((a.var < 0 ? 3 : 1) * cells + 63) / 64), dim3(64), 0, s,
-                           a.tab, gs, a.Lam, a.Dl, a.Lder, a.var);
+        hipLaunchKernelGGL((k_vjp_tpp<K, W, M, TP>), dim3((a.nv * cells + 63) / 64), dim3(64), 0, s, a.tab, gs,
+                           a.Lam, a.Dl, a.Lder, a.v0, a.nv);
       break;
     case kVjpGather: {
-      const size_t padded = (size_t)(a.var < 0 ? 3 : 1) * 6 * P * P;
+      const size_t padded = (size_t)a.nv * 6 * P * P;
       hipLaunchKernelGGL((k_vjp_gather<K, W, M>), dim3((unsigned)((padded + 255) / 256)), dim3(256), 0, s, a.tab, gs,
-                         a.Lam, a.Dl, a.gpad, a.var);
+                         a.Lam, a.Dl, a.gpad, a.v0, a.nv);
       break;
     }
     case kVjpGhostT:

@@ -15,8 +15,8 @@ struct VjpArgs {
   double* gq;
   double* T;       // point values of every cell, [NP][3][6n^2]
   double* Lam;     // their cotangents, same layout
-  double* Dl;      // stencil cotangents: one variable [K^2][6n^2] (over T, no longer read by then),
-                   // or all three [K^2][3][6n^2]
+  double* Dl;      // stencil cotangents of variables v0 .. v0+nv-1, [K^2][nv][6n^2] (on large grids
+                   // over T, no longer read by then)
   double* gpad;    // padded cotangent, 3 x 6 x P x P
   // G^T by the interior cells that some ghost row reads (gt_rows of them)
   int32_t gt_rows;
@@ -30,14 +30,19 @@ struct VjpArgs {
   TopoDev topo;            // bottom topography (null sbar: none)
   double* Lder;            // topography: cotangents of d(sqrtG phi_t)/dxi, /deta at the cell nodes,
                            // [2][m*m][6n^2]
-  int var = -1;            // the variable of a kVjpWeno / kVjpGather launch (-1: all three)
+  int v0 = 0, nv = 3;      // the variables of a kVjpWeno / kVjpGather launch
 };
-// whether the adjoint takes the stencil cotangents one variable at a time
-// (over the point values' space: 37 % less workspace at C360 WENO5 for
-// about 2 % more time); small grids take all three in one launch, which
-// measured 15 % faster at TPP11 C90 (launches a third the size underfill the
-// chip there)
-inline bool vjp_per_variable(int n) { return n >= 160; }
+// whether the adjoint takes the stencil cotangents in groups of variables
+// that fit in the point values' space (37 % less workspace at C360 WENO5);
+// small grids take all three in one launch (third-size launches underfill
+// the chip there: TPP11 C90 adjoint 0.435 -> 0.493 ms one by one)
+inline bool vjp_grouped(int n) { return n >= 160; }
+// variables per group: as many as have their stencil cotangents (k^2 per
+// cell each) in the point values' space (3 (4m + m^2) per cell)
+inline int vjp_group(int k, int m) {
+  const int np3 = 3 * (4 * m + m * m);
+  return 3 * k * k <= np3 ? 3 : (2 * k * k <= np3 ? 2 : 1);
+}
 // the adjoint's kernels in launch order (kVjpWeno and kVjpGather once per
 // variable, in turn)
 enum { kVjpTraces = 0, kVjpPoints, kVjpEdges, kVjpWeno, kVjpGather, kVjpGhostT, kVjpSteps };
