@@ -381,12 +381,17 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
   // (32-bit offsets: a seam buffer holds at most 6 n^2 (6m + 11) / 2 elements)
   const int seam_ns = A.seam ? 6 * (A.n_segs - 1) * n : 0;
   auto seam_at = [&](int u, int f) -> double& { return A.seam[f * seam_ns + (p * (A.n_segs - 1) + (u - 1)) * n + i]; };
-  // the traces a seam takes, stored as the row's reconstruction forms them:
-  // the bottom traces of row j0 (seam below), the top traces of row j1-1
-  // (seam above)
+  // the traces a seam takes: the bottom traces of row j0 (seam below) and the
+  // top traces of row j1-1 (seam above).  TPP stores them as the row's
+  // reconstruction forms them; WENO, whose unrolled reconstruction holds more
+  // registers, from LDS afterwards (the bottom traces from the point slots at
+  // the end of step j0, the top traces from ptop after the loop), which
+  // measured faster for WENO and slower for TPP
   auto seam_traces = [&](int pc, int h, double bot, double topv) {
-    if (sb && pc == j0 && owner) seam_at(seg, SeamLayout::tb(M, h, wv)) = bot;
-    if (sa && pc == j1 - 1 && owner) seam_at(seg + 1, SeamLayout::tt(M, h, wv)) = topv;
+    if constexpr (!W) {
+      if (sb && pc == j0 && owner) seam_at(seg, SeamLayout::tb(M, h, wv)) = bot;
+      if (sa && pc == j1 - 1 && owner) seam_at(seg + 1, SeamLayout::tt(M, h, wv)) = topv;
+    }
   };
   // ---- reconstruction phase: wavefront wv, variable wv ----------------------
   // every point of row pc
@@ -764,8 +769,14 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
     const double fl = fx(wv, lane);
     const double fr = fx(wv, min(lane + 1, 63));
     if (j == j0 && sb) {
-      // row j0: the parts of its tendency other than the bottom flux
+      // row j0: (WENO) its bottom traces, still in the point slots since the y
+      // flux of this step was not formed, and the parts of its tendency other
+      // than the bottom flux
       if (owner) {
+        if constexpr (W) {
+#pragma unroll
+          for (int h = 0; h < M; ++h) seam_at(seg, SeamLayout::tb(M, h, wv)) = pt(wv, SM::PB + h);
+        }
         seam_at(seg, SeamLayout::hi_x(M, wv)) = fl - fr;
         if (wv > 0) seam_at(seg, SeamLayout::hi_src(M, wv - 1)) = src(wv - 1);
       }
@@ -776,8 +787,16 @@ __device__ __forceinline__ void stage_tile(const double* __restrict__ tab_, cdp 
 #pragma unroll
     for (int h = 0; h < M; ++h) sm.ptop[wv][h][lane] = top[h];
   }
-  // row j1-1's partial tendency (all but its top flux) for the seam above
-  if (owner && sa) seam_at(seg + 1, SeamLayout::lo_acc(M, wv)) = acc;
+  // row j1-1's partial tendency (all but its top flux) and (WENO) its top
+  // traces, moved to ptop at the end of its step and left there by the last
+  // step, for the seam above
+  if (owner && sa) {
+    seam_at(seg + 1, SeamLayout::lo_acc(M, wv)) = acc;
+    if constexpr (W) {
+#pragma unroll
+      for (int h = 0; h < M; ++h) seam_at(seg + 1, SeamLayout::tt(M, h, wv)) = sm.ptop[wv][h][lane];
+    }
+  }
 }
 
 // One segment seam: the flux through the boundary e = u seg_h of panel p at
