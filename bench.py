@@ -490,8 +490,9 @@ def ensemble(args):
                            "loss": "0.5 ||q_T||^2 per member; each member's checkpointed rollout and step "
                                    "adjoints on its own derived grid, members spread over "
                                    f"{args.vjp_streams} HIP streams"},
-            "launches_per_step": 9,
-            "note": "batched: one captured graph per step (9 kernel launches over all members); looped: "
+            "launches_per_step": 12,
+            "note": "batched: one captured graph per step (12 kernel launches over all members: ghost fill, "
+                    "panel-edge traces, fused stage and segment seams per stage); looped: "
                     "hope_rk_step per member on its resolution's grid (timing only)"}
 
 

@@ -286,12 +286,13 @@ int hope_inspect_ghost_map(const hope_grid_desc* desc, int64_t* rows, int64_t* n
 /* ------------------------------------------------------------------------
  * Batched ensemble.  Members of one order and scheme, on grids of any
  * resolutions (members may share a grid), advanced together: each kernel of
- * a stage (ghost fill, panel-edge traces, fused stage) is one launch over all
- * members, so a whole Runge-Kutta step is 9 launches whatever the member
- * count, and no call below except create / set_launch / destroy allocates or
- * synchronises: the stage and step calls can be captured in a HIP graph.
- * (The batched stage reconstructs the rows beside its segment boundaries
- * itself; it has no segment seams.)
+ * a stage (ghost fill, panel-edge traces, fused stage, and at WENO5 and TPP9
+ * and up the segment seams) is one launch over all members, so a whole
+ * Runge-Kutta step is 9 or 12 launches whatever the member count, and no call
+ * below except create / set_launch / destroy allocates or synchronises: the
+ * stage and step calls can be captured in a HIP graph.  The batch owns its
+ * scratch (panel-edge traces and segment seams, the latter sized by the launch
+ * shapes), so calls on one batch must not overlap on different streams.
  * Each member's result is bitwise the one hope_rk_step / hope_tendency give
  * on its own grid (with its own axis tilt).
  *
@@ -324,7 +325,8 @@ int hope_batch_layout(const hope_batch* batch, hope_batch_info* out, int64_t* st
 /* Work-item shape per member (strip width 1..62, segment height 1..n; NULL
  * keeps the current values) and the fused-stage grid size (0: one workgroup
  * per item; otherwise that many workgroups stride the item list).  Waits for
- * the device, then rebuilds and uploads the item list: allocates and
+ * the device, then rebuilds and uploads the item list and grows the segment
+ * seam scratch to the new shapes (it never shrinks): allocates and
  * synchronises.  Any values give bitwise identical results.  Refused with
  * HOPE_ERR_INVALID once a stage of the batch has been recorded under stream
  * capture, since the graph refers to the item list. */

@@ -6,13 +6,14 @@
 //  k_fill_halo_batch      ghost fill g = G q (appendix (7.12)) of all members:
 //                         one lane group per ghost row of a grid, applied to
 //                         that grid's members while the row's entries sit in
-//                         registers (G is read once per kHaloChunk = 16 members)
+//                         registers (G is read once per kHaloChunk members)
 //  k_edge_traces_batch    panel-edge traces (3.26)-(3.29) of all members; each
 //                         member's range is padded to 64 sides (whole
 //                         wavefronts of lane groups)
 //  k_stage_batch          the fused stage over a flattened list of work items
 //                         (member, panel, strip, segment); with blocks < items
 //                         it is persistent, each workgroup striding the list
+//  k_stage_seams_batch    the segment seams of all members (WENO5, TPP9+)
 #include <hip/hip_runtime.h>
 
 #include "batch_internal.hpp"
@@ -104,34 +105,63 @@ __global__ __launch_bounds__(64) void k_edge_traces_batch(const BatchMember* __r
   edge_trace<K, W, M>((cdp)bm.tab, (cip)bm.itab, bm.gs, in + bm.q_off, bt + bm.bt_off, local, t % kEdgeLanes);
 }
 
+// the stage arguments of member mi in one launch
+__device__ __forceinline__ StageArgs member_args(const BatchMember& bm, const BatchStage& S, int mi) {
+  StageArgs A;
+  A.q = S.in + bm.q_off;
+  A.qn = S.qn ? S.qn + bm.q_off : nullptr;
+  A.out = S.out + (S.out_padded ? bm.q_off : bm.f_off);
+  A.bt = S.bt + bm.bt_off;
+  A.ca = S.ca;
+  A.cb = S.cb;
+  A.cc = S.dt ? S.cs * S.dt[mi] : S.cs;
+  A.out_padded = S.out_padded;
+  A.strip_w = bm.strip_w;
+  A.seg_h = bm.seg_h;
+  A.n_strips = bm.n_strips;
+  A.n_segs = bm.n_segs;
+  A.half = bm.half;
+  A.seam = (S.seam && bm.seam_off >= 0) ? S.seam + bm.seam_off : nullptr;
+  return A;
+}
+
 // orders <= 5 fit 4 workgroups (3 wavefronts per SIMD) by LDS; the register
-// allocation is held to that occupancy
-template <int K, bool W, int M>
-__global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu(K <= 5 ? 3 : 1))) void k_stage_batch(const BatchMember* __restrict__ mem,
-                                                                      const int32_t* __restrict__ items,
-                                                                      int n_items, BatchStage S) {
+// allocation is held to that occupancy.  PERSIST: each workgroup strides the
+// item list (fewer workgroups than items); else one item per workgroup, which
+// keeps no loop state live across the stage body (no scratch at WENO5)
+template <int K, bool W, int M, bool PERSIST>
+__global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu(K <= 5 ? 3 : 1))) void k_stage_batch(
+    const BatchMember* __restrict__ mem, const int32_t* __restrict__ items, int n_items, BatchStage S) {
   __shared__ StageSmem<K, W, M> sm;
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  auto run = [&](int it) {
     const int code = __builtin_amdgcn_readfirstlane(items[it]);
     const int mi = code >> 20, local = code & 0xFFFFF;
     const BatchMember& bm = mem[mi];
-    StageArgs A;
-    A.q = S.in + bm.q_off;
-    A.qn = S.qn ? S.qn + bm.q_off : nullptr;
-    A.out = S.out + (S.out_padded ? bm.q_off : bm.f_off);
-    A.bt = S.bt + bm.bt_off;
-    A.ca = S.ca;
-    A.cb = S.cb;
-    A.cc = S.dt ? S.cs * S.dt[mi] : S.cs;
-    A.out_padded = S.out_padded;
-    A.strip_w = bm.strip_w;
-    A.seg_h = bm.seg_h;
-    A.n_strips = bm.n_strips;
-    A.n_segs = bm.n_segs;
-    A.half = bm.half;
-    if (it != (int)blockIdx.x) __syncthreads();   // the previous item's LDS reads are done
-    stage_tile<K, W, M>(bm.tab, (cdp)bm.fcoef, bm.gs, A, local, sm);
+    const StageArgs A = member_args(bm, S, mi);
+    stage_tile<K, W, M, false, kSeams<K, W, M>>(bm.tab, (cdp)bm.fcoef, bm.gs, A, local, sm);
+  };
+  if constexpr (PERSIST) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+      if (it != (int)blockIdx.x) __syncthreads();   // the previous item's LDS reads are done
+      run(it);
+    }
+  } else {
+    run(blockIdx.x);   // the grid has exactly n_items workgroups
   }
+}
+
+// the segment seams of every member that has them: block b holds records
+// (b - seam_block) 256 + thread of member seam_member[b]
+template <int K, bool W, int M>
+__global__ __launch_bounds__(kSeamBlock) void k_stage_seams_batch(const BatchMember* __restrict__ mem,
+                                                                  const int32_t* __restrict__ seam_member,
+                                                                  BatchStage S) {
+  const int mi = __builtin_amdgcn_readfirstlane(seam_member[blockIdx.x]);
+  const BatchMember& bm = mem[mi];
+  const size_t idx = (size_t)(blockIdx.x - bm.seam_block) * kSeamBlock + threadIdx.x;
+  if (idx >= (size_t)6 * (bm.n_segs - 1) * bm.gs.n) return;
+  const StageArgs A = member_args(bm, S, mi);
+  stage_seam<K, W, M>(bm.tab, bm.gs, A, idx);
 }
 
 // ---------------------------------------------------------------------------
@@ -163,10 +193,18 @@ static int batch_edges_t(const BatchMember* members, const int32_t* edge_member,
 
 template <int K, bool W, int M>
 static int batch_stage_t(const BatchMember* members, const int32_t* items, int n_items, int blocks,
-                         const BatchStage& st, void* stream) {
-  const int grid = (blocks > 0 && blocks < n_items) ? blocks : n_items;
-  hipLaunchKernelGGL((k_stage_batch<K, W, M>), dim3(grid), dim3(kStageThreads), 0, (hipStream_t)stream, members, items,
-                     n_items, st);
+                         const int32_t* seam_member, int seam_blocks, const BatchStage& st, void* stream) {
+  if (blocks > 0 && blocks < n_items)
+    hipLaunchKernelGGL((k_stage_batch<K, W, M, true>), dim3(blocks), dim3(kStageThreads), 0, (hipStream_t)stream,
+                       members, items, n_items, st);
+  else
+    hipLaunchKernelGGL((k_stage_batch<K, W, M, false>), dim3(n_items), dim3(kStageThreads), 0, (hipStream_t)stream,
+                       members, items, n_items, st);
+  if constexpr (kSeams<K, W, M>) {
+    if (seam_blocks > 0 && st.seam)
+      hipLaunchKernelGGL((k_stage_seams_batch<K, W, M>), dim3(seam_blocks), dim3(kSeamBlock), 0,
+                         (hipStream_t)stream, members, seam_member, st);
+  }
   return (int)hipGetLastError();
 }
 
@@ -197,9 +235,9 @@ int launch_batch_edge_traces(int k, int weno, const BatchMember* members, const 
 }
 
 int launch_batch_stage(int k, int weno, const BatchMember* members, const int32_t* items, int n_items, int blocks,
-                       const BatchStage& st, void* stream) {
+                       const int32_t* seam_member, int seam_blocks, const BatchStage& st, void* stream) {
   if (n_items == 0) return 0;
-  HOPE_BATCH_DISPATCH(batch_stage_t, members, items, n_items, blocks, st, stream);
+  HOPE_BATCH_DISPATCH(batch_stage_t, members, items, n_items, blocks, seam_member, seam_blocks, st, stream);
 }
 
 }  // namespace hope

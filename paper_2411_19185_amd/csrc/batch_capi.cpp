@@ -28,6 +28,13 @@ struct hope_batch {
   int32_t* items = nullptr;
   double* fcoef = nullptr;
   double* bt = nullptr;
+  // segment seams (orders that use them): the buffer grows to what the launch
+  // shapes need; seam_member gives the member of each block of the seam launch
+  bool seams = false;
+  double* seam = nullptr;
+  size_t seam_cap = 0;
+  int32_t* seam_member = nullptr;
+  int seam_blocks = 0;
   std::vector<void*> allocs;
   // set once a stage has been recorded into a graph under stream capture: the
   // graph holds the work-item list and member table, so they stay fixed
@@ -40,6 +47,8 @@ void free_batch(hope_batch* B) {
   if (!B) return;
   for (void* p : B->allocs) (void)hipFree(p);
   if (B->items) (void)hipFree(B->items);
+  if (B->seam) (void)hipFree(B->seam);
+  if (B->seam_member) (void)hipFree(B->seam_member);
   delete B;
 }
 
@@ -86,6 +95,52 @@ int build_items(hope_batch* B) {
   return HOPE_OK;
 }
 
+// the members' segment seams at their current launch shapes: offsets into
+// the seam buffer (grown when needed) and the member of each block of 256
+// records.  Run only when no queued work can still read the old ones.
+int build_seams(hope_batch* B) {
+  B->seam_blocks = 0;
+  std::vector<int32_t> owner;
+  size_t off = 0;
+  for (int i = 0; i < B->n_members; ++i) {
+    BatchMember& bm = B->hmem[i];
+    bm.seam_off = -1;
+    bm.seam_block = 0;
+    if (!B->seams || !has_seams(bm.gs.n, bm.seg_h)) continue;
+    bm.seam_off = (int64_t)off;
+    bm.seam_block = (int32_t)owner.size();
+    off += seam_elems(bm.gs.n, B->m, bm.seg_h);
+    const size_t records = (size_t)6 * (bm.n_segs - 1) * bm.gs.n;
+    owner.resize(owner.size() + (records + kSeamBlock - 1) / kSeamBlock, i);
+  }
+  auto none = [&](int status) {
+    for (BatchMember& bm : B->hmem) bm.seam_off = -1;
+    return status;
+  };
+  if (off > B->seam_cap) {
+    if (B->seam) (void)hipFree(B->seam);
+    B->seam = nullptr;
+    B->seam_cap = 0;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, off * sizeof(double));
+    if (e != hipSuccess) return none(hip_fail(e, "hipMalloc (batch seams)"));
+    B->seam = static_cast<double*>(p);
+    B->seam_cap = off;
+  }
+  if (B->seam_member) (void)hipFree(B->seam_member);
+  B->seam_member = nullptr;
+  if (!owner.empty()) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, owner.size() * sizeof(int32_t));
+    if (e != hipSuccess) return none(hip_fail(e, "hipMalloc (batch seam blocks)"));
+    B->seam_member = static_cast<int32_t*>(p);
+    e = hipMemcpy(p, owner.data(), owner.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return none(hip_fail(e, "hipMemcpy (batch seam blocks)"));
+  }
+  B->seam_blocks = (int)owner.size();
+  return HOPE_OK;
+}
+
 int upload_members(hope_batch* B) {
   hipError_t e = hipMemcpy(B->mem, B->hmem.data(), B->hmem.size() * sizeof(BatchMember), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy (batch members)");
@@ -113,7 +168,9 @@ int batch_stage(const hope_batch* B, double* in, const double* qn, double* out, 
   st.cs = cs;
   st.dt = dt;
   st.bt = B->bt;
-  e = launch_batch_stage(B->k, B->weno, B->mem, B->items, B->n_items, B->blocks, st, stream);
+  st.seam = B->seam;
+  e = launch_batch_stage(B->k, B->weno, B->mem, B->items, B->n_items, B->blocks, B->seam_member, B->seam_blocks, st,
+                         stream);
   if (e) return hip_fail((hipError_t)e, "batch stage launch");
   return HOPE_OK;
 }
@@ -141,6 +198,7 @@ int hope_batch_create(const hope_grid* const* grids, int32_t n_members, const do
   B->k = grids[0]->h.k;
   B->weno = grids[0]->h.weno;
   B->m = grids[0]->h.m;
+  B->seams = uses_seams(grids[0]->h);
   B->member_grid.assign(grids, grids + n_members);
   std::vector<double> fco(18 * (size_t)n_members);
   int64_t qo = 0, fo = 0, bo = 0;
@@ -203,6 +261,7 @@ int hope_batch_create(const hope_grid* const* grids, int32_t n_members, const do
   if (!st) st = upload_vec(B, bgs, &B->dgrids);
   if (!st) st = upload_vec(B, ml, &B->mlist);
   if (!st) st = upload_vec(B, em, &B->edge_member);
+  if (!st) st = build_seams(B);
   if (!st) {
     for (int i = 0; i < n_members; ++i) B->hmem[i].fcoef = B->fcoef + 18 * (size_t)i;
     st = upload_vec(B, B->hmem, &B->mem);
@@ -269,7 +328,8 @@ int hope_batch_set_launch(hope_batch* B, const int32_t* strip_w, const int32_t* 
   hipError_t e0 = hipDeviceSynchronize();
   if (e0 != hipSuccess) return hip_fail(e0, "hipDeviceSynchronize");
   B->blocks = blocks;
-  int st = upload_members(B);
+  int st = build_seams(B);
+  if (!st) st = upload_members(B);
   if (!st) st = build_items(B);
   if (st) return st;
   hipError_t e = hipDeviceSynchronize();

@@ -21,6 +21,8 @@ struct BatchMember {
   int32_t edge_begin;       // first flattened panel-edge side (multiple of 64)
   int32_t strip_w, seg_h, n_strips, n_segs;
   int32_t half;             // strip_w <= kHalfStrip: two strips per work item
+  int32_t seam_block;       // first block of this member's records in the seam launch
+  int64_t seam_off;         // segment seams at seam + seam_off (SeamLayout), or -1: none
 };
 
 // The members of one grid, for the ghost fill: rows of that grid's G are
@@ -43,6 +45,7 @@ struct BatchStage {
   double ca, cb, cs;
   const double* dt;         // per member, device, or null
   double* bt;               // base of the panel-edge trace scratch
+  double* seam;             // base of the segment seams (or null)
 };
 
 // All enqueue on `stream`; return a hipError_t value.
@@ -52,8 +55,13 @@ int launch_batch_fill_halo(const BatchGrid* grids, int n_grids, int total_rows, 
 // edge_member: the member of each block of 64 flattened panel-edge sides
 int launch_batch_edge_traces(int k, int weno, const BatchMember* members, const int32_t* edge_member,
                              int total_edges, const double* in, double* bt, void* stream);
+// the stage over all work items (one workgroup per item, or `blocks`
+// persistent workgroups when 0 < blocks < n_items), then, with seam_blocks >
+// 0, the segment seams of the members that have them (seam_member: the member
+// of each block of 256 records; a member's records start on a block)
 int launch_batch_stage(int k, int weno, const BatchMember* members, const int32_t* items, int n_items, int blocks,
-                       const BatchStage& st, void* stream);
+                       const int32_t* seam_member, int seam_blocks, const BatchStage& st, void* stream);
+constexpr int kSeamBlock = 256;
 
 // members per ghost-fill pass (the accumulators of one pass live in
 // registers): 8 measured 184 us per batched fill of the 64-member ensemble

@@ -173,6 +173,12 @@ struct StageArgs {
 
 
 
+// Segment seams (SeamLayout) at WENO5 and TPP9 and up, in the single-grid and
+// batched stages alike: at the cheaper orders the seam kernel and its stores
+// cost more than the boundary rows they save.
+template <int K, bool W, int M>
+constexpr bool kSeams = (W && K == 5) || K >= 9;
+
 // The fused stage runs three wavefronts per work item: in the reconstruction
 // phase wavefront v reconstructs variable v, so that each keeps only one
 // variable's stencil passes and WENO weights live; the flux, source and

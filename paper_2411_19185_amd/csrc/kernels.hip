@@ -50,11 +50,9 @@ __global__ __launch_bounds__(64) void k_edge_traces(const double* __restrict__ t
 // ---------------------------------------------------------------------------
 // Fused stage kernel: one work item per workgroup
 // ---------------------------------------------------------------------------
-// segment seams at WENO5 and TPP9 and up (uses_seams); WENO5 is held to
+// segment seams where kSeams (uses_seams on the host); WENO5 is held to
 // three wavefronts per SIMD, the occupancy its workgroup's LDS allows (the
 // seam stores would otherwise raise its allocation past it)
-template <int K, bool W, int M>
-constexpr bool kSeams = (W && K == 5) || K >= 9;
 
 template <int K, bool W, int M, bool TP>
 __global__ __launch_bounds__(kStageThreads) __attribute__((amdgpu_waves_per_eu((W && K == 5) ? 3 : 1))) void k_stage(

@@ -114,8 +114,9 @@ class Ensemble:
 
     def capture_step(self, q_all: torch.Tensor, dt: torch.Tensor, ws: torch.Tensor | None = None,
                      scheme: str = "ssp3") -> torch.cuda.CUDAGraph:
-        """A HIP graph of one Runge-Kutta step on these buffers (nine kernel
-        launches, no memory operations).  Replaying it advances q_all in
+        """A HIP graph of one Runge-Kutta step on these buffers (12 kernel
+        launches at WENO5 and TPP9+, 9 at the other orders; no memory
+        operations).  Replaying it advances q_all in
         place with the values dt holds at replay time."""
         if ws is None:
             ws = self.workspace()

@@ -97,6 +97,31 @@ def test_batch_rk_steps_equal_each_member_grid_bitwise(scheme):
         assert same, (i, rel_err(got, g.interior(qp)))
 
 
+@pytest.mark.parametrize("blocks", [0, 5])
+def test_batch_segment_seams_rk_steps_equal_each_member_grid_bitwise(blocks):
+    """WENO5 members cut into 2-, 3- and 4-row segments, so that the batched
+    segment seams finish the rows beside every boundary (the Runge-Kutta
+    combination included), one workgroup per item or persistent."""
+    ns = [12, 17, 9]
+    print("case batch seams rk", ns, blocks, flush=True)
+    ens, q_all, tilts, states, _ = _setup(ns, order=5, scheme="weno", seed=400)
+    ens.set_launch([6, 17, 30], [2, 3, 4], blocks)
+    dts = [cfl_dt(q) * (1.0 - 0.1 * i) for i, q in enumerate(states)]
+    dt = torch.tensor(dts, dtype=torch.float64, device="cuda")
+    ws = ens.workspace()
+    for _ in range(2):
+        ens.rk_step(q_all, dt, ws, "ssp3")
+    for i, n in enumerate(ns):
+        g = _grid(n, 5, "weno", tilts[i])
+        qp = to_padded(states[i], g.r)
+        w = g.workspace()
+        for _ in range(2):
+            g.rk_step(qp, dts[i], "ssp3", w)
+        torch.cuda.synchronize()
+        got = ens.member_interior(q_all, i)
+        assert torch.equal(got, g.interior(qp)), (i, rel_err(got, g.interior(qp)))
+
+
 def test_batch_launch_shapes_and_persistent_grid_do_not_change_results():
     ns = [16, 11, 16]
     ens, q_all, _, _, _ = _setup(ns, seed=300)
