@@ -109,13 +109,14 @@ def tune_grid(grid, q: torch.Tensor, reps: int = 5, cache: str | None = None, fo
     return sw, sh
 
 
-def tune_ensemble(ens, q_all: torch.Tensor, reps: int = 3, cache: str | None = None, force: bool = False,
-                  blocks_candidates=(0, 1024, 2048, 4096)):
+def tune_ensemble(ens, q_all: torch.Tensor, reps: int = 5, cache: str | None = None, force: bool = False,
+                  blocks_candidates=(0, 1024, 2048, 4096), passes: int = 2):
     """Per-resolution (strip_w, seg_h) and the stage grid size for an
     ensemble, timed on the batched tendency of q_all: coordinate descent over
-    the resolutions (all members of one grid share a shape), then over the
-    grid size.  Applied to the ensemble and returned as (strip_w, seg_h,
-    blocks) lists per member."""
+    the resolutions (all members of one grid share a shape; ``passes`` rounds,
+    each resolution searched again with the others at their latest shapes),
+    then over the grid size.  Applied to the ensemble and returned as
+    (strip_w, seg_h, blocks) lists per member."""
     path = _cache_path(cache)
     ns = [g.n for g in ens.grids]
     groups: dict[int, list[int]] = {}
@@ -137,22 +138,23 @@ def tune_ensemble(ens, q_all: torch.Tensor, reps: int = 3, cache: str | None = N
     def run():
         ens.tendency(q_all, out)
 
-    for members in groups.values():
-        n = ens.grids[members[0]].n
-        best = None
-        for cw in strip_candidates(n):
-            for ch in SEG_CANDIDATES:
-                if ch > n:
-                    continue
-                for i in members:
-                    sw[i], sh[i] = cw, ch
-                ens.set_launch(sw, sh, blocks)
-                run()
-                t = _time(run, reps)
-                if best is None or t < best[0]:
-                    best = (t, cw, ch)
-        for i in members:
-            sw[i], sh[i] = best[1], best[2]
+    for _ in range(max(1, passes)):
+        for members in groups.values():
+            n = ens.grids[members[0]].n
+            best = None
+            for cw in strip_candidates(n):
+                for ch in SEG_CANDIDATES:
+                    if ch > n:
+                        continue
+                    for i in members:
+                        sw[i], sh[i] = cw, ch
+                    ens.set_launch(sw, sh, blocks)
+                    run()
+                    t = _time(run, reps)
+                    if best is None or t < best[0]:
+                        best = (t, cw, ch)
+            for i in members:
+                sw[i], sh[i] = best[1], best[2]
     best = None
     for b in blocks_candidates:
         ens.set_launch(sw, sh, b)
