@@ -257,12 +257,16 @@ int hope_grid_set_launch(hope_grid* grid, int32_t strip_w, int32_t seg_h);
 int hope_grid_get_launch(const hope_grid* grid, int32_t* strip_w, int32_t* seg_h);
 
 /* Per-kernel timing.  While enabled, the library brackets each kernel it
- * launches with HIP events recorded on the launch stream (events are created
- * on first use and kept by the grid).  hope_grid_profile(g, 1) clears the
- * record and starts timing every kernel; (g, HOPE_PROFILE_SELECT | bits)
- * does the same for the kernels whose bit (1 << index, indices below) is
- * set, so that the other launches carry no events (each event costs the
- * stream a few microseconds); (g, 0) stops.  hope_grid_profile_read waits for the
+ * launches with HIP events on the launch stream (events are created on first
+ * use and kept by the grid).  The fused stage's events are recorded by its
+ * launches themselves (the start of the stage kernel, the end of the seam
+ * kernel), which adds nothing between kernels; the other kernels' events are
+ * markers between launches, each costing the stream a few microseconds.
+ * Timing is skipped while the stream is being captured.
+ * hope_grid_profile(g, 1) clears the record and starts timing every kernel;
+ * (g, HOPE_PROFILE_SELECT | bits) does the same for the kernels whose bit
+ * (1 << index, indices below) is set, so that the other launches carry no
+ * events; (g, 0) stops.  hope_grid_profile_read waits for the
  * recorded events and returns the summed elapsed time and launch count of one
  * kernel: 0 ghost fill, 1 panel-edge traces, 2 fused stage, and the kernels
  * of the adjoint: 3 point values, 4 flux and source adjoints, 5 panel-edge

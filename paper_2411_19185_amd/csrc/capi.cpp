@@ -61,6 +61,33 @@ struct Timed {
     G->recs.push_back({kind, a, (int)G->used - 1});
   }
 };
+// per-kernel timing whose two events the launches record themselves
+// (launch_stage: hipExtLaunchKernel), so that timing adds no marker between
+// kernels; off under stream capture
+struct TimedLaunch {
+  hope_grid* G;
+  int kind;
+  int a = -1, b = -1;
+  hipEvent_t start = nullptr, stop = nullptr;
+  TimedLaunch(const hope_grid* g, int k, void* stream) : G(const_cast<hope_grid*>(g)), kind(k) {
+    if (!G->timing || !((G->timing_mask >> kind) & 1u)) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    hipEvent_t e0 = next_event(G);
+    if (!e0) return;
+    const int i0 = (int)G->used - 1;
+    hipEvent_t e1 = next_event(G);
+    if (!e1) return;
+    start = e0;
+    stop = e1;
+    a = i0;
+    b = (int)G->used - 1;
+  }
+  // after a successful launch
+  void done() {
+    if (a >= 0) G->recs.push_back({kind, a, b});
+  }
+};
 }  // namespace
 
 // The grid's one mutable word: the counter of hope_check_state.  Every
@@ -471,10 +498,11 @@ static int run_stage(const hope_grid* G, double* q, const double* qn, double* ou
   }
   if (e) return hip_fail((hipError_t)e, "edge_traces launch");
   {
-    Timed tm(G, 2, stream);
+    TimedLaunch tm(G, 2, stream);
     double* seam = uses_seams(G->h) ? bt + trace_bytes(G->h) / sizeof(double) : nullptr;
     e = launch_stage(G->h.k, G->h.weno, G->tab, G->itab, G->gs, q, qn, out, out_padded, ca, cb, cc, bt,
-                     G->strip_w, G->seg_h, G->topo, seam, stream);
+                     G->strip_w, G->seg_h, G->topo, seam, stream, tm.start, tm.stop);
+    if (!e) tm.done();
   }
   if (e) return hip_fail((hipError_t)e, "stage launch");
   return HOPE_OK;

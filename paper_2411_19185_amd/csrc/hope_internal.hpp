@@ -235,8 +235,13 @@ int launch_combine(size_t len, double* out, const double* x, const double* y, co
                    double c, void* stream);
 int launch_edge_traces(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs,
                        const double* q, double* bt, const TopoDev& topo, void* stream);
+// ev_start / ev_stop: null, or HIP events (hipEvent_t) that the launches
+// record themselves (hipExtLaunchKernel): the start of the stage kernel and
+// the end of the stage's last kernel, so that timing the stage adds no
+// marker to the stream
 int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs,
                  const double* q, const double* qn, double* out, int out_padded, double ca, double cb, double cc,
-                 const double* bt, int strip_w, int seg_h, const TopoDev& topo, double* seam, void* stream);
+                 const double* bt, int strip_w, int seg_h, const TopoDev& topo, double* seam, void* stream,
+                 void* ev_start = nullptr, void* ev_stop = nullptr);
 
 }  // namespace hope

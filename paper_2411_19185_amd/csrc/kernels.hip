@@ -13,6 +13,7 @@
 //  k_combine       out = a x + b y + c z (the Runge-Kutta adjoint)
 //  k_check_state   count of interior cells with a thickness that is not positive
 //                  or a variable that is not finite
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -148,26 +149,30 @@ static int edge_traces_t(const double* tab, const int32_t* itab, const GridScala
 }
 
 template <int K, bool W, int M>
-static int stage_t(const double* tab, const GridScalars& gs, const StageArgs& a_in, void* stream) {
+static int stage_t(const double* tab, const GridScalars& gs, const StageArgs& a_in, void* stream, void* ev_start,
+                   void* ev_stop) {
   StageArgs a = a_in;
   if constexpr (!kSeams<K, W, M>) a.seam = nullptr;   // the kernel is compiled without them
   const int items = stage_items(a.strip_w, a.n_strips, a.n_segs);
+  const hipStream_t s = (hipStream_t)stream;
+  const hipEvent_t e0 = (hipEvent_t)ev_start, e1 = (hipEvent_t)ev_stop;
+  const bool seams = a.seam != nullptr;
   if (a.tp.sbar)
-    hipLaunchKernelGGL((k_stage<K, W, M, true>), dim3(items), dim3(kStageThreads), 0, (hipStream_t)stream, tab, gs,
-                       a);
+    hipExtLaunchKernelGGL((k_stage<K, W, M, true>), dim3(items), dim3(kStageThreads), 0, s, e0, seams ? nullptr : e1,
+                          0, tab, gs, a);
   else
-    hipLaunchKernelGGL((k_stage<K, W, M, false>), dim3(items), dim3(kStageThreads), 0, (hipStream_t)stream, tab, gs,
-                       a);
+    hipExtLaunchKernelGGL((k_stage<K, W, M, false>), dim3(items), dim3(kStageThreads), 0, s, e0, seams ? nullptr : e1,
+                          0, tab, gs, a);
   if constexpr (kSeams<K, W, M>) {
-    if (a.seam) {
+    if (seams) {
       const size_t records = (size_t)6 * (a.n_segs - 1) * gs.n;
       const dim3 grid((unsigned)((records + 255) / 256));
       if (a.tp.sbar)
-        hipLaunchKernelGGL((k_stage_seams<K, W, M, true>), grid, dim3(256), 0, (hipStream_t)stream, tab, gs, a,
-                           records);
+        hipExtLaunchKernelGGL((k_stage_seams<K, W, M, true>), grid, dim3(256), 0, s, nullptr, e1, 0, tab, gs, a,
+                              records);
       else
-        hipLaunchKernelGGL((k_stage_seams<K, W, M, false>), grid, dim3(256), 0, (hipStream_t)stream, tab, gs, a,
-                           records);
+        hipExtLaunchKernelGGL((k_stage_seams<K, W, M, false>), grid, dim3(256), 0, s, nullptr, e1, 0, tab, gs, a,
+                              records);
     }
   }
   return (int)hipGetLastError();
@@ -200,7 +205,8 @@ int launch_edge_traces(int k, int weno, const double* tab, const int32_t* itab, 
 
 int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const GridScalars& gs, const double* q,
                  const double* qn, double* out, int out_padded, double ca, double cb, double cc, const double* bt,
-                 int strip_w, int seg_h, const TopoDev& topo, double* seam, void* stream) {
+                 int strip_w, int seg_h, const TopoDev& topo, double* seam, void* stream, void* ev_start,
+                 void* ev_stop) {
   (void)itab;
   StageArgs a;
   a.tp = topo;
@@ -220,7 +226,7 @@ int launch_stage(int k, int weno, const double* tab, const int32_t* itab, const 
   // seams only where the scratch is sized for them (segments of >= 2 rows,
   // >= 2 segments) and the kernel is compiled with them
   a.seam = has_seams(gs.n, seg_h) ? seam : nullptr;
-  HOPE_DISPATCH(stage_t, tab, gs, a, stream);
+  HOPE_DISPATCH(stage_t, tab, gs, a, stream, ev_start, ev_stop);
 }
 
 }  // namespace hope

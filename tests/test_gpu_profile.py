@@ -1,5 +1,6 @@
 """GPU test of the per-kernel timing: every kernel, or only selected ones,
-is bracketed by events, and timing does not change results."""
+is bracketed by events (the fused stage's recorded by its own launches, with
+and without the seam kernel), and timing does not change results."""
 import ctypes
 
 import pytest
@@ -28,8 +29,15 @@ def test_profile_all_or_selected_kernels():
     b2 = g.tendency(qp)
     g.profile(False)
     assert [g.profile_read(k)[1] for k in ("fill_halo", "edge_traces", "stage")] == [0, 0, 2]
+    # one segment per panel: no seam kernel, the stage kernel records both events
+    g.set_launch(30, n)
+    g.profile(True, only=("stage",))
+    c = g.tendency(qp)
+    g.profile(False)
+    ms, cnt = g.profile_read("stage")
+    assert cnt == 1 and ms > 0
     torch.cuda.synchronize()
-    assert torch.equal(a, ref) and torch.equal(b, ref) and torch.equal(b2, ref)
+    assert torch.equal(a, ref) and torch.equal(b, ref) and torch.equal(b2, ref) and torch.equal(c, ref)
     # codes other than 0, 1 and HOPE_PROFILE_SELECT | kernel bits are rejected
     assert lib().hope_grid_profile(g._h, 2) == -1
     assert lib().hope_grid_profile(g._h, HOPE_PROFILE_SELECT | (1 << 12)) == -1
