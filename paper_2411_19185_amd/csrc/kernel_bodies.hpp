@@ -11,14 +11,15 @@
 //
 // stage_tile marches: a workgroup of three wavefronts owns a strip of up to 62
 // interior columns of one panel (lanes 1..62; lanes 0 and 63 are the strip's
-// ring columns) and a segment of rows, walking up the rows.  The 2r+1 stencil
-// rows of the strip sit in an LDS ring buffer (one new row per step, fetched
-// a step ahead).  At each row wavefront v reconstructs variable v of every
-// lane's cell into LDS; then wavefront 0 evaluates the flux through each
-// lane's left edge (left state: lane L-1's right trace), wavefront 1 the flux
-// through the bottom edge (left state: the top traces of the row below,
-// carried from the previous step) and wavefront 2 the sources.  No trace goes
-// to HBM.
+// ring columns), or two strips of up to 30 (one per half of the lanes), and a
+// segment of rows, walking up the rows.  The 2r+1 stencil rows of the strip
+// sit in an LDS ring buffer (one new row per step, fetched a step ahead).  At
+// each row wavefront v reconstructs variable v of every lane's cell into LDS;
+// then wavefront 0 evaluates the flux through each lane's left edge (left
+// state: lane L-1's right trace), wavefront 1 the flux through the bottom edge
+// (left state: the top traces of the row below, carried from the previous
+// step) and wavefront 2 the sources.  The only traces that go to HBM are those
+// of the rows beside a segment boundary, for the segment seams.
 //
 // The grid's constant tables are one buffer read through the constant address
 // space: with uniform addresses those reads are scalar loads into SGPRs.
