@@ -6,7 +6,7 @@ import ctypes
 import pytest
 import torch
 
-from cases import STATES, to_padded
+from cases import STATES, cfl_dt, to_padded
 
 pytestmark = pytest.mark.gpu
 
@@ -42,3 +42,29 @@ def test_profile_all_or_selected_kernels():
     assert lib().hope_grid_profile(g._h, 2) == -1
     assert lib().hope_grid_profile(g._h, HOPE_PROFILE_SELECT | (1 << 12)) == -1
     assert lib().hope_grid_profile(g._h, 0) == 0
+
+
+def test_captured_rk_steps_with_stage_timing_on_equal_eager_steps():
+    """hope_rk_step recorded in a HIP graph while the stage is being timed
+    (timing steps aside under stream capture): every replay, with eager steps
+    and synchronisations between the replays, equals the eager steps bitwise."""
+    from paper_2411_19185_amd import Grid
+    n = 24
+    alpha, q = STATES["member"](n, 5, nq=2)
+    g = Grid(n, 5, "weno", axis_tilt=alpha)
+    dt = cfl_dt(q)
+    ws, ws_eager = g.workspace(), g.workspace()
+    q_graph = to_padded(q, g.r)
+    q_eager = q_graph.clone()
+    g.profile(True, only=("stage",))
+    g.rk_step(q_graph.clone(), dt, "ssp3", ws)      # loads the kernels before capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.rk_step(q_graph, dt, "ssp3", ws)
+    g.profile(False)
+    for k in range(3):
+        graph.replay()
+        g.rk_step(q_eager, dt, "ssp3", ws_eager)
+        torch.cuda.synchronize()
+        assert torch.equal(q_graph, q_eager), k
