@@ -176,6 +176,17 @@ struct GhostDev {
   int64_t nnz;           // entries of all rows
   int64_t cnnz;          // entries of the canonical rows
   int rows;
+  // row blocks of the LDS-staged fill (blocks = 0: none): block b holds rows
+  // brow[b] .. brow[b+1]-1, which read the interior cells bsrc[bptr[b] ..
+  // bptr[b+1]) (offsets in variable 0 of the padded state, as GhostEnt.col);
+  // lent[k] = entry k's ce (canonical value and frame code, 16 bits) | the
+  // position of its cell in its block's list << 16; umax the longest list
+  const int32_t* brow = nullptr;
+  const int32_t* bptr = nullptr;
+  const int32_t* bsrc = nullptr;
+  const uint32_t* lent = nullptr;
+  int blocks = 0;
+  int umax = 0;
 };
 
 // Topography tables on the device (the TopoHost arrays); a null sbar means

@@ -1,7 +1,8 @@
 // Device bodies of the HOPE right-hand-side kernels, shared by the kernels of
 // one grid (kernels.hip) and the batched ensemble kernels (batch.hip).
 //
-//  halo_row    one row of the ghost fill g = G q (appendix (7.12))
+//  halo_row    one row of the ghost fill g = G q (appendix (7.12)), from the
+//              state or from a workgroup's LDS copy of the cells its rows read
 //  edge_trace  at one panel-edge side, the neighbour panel's own trace,
 //              converted into this panel's variables (3.26)-(3.29)
 //  stage_tile  one work item of the fused stage: reconstruction (TPP (3.14)
@@ -49,26 +50,29 @@ constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_block(int b, int nb) { return (b % kXcds) * (nb / kXcds) + b / kXcds; }
 
 // one ghost row of g = G q, reduced over LANES lanes (lane = 0.. of the
-// group): entries in column order, values from the row's canonical row
-template <int LANES>
-__device__ __forceinline__ void halo_row(const GhostDev& g, double* __restrict__ q, size_t plane, int row, int lane) {
+// group): entries in column order, values from the row's canonical row;
+// src(k, ce, a0, a1, a2) gives entry k's ce (canonical value and frame code)
+// and the three variables of its cell (from the state, or from the LDS copy
+// of the LDS-staged fill: the same values)
+template <int LANES, typename Src>
+__device__ __forceinline__ void halo_row_from(const GhostDev& g, double* __restrict__ q, size_t plane, int row,
+                                              int lane, Src src) {
   const int b = g.ptr[row], e = g.ptr[row + 1];
   const int info = g.info[row];
   const GhostVal* cv = g.cval + (info & 0x0fffffff);
-  const double* q1 = q + plane;
-  const double* q2 = q + 2 * (size_t)plane;
   double mass = 0, mu = 0, mv = 0;
   for (int k = b + lane; k < e; k += LANES) {
-    const GhostEnt en = g.ent[k];
-    const int c = en.col;
-    const int j = en.ce & 0x1fff, f = en.ce >> 13;
+    int ce;
+    double a0, a1, a2;
+    src(k, ce, a0, a1, a2);
+    const int j = ce & 0x1fff, f = ce >> 13;
     const GhostVal cj = cv[j];
     double w1, w2, w3, w4;
     frame_apply(f, cj.v[1], cj.v[2], w1, w2);
     frame_apply(f, cj.v[3], cj.v[4], w3, w4);
-    mass = fma(cj.v[0], q[c], mass);
-    mu = fma(w1, q1[c], fma(w2, q2[c], mu));
-    mv = fma(w3, q1[c], fma(w4, q2[c], mv));
+    mass = fma(cj.v[0], a0, mass);
+    mu = fma(w1, a1, fma(w2, a2, mu));
+    mv = fma(w3, a1, fma(w4, a2, mv));
   }
 #pragma unroll
   for (int off = LANES / 2; off > 0; off >>= 1) {
@@ -84,6 +88,21 @@ __device__ __forceinline__ void halo_row(const GhostDev& g, double* __restrict__
     q[plane + d] = gu;
     q[2 * (size_t)plane + d] = gv;
   }
+}
+
+// one ghost row reading the state itself
+template <int LANES>
+__device__ __forceinline__ void halo_row(const GhostDev& g, double* __restrict__ q, size_t plane, int row, int lane) {
+  const double* q1 = q + plane;
+  const double* q2 = q + 2 * (size_t)plane;
+  halo_row_from<LANES>(g, q, plane, row, lane, [&](int k, int& ce, double& a0, double& a1, double& a2) {
+    const GhostEnt en = g.ent[k];
+    const int c = en.col;
+    ce = en.ce;
+    a0 = q[c];
+    a1 = q1[c];
+    a2 = q2[c];
+  });
 }
 
 // the converted neighbour trace at the panel-edge side idx (0 <= idx < 24 n),

@@ -2,6 +2,7 @@
 // bodies they run are in kernel_bodies.hpp.
 //
 //  k_fill_halo     ghost cells g = G q (appendix (7.12)); halo_lanes(k) lanes per ghost row
+//  k_fill_halo_lds the same by blocks of rows, the cells a block reads staged in LDS
 //  k_edge_traces   at every panel-edge Gauss point, the neighbour panel's own
 //                  trace, converted into this panel's variables (3.26)-(3.29);
 //                  one group of kEdgeLanes lanes per panel-edge cell side
@@ -33,6 +34,39 @@ __global__ __launch_bounds__(256) void k_fill_halo(GhostDev g, double* __restric
   const int row = (int)((lb * (size_t)blockDim.x + threadIdx.x) / LANES);
   if (row >= g.rows) return;   // the whole lane group leaves together
   halo_row<LANES>(g, q, plane, row, threadIdx.x % LANES);
+}
+
+// the same, a block of rows per workgroup (GhostDev.brow): the interior cells
+// the block reads are first copied to LDS (3 x umax doubles), then each row's
+// lane group sums its entries from there, in the order of k_fill_halo
+template <int LANES>
+__global__ __launch_bounds__(256) void k_fill_halo_lds(GhostDev g, double* __restrict__ q, int plane) {
+  extern __shared__ double sq[];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= g.blocks) return;   // the whole workgroup leaves together
+  const int s0 = g.bptr[b], U = g.bptr[b + 1] - s0;
+  const double* q1 = q + plane;
+  const double* q2 = q + 2 * (size_t)plane;
+  double* l0 = sq;
+  double* l1 = sq + g.umax;
+  double* l2 = sq + 2 * g.umax;
+  for (int u = threadIdx.x; u < U; u += blockDim.x) {
+    const int c = g.bsrc[s0 + u];
+    l0[u] = q[c];
+    l1[u] = q1[c];
+    l2[u] = q2[c];
+  }
+  __syncthreads();
+  const int row = g.brow[b] + (int)threadIdx.x / LANES;
+  if (row >= g.brow[b + 1]) return;   // the whole lane group leaves together
+  halo_row_from<LANES>(g, q, plane, row, threadIdx.x % LANES, [&](int k, int& ce, double& a0, double& a1, double& a2) {
+    const uint32_t le = g.lent[k];
+    const int l = (int)(le >> 16);
+    ce = (int)(le & 0xffffu);
+    a0 = l0[l];
+    a1 = l1[l];
+    a2 = l2[l];
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -125,6 +159,15 @@ int launch_fill_halo(const GhostDev& g, double* q, int plane, int lanes, void* s
   if (g.rows == 0) return 0;
   if (lanes != 32 && lanes != 64) return (int)hipErrorInvalidValue;
   const int threads = 256;
+  if (g.blocks > 0) {
+    const int blocks = (g.blocks + kXcds - 1) / kXcds * kXcds;
+    const size_t lds = (size_t)3 * g.umax * sizeof(double);
+    if (lanes == 64)
+      hipLaunchKernelGGL(k_fill_halo_lds<64>, dim3(blocks), dim3(threads), lds, (hipStream_t)stream, g, q, plane);
+    else
+      hipLaunchKernelGGL(k_fill_halo_lds<32>, dim3(blocks), dim3(threads), lds, (hipStream_t)stream, g, q, plane);
+    return (int)hipGetLastError();
+  }
   int blocks = (int)(((size_t)g.rows * lanes + threads - 1) / threads);
   blocks = (blocks + kXcds - 1) / kXcds * kXcds;
   if (lanes == 64)
