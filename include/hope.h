@@ -314,6 +314,7 @@ typedef struct hope_batch_info {
   int64_t items;               /* fused-stage work items per launch */
   int64_t blocks;              /* workgroups of the fused stage (0: one per item) */
   int64_t ghost_rows;          /* ghost rows of all distinct grids */
+  int64_t fill_blocks;         /* row blocks of the LDS-staged ghost fill (0: the direct fill) */
 } hope_batch_info;
 
 /* grids[i]: the grid of member i (they must outlive the batch; grids with

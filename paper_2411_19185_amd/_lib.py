@@ -84,6 +84,7 @@ class BatchInfo(ctypes.Structure):
         ("items", ctypes.c_int64),
         ("blocks", ctypes.c_int64),
         ("ghost_rows", ctypes.c_int64),
+        ("fill_blocks", ctypes.c_int64),
     ]
 
 

@@ -3,6 +3,8 @@
 // bodies as the single-grid kernels (kernel_bodies.hpp), so a member's result
 // is bitwise the one its own grid gives.
 //
+//  k_fill_halo_batch_lds  the same by row blocks, the cells a block reads
+//                         staged in LDS for kHaloLdsChunk members at a time
 //  k_fill_halo_batch      ghost fill g = G q (appendix (7.12)) of all members:
 //                         one lane group per ghost row of a grid, applied to
 //                         that grid's members while the row's entries sit in
@@ -78,6 +80,89 @@ __global__ __launch_bounds__(256) void k_fill_halo_batch(const BatchGrid* __rest
       }
       if (lane == 0 && t < cnt) {
         double* q = qm[t];
+        double gu, gv;
+        frame_apply(info >> 28, acc[t][1], acc[t][2], gu, gv);
+        q[d] = acc[t][0];
+        q[plane + d] = gu;
+        q[2 * plane + d] = gv;
+      }
+    }
+  }
+}
+
+// the batched fill by row blocks (BatchGrid.brow ...): workgroup lb takes one
+// block of one grid; for each chunk of kHaloLdsChunk of that grid's members it
+// stages their cells in LDS, then each row's lane group sums its entries from
+// there, in the order of k_fill_halo_batch
+template <int LANES>
+__global__ __launch_bounds__(256) void k_fill_halo_batch_lds(const BatchGrid* __restrict__ grids, int n_grids,
+                                                             int total_blocks, int ucap,
+                                                             const int32_t* __restrict__ mlist,
+                                                             const BatchMember* __restrict__ mem,
+                                                             double* __restrict__ base) {
+  extern __shared__ double sq[];   // [kHaloLdsChunk][3][ucap]
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  if (lb >= total_blocks) return;   // the whole workgroup leaves together
+  int gi = 0;
+  while (gi + 1 < n_grids && grids[gi + 1].block_begin <= lb) ++gi;
+  const BatchGrid& bg = grids[gi];
+  const GhostDev& g = bg.g;
+  const int b = lb - bg.block_begin;
+  const int s0 = bg.bptr[b], U = bg.bptr[b + 1] - s0;
+  const int row = bg.brow[b] + (int)threadIdx.x / LANES;
+  const bool active = row < bg.brow[b + 1];   // uniform over a lane group
+  const int lane = threadIdx.x % LANES;
+  const size_t plane = (size_t)6 * bg.P * bg.P;
+  const int kb = active ? g.ptr[row] : 0, ke = active ? g.ptr[row + 1] : 0;
+  const int info = active ? g.info[row] : 0;
+  const GhostVal* cv = g.cval + (info & 0x0fffffff);
+  for (int c0 = 0; c0 < bg.member_count; c0 += kHaloLdsChunk) {
+    const int cnt = min(kHaloLdsChunk, bg.member_count - c0);
+    if (c0 > 0) __syncthreads();   // the previous chunk's LDS reads are done
+    for (int x = threadIdx.x; x < cnt * U; x += blockDim.x) {
+      const int t = x / U, u = x - t * U;
+      const double* q = base + mem[mlist[bg.member_begin + c0 + t]].q_off;
+      const int c = bg.bsrc[s0 + u];
+      sq[(t * 3 + 0) * ucap + u] = q[c];
+      sq[(t * 3 + 1) * ucap + u] = q[plane + c];
+      sq[(t * 3 + 2) * ucap + u] = q[2 * plane + c];
+    }
+    __syncthreads();
+    if (!active) continue;
+    double acc[kHaloLdsChunk][3];
+#pragma unroll
+    for (int t = 0; t < kHaloLdsChunk; ++t) acc[t][0] = acc[t][1] = acc[t][2] = 0.0;
+    for (int k = kb + lane; k < ke; k += LANES) {
+      const uint32_t le = bg.lent[k];
+      const int l = (int)(le >> 16), ce = (int)(le & 0xffffu);
+      const int j = ce & 0x1fff, f = ce >> 13;
+      const GhostVal cj = cv[j];
+      const double v0 = cj.v[0];
+      double w1, w2, w3, w4;   // the block rows acting on the cell's own frame
+      frame_apply(f, cj.v[1], cj.v[2], w1, w2);
+      frame_apply(f, cj.v[3], cj.v[4], w3, w4);
+#pragma unroll
+      for (int t = 0; t < kHaloLdsChunk; ++t) {
+        if (t < cnt) {
+          const double a0 = sq[(t * 3 + 0) * ucap + l], a1 = sq[(t * 3 + 1) * ucap + l],
+                       a2 = sq[(t * 3 + 2) * ucap + l];
+          acc[t][0] = fma(v0, a0, acc[t][0]);
+          acc[t][1] = fma(w1, a1, fma(w2, a2, acc[t][1]));
+          acc[t][2] = fma(w3, a1, fma(w4, a2, acc[t][2]));
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kHaloLdsChunk; ++t) {
+#pragma unroll
+      for (int off = LANES / 2; off > 0; off >>= 1) {
+        acc[t][0] += __shfl_xor(acc[t][0], off, LANES);
+        acc[t][1] += __shfl_xor(acc[t][1], off, LANES);
+        acc[t][2] += __shfl_xor(acc[t][2], off, LANES);
+      }
+      if (lane == 0 && t < cnt) {
+        double* q = base + mem[mlist[bg.member_begin + c0 + t]].q_off;
+        const int d = g.dst[row];
         double gu, gv;
         frame_apply(info >> 28, acc[t][1], acc[t][2], gu, gv);
         q[d] = acc[t][0];
@@ -168,10 +253,22 @@ __global__ __launch_bounds__(kSeamBlock) void k_stage_seams_batch(const BatchMem
 // Launchers
 // ---------------------------------------------------------------------------
 int launch_batch_fill_halo(const BatchGrid* grids, int n_grids, int total_rows, const int32_t* members_by_grid,
-                           const BatchMember* members, double* base, int lanes, void* stream) {
+                           const BatchMember* members, double* base, int lanes, int total_blocks, int ucap,
+                           void* stream) {
   if (total_rows == 0) return 0;
   const int threads = 256;
   if (lanes != 32 && lanes != 64) return (int)hipErrorInvalidValue;
+  if (total_blocks > 0) {
+    const int blocks = (total_blocks + kXcds - 1) / kXcds * kXcds;
+    const size_t lds = (size_t)kHaloLdsChunk * 3 * ucap * sizeof(double);
+    if (lanes == 64)
+      hipLaunchKernelGGL(k_fill_halo_batch_lds<64>, dim3(blocks), dim3(threads), lds, (hipStream_t)stream, grids,
+                         n_grids, total_blocks, ucap, members_by_grid, members, base);
+    else
+      hipLaunchKernelGGL(k_fill_halo_batch_lds<32>, dim3(blocks), dim3(threads), lds, (hipStream_t)stream, grids,
+                         n_grids, total_blocks, ucap, members_by_grid, members, base);
+    return (int)hipGetLastError();
+  }
   int blocks = (int)(((size_t)total_rows * lanes + threads - 1) / threads);
   blocks = (blocks + kXcds - 1) / kXcds * kXcds;
   if (lanes == 64)

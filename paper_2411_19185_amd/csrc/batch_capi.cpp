@@ -20,6 +20,7 @@ struct hope_batch {
   std::vector<int64_t> q_off, f_off;           // per member
   int64_t state_elems = 0, field_elems = 0, bt_elems = 0;
   int total_rows = 0, total_edges = 0, n_items = 0, blocks = 0;
+  int fill_blocks = 0, fill_ucap = 0;          // the LDS-staged fill (0: the direct one)
   std::vector<BatchMember> hmem;               // host copy of the member table
   BatchMember* mem = nullptr;
   BatchGrid* dgrids = nullptr;
@@ -154,7 +155,7 @@ int batch_stage(const hope_batch* B, double* in, const double* qn, double* out, 
       cs_status != hipStreamCaptureStatusNone)
     B->captured = true;
   int e = launch_batch_fill_halo(B->dgrids, B->n_grids, B->total_rows, B->mlist, B->mem, in, halo_lanes(B->k),
-                                 stream);
+                                 B->fill_blocks, B->fill_ucap, stream);
   if (e) return hip_fail((hipError_t)e, "batch fill_halo launch");
   e = launch_batch_edge_traces(B->k, B->weno, B->mem, B->edge_member, B->total_edges, in, B->bt, stream);
   if (e) return hip_fail((hipError_t)e, "batch edge_traces launch");
@@ -252,12 +253,52 @@ int hope_batch_create(const hope_grid* const* grids, int32_t n_members, const do
       if (grids[i] == G) ml.push_back(i);
     bg.member_count = (int32_t)ml.size() - bg.member_begin;
     bg.P = G->h.P;
+    bg.brow = bg.bptr = bg.bsrc = nullptr;
+    bg.lent = nullptr;
+    bg.block_begin = bg.blocks = 0;
     rows += G->g.rows;
     bgs.push_back(bg);
   }
   B->n_grids = (int)bgs.size();
   B->total_rows = rows;
-  int st = upload_vec(B, fco, &B->fcoef);
+  int st = HOPE_OK;
+  {
+    // row blocks of the LDS-staged fill for every grid, or none at all
+    // (the grid keeps its ghost map on the device only: copied back here)
+    std::vector<FillBlocks> fbs(B->grids.size());
+    bool lds = true;
+    for (size_t gi = 0; gi < B->grids.size() && lds; ++gi) {
+      const hope_grid* G = B->grids[gi];
+      const int grows = G->g.rows;
+      std::vector<int32_t> ptr((size_t)grows + 1), ent(2 * (size_t)G->g.nnz);
+      hipError_t e = hipMemcpy(ptr.data(), G->g.ptr, ptr.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+      if (e == hipSuccess)
+        e = hipMemcpy(ent.data(), G->g.ent, ent.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        st = hip_fail(e, "hipMemcpy (batch ghost map)");
+        break;
+      }
+      lds = build_fill_blocks(grows, ptr.data(), ent.data(), (size_t)6 * G->h.P * G->h.P, 256 / halo_lanes(B->k),
+                              kHaloLdsCells, fbs[gi]);
+    }
+    if (st) lds = false;
+    if (lds) {
+      int nb = 0;
+      for (size_t gi = 0; gi < B->grids.size() && !st; ++gi) {
+        BatchGrid& bg = bgs[gi];
+        st = upload_vec(B, fbs[gi].brow, const_cast<int32_t**>(&bg.brow));
+        if (!st) st = upload_vec(B, fbs[gi].bptr, const_cast<int32_t**>(&bg.bptr));
+        if (!st) st = upload_vec(B, fbs[gi].bsrc, const_cast<int32_t**>(&bg.bsrc));
+        if (!st) st = upload_vec(B, fbs[gi].lent, const_cast<uint32_t**>(&bg.lent));
+        bg.block_begin = nb;
+        bg.blocks = (int32_t)fbs[gi].brow.size() - 1;
+        nb += bg.blocks;
+        B->fill_ucap = std::max(B->fill_ucap, fbs[gi].umax);
+      }
+      B->fill_blocks = nb;
+    }
+  }
+  if (!st) st = upload_vec(B, fco, &B->fcoef);
   if (!st) st = upload_vec(B, bgs, &B->dgrids);
   if (!st) st = upload_vec(B, ml, &B->mlist);
   if (!st) st = upload_vec(B, em, &B->edge_member);
@@ -296,6 +337,7 @@ int hope_batch_layout(const hope_batch* B, hope_batch_info* out, int64_t* state_
   out->items = B->n_items;
   out->blocks = B->blocks;
   out->ghost_rows = B->total_rows;
+  out->fill_blocks = B->fill_blocks;
   for (int i = 0; i < B->n_members; ++i) {
     if (state_offsets) state_offsets[i] = B->q_off[i];
     if (field_offsets) field_offsets[i] = B->f_off[i];

@@ -33,6 +33,14 @@ struct BatchGrid {
   int32_t member_begin;     // into the member list grouped by grid
   int32_t member_count;
   int32_t P;
+  // the LDS-staged fill: this grid's row blocks (as GhostDev.brow ..., at
+  // most kHaloLdsCells cells each), the first in the launch's flattened list
+  const int32_t* brow;
+  const int32_t* bptr;
+  const int32_t* bsrc;
+  const uint32_t* lent;
+  int32_t block_begin;
+  int32_t blocks;
 };
 
 // One launch of a stage: q_{s+1} = ca q^n + cb q_s + cs * dt[member] * L(q_s)
@@ -50,8 +58,12 @@ struct BatchStage {
 
 // All enqueue on `stream`; return a hipError_t value.
 // lanes: lanes per ghost row, halo_lanes(order) as in the single-grid fill
+// with total_blocks > 0 the LDS-staged fill (each workgroup one row block of
+// one grid, its members' cells staged kHaloLdsChunk members at a time; ucap:
+// the longest cell list)
 int launch_batch_fill_halo(const BatchGrid* grids, int n_grids, int total_rows, const int32_t* members_by_grid,
-                           const BatchMember* members, double* base, int lanes, void* stream);
+                           const BatchMember* members, double* base, int lanes, int total_blocks, int ucap,
+                           void* stream);
 // edge_member: the member of each block of 64 flattened panel-edge sides
 int launch_batch_edge_traces(int k, int weno, const BatchMember* members, const int32_t* edge_member,
                              int total_edges, const double* in, double* bt, void* stream);
@@ -70,5 +82,11 @@ constexpr int kSeamBlock = 256;
 #define HOPE_HALO_CHUNK 8
 #endif
 constexpr int kHaloChunk = HOPE_HALO_CHUNK;
+// the LDS-staged batched fill stages kHaloLdsChunk members at a time, at most
+// kHaloLdsCells cells per row block: 4 x 3 x 512 doubles = 48 KB of LDS per
+// workgroup (a WENO5 ghost row reads up to 342 cells; rows that read more, from
+// order 7, take the direct batched fill)
+constexpr int kHaloLdsChunk = 4;
+constexpr int kHaloLdsCells = 512;
 
 }  // namespace hope

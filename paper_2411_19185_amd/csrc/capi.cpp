@@ -118,64 +118,73 @@ static int upload(hope_grid* G, const std::vector<T>& v, const T** out) {
   return 0;
 }
 
-// Row blocks of the LDS-staged ghost fill: consecutive device rows, as many
-// as one workgroup's lane groups take (256 / halo_lanes), closed early when the
-// interior cells they read would pass the LDS budget (1024 cells, 2048 from
-// order 7); each block lists the distinct cells its rows read, and each entry
-// gets the position of its cell in that list, packed with its ce.
-static int build_fill_blocks(hope_grid* G) {
-  const hope::HostTables& h = G->h;
-  hope::GhostDev& g = G->g;
-  const int rows = (int)h.z_dst.size();
-  if (rows == 0) return 0;
-  const int rb = 256 / hope::halo_lanes(h.k);
-  const int cap = h.k >= 7 ? 2048 : 1024;
-  const size_t cells = (size_t)6 * h.P * h.P;
+namespace hope {
+bool build_fill_blocks(int rows, const int32_t* ptr, const int32_t* ent, size_t cells, int rb, int cap,
+                       FillBlocks& out) {
+  out = FillBlocks();
+  if (rows == 0 || cap > 0xffff) return false;
   std::vector<int32_t> mark(cells, -1), seen(cells, -1), local(cells, 0);
-  std::vector<int32_t> brow(1, 0), bptr(1, 0), bsrc;
-  std::vector<uint32_t> lent(h.z_ent.size() / 2);
-  int blk = 0, in_blk = 0, used = 0, umax = 0;
+  FillBlocks fb;
+  fb.brow.push_back(0);
+  fb.bptr.push_back(0);
+  fb.lent.resize((size_t)ptr[rows]);
+  int blk = 0, in_blk = 0, used = 0;
   for (int r = 0; r < rows; ++r) {
     int add = 0, distinct = 0;
-    for (int32_t k = h.z_ptr[r]; k < h.z_ptr[r + 1]; ++k) {
-      const int32_t c = h.z_ent[2 * (size_t)k];
-      if (c < 0 || (size_t)c >= cells) return hope::fail(HOPE_ERR_NUMERIC, "ghost map: entry outside the state");
-      if (h.z_ent[2 * (size_t)k + 1] < 0 || h.z_ent[2 * (size_t)k + 1] > 0xffff) return 0;   // keep the direct fill
+    for (int32_t k = ptr[r]; k < ptr[r + 1]; ++k) {
+      const int32_t c = ent[2 * (size_t)k], ce = ent[2 * (size_t)k + 1];
+      if (c < 0 || (size_t)c >= cells || ce < 0 || ce > 0xffff) return false;
       if (seen[c] != r) {
         seen[c] = r;
         ++distinct;
         if (mark[c] != blk) ++add;
       }
     }
-    if (distinct > cap) return 0;   // a row too long for the budget: keep the direct fill
+    if (distinct > cap) return false;
     if (in_blk > 0 && (in_blk == rb || used + add > cap)) {
-      brow.push_back(r);
-      bptr.push_back((int32_t)bsrc.size());
+      fb.brow.push_back(r);
+      fb.bptr.push_back((int32_t)fb.bsrc.size());
       ++blk;
       in_blk = 0;
       used = 0;
     }
-    for (int32_t k = h.z_ptr[r]; k < h.z_ptr[r + 1]; ++k) {
-      const int32_t c = h.z_ent[2 * (size_t)k];
+    for (int32_t k = ptr[r]; k < ptr[r + 1]; ++k) {
+      const int32_t c = ent[2 * (size_t)k];
       if (mark[c] != blk) {
         mark[c] = blk;
         local[c] = used++;
-        bsrc.push_back(c);
+        fb.bsrc.push_back(c);
       }
-      lent[k] = ((uint32_t)local[c] << 16) | (uint32_t)h.z_ent[2 * (size_t)k + 1];
+      fb.lent[k] = ((uint32_t)local[c] << 16) | (uint32_t)ent[2 * (size_t)k + 1];
     }
-    umax = std::max(umax, used);
+    fb.umax = std::max(fb.umax, used);
     ++in_blk;
   }
-  brow.push_back(rows);
-  bptr.push_back((int32_t)bsrc.size());
-  int e = upload(G, brow, &g.brow);
-  if (!e) e = upload(G, bptr, &g.bptr);
-  if (!e) e = upload(G, bsrc, &g.bsrc);
-  if (!e) e = upload(G, lent, &g.lent);
+  fb.brow.push_back(rows);
+  fb.bptr.push_back((int32_t)fb.bsrc.size());
+  out = std::move(fb);
+  return true;
+}
+}  // namespace hope
+
+// The grid's own fill blocks: as many rows as one workgroup's lane groups take
+// (256 / halo_lanes), at most 1024 cells (2048 from order 7) per block; without
+// them (a row too long) the fill reads the state directly.
+static int upload_fill_blocks(hope_grid* G) {
+  const hope::HostTables& h = G->h;
+  hope::FillBlocks fb;
+  if (h.z_ptr.empty() ||
+      !hope::build_fill_blocks((int)h.z_dst.size(), h.z_ptr.data(), h.z_ent.data(), (size_t)6 * h.P * h.P,
+                               256 / hope::halo_lanes(h.k), h.k >= 7 ? 2048 : 1024, fb))
+    return 0;
+  hope::GhostDev& g = G->g;
+  int e = upload(G, fb.brow, &g.brow);
+  if (!e) e = upload(G, fb.bptr, &g.bptr);
+  if (!e) e = upload(G, fb.bsrc, &g.bsrc);
+  if (!e) e = upload(G, fb.lent, &g.lent);
   if (e) return e;
-  g.blocks = blk + 1;
-  g.umax = umax;
+  g.blocks = (int)fb.brow.size() - 1;
+  g.umax = fb.umax;
   return 0;
 }
 
@@ -332,7 +341,7 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
   g.nnz = (int64_t)(h.z_ent.size() / 2);
   g.cnnz = (int64_t)(h.z_cval.size() / 6);
   g.rows = (int)h.z_dst.size();
-  if (int eb = build_fill_blocks(G)) { free_grid(G); return eb; }
+  if (int eb = upload_fill_blocks(G)) { free_grid(G); return eb; }
   {
     // transpose of G, rows by interior cell (CSR over the cells it reads)
     const int n = h.n, P = h.P, r = h.r;

@@ -40,6 +40,20 @@ struct hope_grid {
 };
 
 namespace hope {
+// Row blocks of an LDS-staged ghost fill (GhostDev.brow ...): consecutive
+// device rows of a ghost map (CSR ptr over rows, ent = (col, ce) pairs, cols
+// below cells), at most rb per block, closed early when the distinct interior
+// cells they read would pass cap; lent packs each entry's ce with the position
+// of its cell in its block's list.  Returns false (and leaves the vectors
+// empty) when a row alone reads more than cap cells or an entry does not fit
+// the packing.
+struct FillBlocks {
+  std::vector<int32_t> brow, bptr, bsrc;
+  std::vector<uint32_t> lent;
+  int umax = 0;
+};
+bool build_fill_blocks(int rows, const int32_t* ptr, const int32_t* ent, size_t cells, int rb, int cap,
+                       FillBlocks& out);
 // set the thread's error message and return the code
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);

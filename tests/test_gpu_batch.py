@@ -41,6 +41,7 @@ def test_batch_tendency_equals_each_member_grid_bitwise():
     ns = [10, 13, 10, 16, 13]
     print("case batch tendency", ns, flush=True)
     ens, q_all, tilts, states, _ = _setup(ns, seed=100)
+    assert ens.info.fill_blocks > 0          # WENO5 rows take the LDS-staged batched fill
     out = ens.tendency(q_all)
     for i, n in enumerate(ns):
         g = _grid(n, 5, "weno", tilts[i])
