@@ -135,6 +135,8 @@ typedef struct hope_layout {
                                         segments of one row or one segment per panel;
                                         otherwise 8 * 6 * n * (segments - 1) *
                                         (6 n_gauss + 11) bytes rounded up to 256) */
+  int64_t fill_blocks;      /* row blocks of the LDS-staged ghost fill (0: the fill reads
+                               the state directly) */
 } hope_layout;
 
 /* Build a grid: equiangular metrics, reconstruction and WENO tables, the

@@ -71,6 +71,7 @@ class Layout(ctypes.Structure):
         ("ghost_sweeps", ctypes.c_int32),
         ("tables_cached", ctypes.c_int32),
         ("tendency_workspace_bytes", ctypes.c_int64),
+        ("fill_blocks", ctypes.c_int64),
     ]
 
 

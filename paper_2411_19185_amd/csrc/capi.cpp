@@ -518,6 +518,7 @@ int hope_grid_layout(const hope_grid* G, hope_layout* out) {
   out->device_bytes = (int64_t)G->device_bytes;
   out->ghost_sweeps = h.ghost_sweeps;
   out->tables_cached = G->tables_cached ? 1 : 0;
+  out->fill_blocks = G->g.blocks;
   return HOPE_OK;
 }
 

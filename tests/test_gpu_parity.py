@@ -60,13 +60,14 @@ def test_tendency_matches_oracle(n, order, scheme, state, seed):
 
 
 @pytest.mark.parametrize("n,order,scheme,state,seed", [(30, 3, "tpp", "member", 11), (16, 5, "weno", "member", 12),
-                                                       (12, 11, "tpp", "member", 13)])
+                                                       (12, 11, "tpp", "member", 13), (13, 13, "tpp", "member", 17)])
 def test_halo_matches_oracle_fixed_point(n, order, scheme, state, seed):
     print(f"case n={n} order={order} {scheme}", flush=True)
     alpha, q = STATES[state](n, seed)
     og = oracle_grid(n, order, scheme, alpha)
     ref = og.ghost.fill(q)
     g = _gpu_grid(n, order, scheme, alpha)
+    assert g.layout.fill_blocks > 0          # the fill runs by row blocks staged in LDS
     qp = to_padded(q, g.r)
     g.fill_halo(qp)
     torch.cuda.synchronize()
