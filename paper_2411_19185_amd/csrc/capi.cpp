@@ -391,6 +391,38 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
     if (!e2) e2 = upload(G, refs, &G->gt_ref);
     if (e2) { free_grid(G); return e2; }
     G->gt_nnz = (int64_t)nnz;
+    // blocks of kGtCells rows of G^T with the distinct ghost cells they read
+    // (kept only if every block fits kGtCap)
+    {
+      const int nrow = (int)ccell.size(), nblk = (nrow + kGtCells - 1) / kGtCells;
+      std::vector<int32_t> bptr(1, 0), bsrc, mark(6 * (size_t)P * P, -1), local(6 * (size_t)P * P, 0);
+      std::vector<uint16_t> lidx(nnz);
+      bool ok = nrow > 0;
+      int umax = 0;
+      for (int b = 0; b < nblk && ok; ++b) {
+        int used = 0;
+        for (int32_t k = cptr[b * kGtCells]; k < cptr[std::min(nrow, (b + 1) * kGtCells)]; ++k) {
+          const int32_t d = rows[k];
+          if (mark[d] != b) {
+            mark[d] = b;
+            local[d] = used++;
+            bsrc.push_back(d);
+          }
+          lidx[k] = (uint16_t)local[d];
+        }
+        if (used > kGtCap) ok = false;
+        umax = std::max(umax, used);
+        bptr.push_back((int32_t)bsrc.size());
+      }
+      if (ok) {
+        int e3 = upload(G, bptr, &G->gt_bptr);
+        if (!e3) e3 = upload(G, bsrc, &G->gt_bsrc);
+        if (!e3) e3 = upload(G, lidx, &G->gt_lidx);
+        if (e3) { free_grid(G); return e3; }
+        G->gt_blocks = nblk;
+        G->gt_umax = umax;
+      }
+    }
   }
   if (desc->surface_geopotential) {
     TopoHost th;
@@ -453,6 +485,11 @@ int hope_grid_derive(const hope_grid* base, double axis_tilt, hope_grid** out) {
   G->gt_ptr = base->gt_ptr;
   G->gt_row = base->gt_row;
   G->gt_ref = base->gt_ref;
+  G->gt_blocks = base->gt_blocks;
+  G->gt_umax = base->gt_umax;
+  G->gt_bptr = base->gt_bptr;
+  G->gt_bsrc = base->gt_bsrc;
+  G->gt_lidx = base->gt_lidx;
   G->gt_nnz = base->gt_nnz;
   G->strip_w = base->strip_w;
   G->seg_h = base->seg_h;
@@ -621,6 +658,11 @@ int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq
   a.gt_ptr = G->gt_ptr;
   a.gt_row = G->gt_row;
   a.gt_ref = G->gt_ref;
+  a.gt_blocks = G->gt_blocks;
+  a.gt_umax = G->gt_umax;
+  a.gt_bptr = G->gt_bptr;
+  a.gt_bsrc = G->gt_bsrc;
+  a.gt_lidx = G->gt_lidx;
   a.gcval = G->g.cval;
   a.gt_nnz = G->gt_nnz;
   a.topo = G->topo;

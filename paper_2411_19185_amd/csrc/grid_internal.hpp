@@ -30,6 +30,14 @@ struct hope_grid {
   const int32_t* gt_row = nullptr;
   const int32_t* gt_ref = nullptr;   // canonical value record and frame codes of each entry
   int64_t gt_nnz = 0;
+  // blocks of kGtCells consecutive G^T rows for the LDS-staged transpose
+  // (gt_blocks = 0: none): the distinct ghost cells block b reads are
+  // gt_bsrc[gt_bptr[b] .. gt_bptr[b+1]), entry k's position in that list
+  // gt_lidx[k], gt_umax the longest list
+  int32_t gt_blocks = 0, gt_umax = 0;
+  const int32_t* gt_bptr = nullptr;
+  const int32_t* gt_bsrc = nullptr;
+  const uint16_t* gt_lidx = nullptr;
   // optional per-kernel timing with HIP events on the launch stream
   bool timing = false;
   uint32_t timing_mask = 0;   // bit k: kernel index k is timed

@@ -21,7 +21,8 @@
 //                   stencil cotangents fit in the space of the point values,
 //                   no longer read; on small ones once for all three)
 //   k_vjp_interior  the interior cotangent
-//   k_vjp_ghost_t   plus G^T times the ghost cotangents
+//   k_vjp_ghost_t   plus G^T times the ghost cotangents (k_vjp_ghost_t_lds: by
+//                   blocks of cells, the ghost cotangents they read staged in LDS)
 // Every kernel gathers (each output is written by one thread): no atomics.
 // Scratch arrays are structs of arrays over cells, so that neighbouring lanes
 // (neighbouring cells) read and write neighbouring addresses.
@@ -936,6 +937,63 @@ __global__ __launch_bounds__(256) void k_vjp_ghost_t(int rows, int n, int P, con
   }
 }
 
+// the same by blocks of kGtCells rows (workgroup b: rows b kGtCells ..): the
+// ghost cotangents the block reads are first copied to LDS (3 x umax), then
+// each row's 16 lanes sum their entries from there, in the order above
+__global__ __launch_bounds__(256) void k_vjp_ghost_t_lds(int rows, int n, int P, int umax,
+                                                         const int32_t* __restrict__ gt_cell,
+                                                         const int32_t* __restrict__ gt_ptr,
+                                                         const int32_t* __restrict__ gt_bptr,
+                                                         const int32_t* __restrict__ gt_bsrc,
+                                                         const uint16_t* __restrict__ gt_lidx,
+                                                         const int32_t* __restrict__ gt_ref,
+                                                         const GhostVal* __restrict__ gcval,
+                                                         const double* __restrict__ gpad, double* __restrict__ gq) {
+  extern __shared__ double sg[];
+  const int b = blockIdx.x;
+  const size_t plane = (size_t)6 * P * P;
+  const int s0 = gt_bptr[b], U = gt_bptr[b + 1] - s0;
+  for (int u = threadIdx.x; u < U; u += blockDim.x) {
+    const int d = gt_bsrc[s0 + u];
+    sg[u] = gpad[d];
+    sg[umax + u] = gpad[plane + d];
+    sg[2 * umax + u] = gpad[2 * plane + d];
+  }
+  __syncthreads();
+  const int row = b * kGtCells + (int)threadIdx.x / 16;
+  if (row >= rows) return;   // the whole 16-lane group leaves together
+  const int lane = threadIdx.x & 15;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int k = gt_ptr[row] + lane; k < gt_ptr[row + 1]; k += 16) {
+    const int l = gt_lidx[k];
+    const double a0 = sg[l], a1 = sg[umax + l], a2 = sg[2 * umax + l];
+    const int ref = gt_ref[k];
+    const GhostVal cj = gcval[ref & 0xffffff];
+    const int f = (ref >> 24) & 7, f0 = (ref >> 27) & 7;
+    double m11, m12, m21, m22, b11, b12, b21, b22;
+    frame_apply_t(f, cj.v[1], cj.v[2], m11, m12);
+    frame_apply_t(f, cj.v[3], cj.v[4], m21, m22);
+    frame_apply_t(f0, m11, m21, b11, b21);
+    frame_apply_t(f0, m12, m22, b12, b22);
+    g0 = fma(cj.v[0], a0, g0);
+    g1 = fma(b11, a1, fma(b21, a2, g1));
+    g2 = fma(b12, a1, fma(b22, a2, g2));
+  }
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) {
+    g0 += __shfl_xor(g0, off, 16);
+    g1 += __shfl_xor(g1, off, 16);
+    g2 += __shfl_xor(g2, off, 16);
+  }
+  if (lane == 0) {
+    const int c = gt_cell[row];
+    const size_t nn = (size_t)6 * n * n;
+    gq[c] += g0;
+    gq[nn + c] += g1;
+    gq[2 * nn + c] += g2;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Launcher of the whole adjoint
 // ---------------------------------------------------------------------------
@@ -976,7 +1034,11 @@ static int vjp_t(const VjpArgs& a, int step, void* stream) {
     }
     case kVjpGhostT:
       hipLaunchKernelGGL(k_vjp_interior, dim3((cells + 255) / 256), dim3(256), 0, s, n, P, gs.r, a.gpad, a.gq);
-      if (a.gt_rows > 0)
+      if (a.gt_blocks > 0)
+        hipLaunchKernelGGL(k_vjp_ghost_t_lds, dim3((unsigned)a.gt_blocks), dim3(256),
+                           (size_t)3 * a.gt_umax * sizeof(double), s, a.gt_rows, n, P, a.gt_umax, a.gt_cell, a.gt_ptr,
+                           a.gt_bptr, a.gt_bsrc, a.gt_lidx, a.gt_ref, a.gcval, a.gpad, a.gq);
+      else if (a.gt_rows > 0)
         hipLaunchKernelGGL(k_vjp_ghost_t, dim3((unsigned)(((size_t)a.gt_rows * 16 + 255) / 256)), dim3(256), 0, s,
                            a.gt_rows, n, P, a.gt_cell, a.gt_ptr, a.gt_row, a.gt_ref, a.gcval, a.gpad, a.gq);
       break;

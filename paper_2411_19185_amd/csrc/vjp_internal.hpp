@@ -6,6 +6,12 @@
 namespace hope {
 
 // Arguments of the adjoint (vjp.hip)
+// G^T rows (interior cells) per block of the LDS-staged transpose: one
+// workgroup of 256 lanes, 16 per cell; at most kGtCap distinct ghost cells
+// per block (48 KB of LDS)
+constexpr int kGtCells = 16;
+constexpr int kGtCap = 2048;
+
 struct VjpArgs {
   const double* tab;
   const int32_t* itab;
@@ -27,6 +33,11 @@ struct VjpArgs {
                            // | (frame code of the ghost << 27), see GhostDev
   const GhostVal* gcval;   // canonical value records of the ghost map
   int64_t gt_nnz;
+  // the LDS-staged transpose (gt_blocks = 0: the direct one), see hope_grid
+  int32_t gt_blocks = 0, gt_umax = 0;
+  const int32_t* gt_bptr = nullptr;
+  const int32_t* gt_bsrc = nullptr;
+  const uint16_t* gt_lidx = nullptr;
   TopoDev topo;            // bottom topography (null sbar: none)
   double* Lder;            // topography: cotangents of d(sqrtG phi_t)/dxi, /deta at the cell nodes,
                            // [2][m*m][6n^2]
