@@ -849,16 +849,26 @@ __global__ __launch_bounds__(256) void k_vjp_gather(const double* __restrict__ t
   const size_t pi = idx % plane;
   const int ii = pi % P, jj = (pi / P) % P, p = (int)(pi / ((size_t)P * P));
   const size_t cells = (size_t)6 * n * n;
+  // a stencil row's K values are requested together (the cells outside the
+  // panel masked), then added in the order of the row: the same sum as
+  // adding the in-panel values one by one
   double acc = 0.0;
+#pragma unroll(K <= 5 ? K : 1)
   for (int dy = -R; dy <= R; ++dy) {
     const int j = jj - R - dy;
-    if (j < 0 || j >= n) continue;
-    for (int dx = -R; dx <= R; ++dx) {
-      const int i = ii - R - dx;
-      if (i < 0 || i >= n) continue;
-      const int c = (p * n + j) * n + i;
-      const int o = (dy + R) * K + (dx + R);
-      acc += Dl[((size_t)o * nv + (v - v0)) * cells + c];
+    const bool jin = j >= 0 && j < n;
+    double val[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const int i = ii - t;   // dx = t - R
+      const bool in = jin && i >= 0 && i < n;
+      const size_t o = (size_t)(dy + R) * K + t;
+      val[t] = in ? Dl[(o * nv + (v - v0)) * cells + (size_t)(p * n + j) * n + i] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const int i = ii - t;
+      if (jin && i >= 0 && i < n) acc += val[t];
     }
   }
   gpad[(size_t)v * plane + pi] = acc;
