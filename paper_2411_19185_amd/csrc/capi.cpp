@@ -418,6 +418,21 @@ int hope_grid_create(const hope_grid_desc* desc, hope_grid** out) {
         int e3 = upload(G, bptr, &G->gt_bptr);
         if (!e3) e3 = upload(G, bsrc, &G->gt_bsrc);
         if (!e3) e3 = upload(G, lidx, &G->gt_lidx);
+        // the blocks in order of the mean canonical record they read: the
+        // records are shared by the 24 rotated images of a ghost row, so
+        // blocks far apart on the cube read the same ones, and a contiguous
+        // range of this list (one L2 domain's) reads a narrow band of them
+        std::vector<double> key(nblk);
+        for (int b = 0; b < nblk; ++b) {
+          const int32_t lo = cptr[b * kGtCells], hi = cptr[std::min(nrow, (b + 1) * kGtCells)];
+          double sum = 0;
+          for (int32_t k = lo; k < hi; ++k) sum += (double)(refs[k] & 0xffffff);
+          key[b] = sum / std::max(1, hi - lo);
+        }
+        std::vector<int32_t> order(nblk);
+        for (int b = 0; b < nblk; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+        if (!e3) e3 = upload(G, order, &G->gt_border);
         if (e3) { free_grid(G); return e3; }
         G->gt_blocks = nblk;
         G->gt_umax = umax;
@@ -490,6 +505,7 @@ int hope_grid_derive(const hope_grid* base, double axis_tilt, hope_grid** out) {
   G->gt_bptr = base->gt_bptr;
   G->gt_bsrc = base->gt_bsrc;
   G->gt_lidx = base->gt_lidx;
+  G->gt_border = base->gt_border;
   G->gt_nnz = base->gt_nnz;
   G->strip_w = base->strip_w;
   G->seg_h = base->seg_h;
@@ -663,6 +679,7 @@ int hope_tendency_vjp(const hope_grid* G, double* q, const double* w, double* gq
   a.gt_bptr = G->gt_bptr;
   a.gt_bsrc = G->gt_bsrc;
   a.gt_lidx = G->gt_lidx;
+  a.gt_border = G->gt_border;
   a.gcval = G->g.cval;
   a.gt_nnz = G->gt_nnz;
   a.topo = G->topo;

@@ -11,6 +11,12 @@ namespace hope {
 typedef const __attribute__((address_space(4))) double* cdp;
 typedef const __attribute__((address_space(4))) int32_t* cip;
 
+// The chip dispatches workgroup b to L2 domain (XCD) b % 8.  xcd_block(b, nb)
+// (nb a multiple of 8) gives each domain a contiguous range of logical
+// blocks; it is a bijection of [0, nb).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) { return (b % kXcds) * (nb / kXcds) + b / kXcds; }
+
 // ---------------------------------------------------------------------------
 // Arithmetic helpers
 // ---------------------------------------------------------------------------

@@ -33,11 +33,14 @@ struct hope_grid {
   // blocks of kGtCells consecutive G^T rows for the LDS-staged transpose
   // (gt_blocks = 0: none): the distinct ghost cells block b reads are
   // gt_bsrc[gt_bptr[b] .. gt_bptr[b+1]), entry k's position in that list
-  // gt_lidx[k], gt_umax the longest list
+  // gt_lidx[k], gt_umax the longest list; gt_border lists the blocks by the
+  // mean index of the canonical value records they read (each L2 domain
+  // takes a contiguous range of that list)
   int32_t gt_blocks = 0, gt_umax = 0;
   const int32_t* gt_bptr = nullptr;
   const int32_t* gt_bsrc = nullptr;
   const uint16_t* gt_lidx = nullptr;
+  const int32_t* gt_border = nullptr;
   // optional per-kernel timing with HIP events on the launch stream
   bool timing = false;
   uint32_t timing_mask = 0;   // bit k: kernel index k is timed

@@ -43,12 +43,6 @@ __device__ __forceinline__ void frame_apply(int f, double c1, double c2, double&
   g2 = sy * (sw ? c1 : c2);
 }
 
-// The chip dispatches workgroup b to L2 domain (XCD) b % 8.  xcd_block(b, nb)
-// (nb a multiple of 8) gives each domain a contiguous range of logical
-// blocks; it is a bijection of [0, nb).
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_block(int b, int nb) { return (b % kXcds) * (nb / kXcds) + b / kXcds; }
-
 // one ghost row of g = G q, reduced over LANES lanes (lane = 0.. of the
 // group): entries in column order, values from the row's canonical row;
 // src(k, ce, a0, a1, a2) gives entry k's ce (canonical value and frame code)

@@ -22,7 +22,8 @@
 //                   no longer read; on small ones once for all three)
 //   k_vjp_interior  the interior cotangent
 //   k_vjp_ghost_t   plus G^T times the ghost cotangents (k_vjp_ghost_t_lds: by
-//                   blocks of cells, the ghost cotangents they read staged in LDS)
+//                   blocks of cells, the ghost cotangents they read staged in LDS,
+//                   the blocks ordered by the canonical value records they read)
 // Every kernel gathers (each output is written by one thread): no atomics.
 // Scratch arrays are structs of arrays over cells, so that neighbouring lanes
 // (neighbouring cells) read and write neighbouring addresses.
@@ -947,10 +948,14 @@ __global__ __launch_bounds__(256) void k_vjp_ghost_t(int rows, int n, int P, con
   }
 }
 
-// the same by blocks of kGtCells rows (workgroup b: rows b kGtCells ..): the
+// the same by blocks of kGtCells rows (block b: rows b kGtCells ..): the
 // ghost cotangents the block reads are first copied to LDS (3 x umax), then
-// each row's 16 lanes sum their entries from there, in the order above
-__global__ __launch_bounds__(256) void k_vjp_ghost_t_lds(int rows, int n, int P, int umax,
+// each row's 16 lanes sum their entries from there, in the order above.  The
+// blocks run in the order of the list border (by the canonical value records
+// they read), each L2 domain a contiguous range of it, so that one domain
+// reads a narrow band of the records instead of all of them
+__global__ __launch_bounds__(256) void k_vjp_ghost_t_lds(int blocks, const int32_t* __restrict__ border,
+                                                         int rows, int n, int P, int umax,
                                                          const int32_t* __restrict__ gt_cell,
                                                          const int32_t* __restrict__ gt_ptr,
                                                          const int32_t* __restrict__ gt_bptr,
@@ -960,7 +965,10 @@ __global__ __launch_bounds__(256) void k_vjp_ghost_t_lds(int rows, int n, int P,
                                                          const GhostVal* __restrict__ gcval,
                                                          const double* __restrict__ gpad, double* __restrict__ gq) {
   extern __shared__ double sg[];
-  const int b = blockIdx.x;
+  // each L2 domain takes a contiguous range of the block list
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  if (lb >= blocks) return;   // the whole workgroup leaves together
+  const int b = border[lb];
   const size_t plane = (size_t)6 * P * P;
   const int s0 = gt_bptr[b], U = gt_bptr[b + 1] - s0;
   for (int u = threadIdx.x; u < U; u += blockDim.x) {
@@ -1045,9 +1053,10 @@ static int vjp_t(const VjpArgs& a, int step, void* stream) {
     case kVjpGhostT:
       hipLaunchKernelGGL(k_vjp_interior, dim3((cells + 255) / 256), dim3(256), 0, s, n, P, gs.r, a.gpad, a.gq);
       if (a.gt_blocks > 0)
-        hipLaunchKernelGGL(k_vjp_ghost_t_lds, dim3((unsigned)a.gt_blocks), dim3(256),
-                           (size_t)3 * a.gt_umax * sizeof(double), s, a.gt_rows, n, P, a.gt_umax, a.gt_cell, a.gt_ptr,
-                           a.gt_bptr, a.gt_bsrc, a.gt_lidx, a.gt_ref, a.gcval, a.gpad, a.gq);
+        hipLaunchKernelGGL(k_vjp_ghost_t_lds, dim3((unsigned)((a.gt_blocks + kXcds - 1) / kXcds * kXcds)),
+                           dim3(256), (size_t)3 * a.gt_umax * sizeof(double), s, a.gt_blocks, a.gt_border,
+                           a.gt_rows, n, P, a.gt_umax, a.gt_cell, a.gt_ptr, a.gt_bptr, a.gt_bsrc, a.gt_lidx,
+                           a.gt_ref, a.gcval, a.gpad, a.gq);
       else if (a.gt_rows > 0)
         hipLaunchKernelGGL(k_vjp_ghost_t, dim3((unsigned)(((size_t)a.gt_rows * 16 + 255) / 256)), dim3(256), 0, s,
                            a.gt_rows, n, P, a.gt_cell, a.gt_ptr, a.gt_row, a.gt_ref, a.gcval, a.gpad, a.gq);

@@ -38,6 +38,7 @@ struct VjpArgs {
   const int32_t* gt_bptr = nullptr;
   const int32_t* gt_bsrc = nullptr;
   const uint16_t* gt_lidx = nullptr;
+  const int32_t* gt_border = nullptr;
   TopoDev topo;            // bottom topography (null sbar: none)
   double* Lder;            // topography: cotangents of d(sqrtG phi_t)/dxi, /deta at the cell nodes,
                            // [2][m*m][6n^2]
