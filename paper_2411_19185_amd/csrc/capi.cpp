@@ -168,14 +168,15 @@ bool build_fill_blocks(int rows, const int32_t* ptr, const int32_t* ent, size_t 
 }  // namespace hope
 
 // The grid's own fill blocks: as many rows as one workgroup's lane groups take
-// (256 / halo_lanes), at most 1024 cells (2048 from order 7) per block; without
+// (fill_lds_threads / halo_lanes), at most 1024 cells (2048 from order 7) per block; without
 // them (a row too long) the fill reads the state directly.
 static int upload_fill_blocks(hope_grid* G) {
   const hope::HostTables& h = G->h;
   hope::FillBlocks fb;
   if (h.z_ptr.empty() ||
       !hope::build_fill_blocks((int)h.z_dst.size(), h.z_ptr.data(), h.z_ent.data(), (size_t)6 * h.P * h.P,
-                               256 / hope::halo_lanes(h.k), h.k >= 7 ? 2048 : 1024, fb))
+                               hope::fill_lds_threads(hope::halo_lanes(h.k)) / hope::halo_lanes(h.k),
+                               h.k >= 7 ? 2048 : 1024, fb))
     return 0;
   hope::GhostDev& g = G->g;
   int e = upload(G, fb.brow, &g.brow);

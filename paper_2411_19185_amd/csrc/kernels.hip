@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_fill_halo(GhostDev g, double* __restric
 // the block reads are first copied to LDS (3 x umax doubles), then each row's
 // lane group sums its entries from there, in the order of k_fill_halo
 template <int LANES>
-__global__ __launch_bounds__(256) void k_fill_halo_lds(GhostDev g, double* __restrict__ q, int plane) {
+__global__ __launch_bounds__(fill_lds_threads(LANES)) void k_fill_halo_lds(GhostDev g, double* __restrict__ q, int plane) {
   extern __shared__ double sq[];
   const int b = xcd_block(blockIdx.x, gridDim.x);
   if (b >= g.blocks) return;   // the whole workgroup leaves together
@@ -162,10 +162,11 @@ int launch_fill_halo(const GhostDev& g, double* q, int plane, int lanes, void* s
   if (g.blocks > 0) {
     const int blocks = (g.blocks + kXcds - 1) / kXcds * kXcds;
     const size_t lds = (size_t)3 * g.umax * sizeof(double);
+    const dim3 t(fill_lds_threads(lanes));
     if (lanes == 64)
-      hipLaunchKernelGGL(k_fill_halo_lds<64>, dim3(blocks), dim3(threads), lds, (hipStream_t)stream, g, q, plane);
+      hipLaunchKernelGGL(k_fill_halo_lds<64>, dim3(blocks), t, lds, (hipStream_t)stream, g, q, plane);
     else
-      hipLaunchKernelGGL(k_fill_halo_lds<32>, dim3(blocks), dim3(threads), lds, (hipStream_t)stream, g, q, plane);
+      hipLaunchKernelGGL(k_fill_halo_lds<32>, dim3(blocks), t, lds, (hipStream_t)stream, g, q, plane);
     return (int)hipGetLastError();
   }
   int blocks = (int)(((size_t)g.rows * lanes + threads - 1) / threads);
