@@ -99,14 +99,41 @@ STAGE_SOURCES = ("paper_2411_19185_amd/csrc/kernels.hip", "paper_2411_19185_amd/
 TRAFFIC_FILE = "profiles/k_stage_weno5_c360_traffic.txt"
 
 
+def _cxx_code(src: str) -> str:
+    """C++ source text with its comments removed and every run of whitespace
+    made one space (string and character literals kept as they are)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def stage_source_hash() -> str:
-    """sha256 over the sources the stage kernel is compiled from and the
-    build flags."""
+    """sha256 over the code of the sources the stage kernel is compiled from
+    (comments and layout aside, so that editing a comment keeps the counters
+    taken for that code) and the build script with its flags."""
     import hashlib
     h = hashlib.sha256()
     for f in STAGE_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            text = fh.read()
+        h.update((text if f.endswith(".py") else _cxx_code(text)).encode())
     return h.hexdigest()[:16]
 
 

@@ -150,12 +150,12 @@ HOPE_HD constexpr bool weno_mixed_axis(int k, int m, int a) { return k == 5 && m
 HOPE_HD constexpr int halo_lanes(int k) { return k >= 7 ? 64 : 32; }
 
 // workgroup size of the single grid's LDS-staged fill with `lanes` lanes per
-// ghost row (lanes / halo_lanes rows per block).  A block's staged cells grow
-// far slower than its rows (neighbouring rows read mostly the same cells), so
-// from order 7, where rows hold several hundred entries, blocks of 16 rows keep
-// more wavefronts per CU for the same LDS; below, 8 rows per block, since
-// larger blocks leave CUs idle on small grids.  Each row's sums are the same
-// whatever the block size.
+// ghost row (fill_lds_threads(lanes) / lanes rows per block).  A block's
+// staged cells grow far slower than its rows (neighbouring rows read mostly
+// the same cells), so from order 7, where rows hold several hundred entries,
+// blocks of 16 rows keep more wavefronts per CU for the same LDS; below, 8
+// rows per block, since larger blocks leave CUs idle on small grids.  Each
+// row's sums are the same whatever the block size.
 HOPE_HD constexpr int fill_lds_threads(int lanes) { return lanes == 64 ? 1024 : 256; }
 
 // Scalars every kernel needs.
