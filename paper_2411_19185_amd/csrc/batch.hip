@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_fill_halo_batch(const BatchGrid* __rest
 // stages their cells in LDS, then each row's lane group sums its entries from
 // there, in the order of k_fill_halo_batch
 template <int LANES>
-__global__ __launch_bounds__(256) void k_fill_halo_batch_lds(const BatchGrid* __restrict__ grids, int n_grids,
+__global__ __launch_bounds__(kHaloLdsThreads) void k_fill_halo_batch_lds(const BatchGrid* __restrict__ grids, int n_grids,
                                                              int total_blocks, int ucap,
                                                              const int32_t* __restrict__ mlist,
                                                              const BatchMember* __restrict__ mem,
@@ -262,11 +262,11 @@ int launch_batch_fill_halo(const BatchGrid* grids, int n_grids, int total_rows, 
     const int blocks = (total_blocks + kXcds - 1) / kXcds * kXcds;
     const size_t lds = (size_t)kHaloLdsChunk * 3 * ucap * sizeof(double);
     if (lanes == 64)
-      hipLaunchKernelGGL(k_fill_halo_batch_lds<64>, dim3(blocks), dim3(threads), lds, (hipStream_t)stream, grids,
-                         n_grids, total_blocks, ucap, members_by_grid, members, base);
+      hipLaunchKernelGGL(k_fill_halo_batch_lds<64>, dim3(blocks), dim3(kHaloLdsThreads), lds, (hipStream_t)stream,
+                         grids, n_grids, total_blocks, ucap, members_by_grid, members, base);
     else
-      hipLaunchKernelGGL(k_fill_halo_batch_lds<32>, dim3(blocks), dim3(threads), lds, (hipStream_t)stream, grids,
-                         n_grids, total_blocks, ucap, members_by_grid, members, base);
+      hipLaunchKernelGGL(k_fill_halo_batch_lds<32>, dim3(blocks), dim3(kHaloLdsThreads), lds, (hipStream_t)stream,
+                         grids, n_grids, total_blocks, ucap, members_by_grid, members, base);
     return (int)hipGetLastError();
   }
   int blocks = (int)(((size_t)total_rows * lanes + threads - 1) / threads);

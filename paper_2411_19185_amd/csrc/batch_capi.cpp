@@ -278,8 +278,8 @@ int hope_batch_create(const hope_grid* const* grids, int32_t n_members, const do
         st = hip_fail(e, "hipMemcpy (batch ghost map)");
         break;
       }
-      lds = build_fill_blocks(grows, ptr.data(), ent.data(), (size_t)6 * G->h.P * G->h.P, 256 / halo_lanes(B->k),
-                              kHaloLdsCells, fbs[gi]);
+      lds = build_fill_blocks(grows, ptr.data(), ent.data(), (size_t)6 * G->h.P * G->h.P,
+                              kHaloLdsThreads / halo_lanes(B->k), kHaloLdsCells, fbs[gi]);
     }
     if (st) lds = false;
     if (lds) {

@@ -88,5 +88,10 @@ constexpr int kHaloChunk = HOPE_HALO_CHUNK;
 // order 7, take the direct batched fill)
 constexpr int kHaloLdsChunk = 4;
 constexpr int kHaloLdsCells = 512;
+// its workgroup size: kHaloLdsThreads / lanes rows per block (16 at 32 lanes).
+// Neighbouring rows read mostly the same cells (at WENO5, blocks of 8 rows
+// stage about 350 cells, blocks of 16 about 420), so twice the rows fit the
+// same LDS and the CU holds twice the wavefronts
+constexpr int kHaloLdsThreads = 512;
 
 }  // namespace hope
